@@ -1,0 +1,170 @@
+"""Independent checks of the FP64 oracle (helpers shared by the pin tests and
+the planted-mistake tests).  Nothing here calls the HIP library.
+
+Each helper recomputes a fact the paper or plain mathematics fixes by a route
+different from the oracle's own code:
+  * rigid motions through 4x4 homogeneous matrices and np.linalg.inv;
+  * Jacobians by central finite differences of the frozen residual;
+  * point-to-point ICP normal equations for isotropic covariances, written
+    with cross-product identities instead of stacked Jacobians.
+"""
+
+import numpy as np
+
+import oracle
+
+
+def hom(pose12):
+    p = np.asarray(pose12, dtype=np.float64)
+    T = np.eye(4)
+    T[:3, :3] = p[:9].reshape(3, 3)
+    T[:3, 3] = p[9:]
+    return T
+
+
+def rows(T):
+    return np.concatenate([T[:3, :3].reshape(9), T[:3, 3]])
+
+
+def so3_exp(w):
+    th = np.linalg.norm(w)
+    K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-12:
+        return np.eye(3) + K
+    return np.eye(3) + np.sin(th) / th * K + (1 - np.cos(th)) / th**2 * (K @ K)
+
+
+def se3_exp_right(xi):
+    """Retraction T <- T Exp(xi), xi = (omega, rho); first-order exact."""
+    T = np.eye(4)
+    T[:3, :3] = so3_exp(xi[:3])
+    T[:3, 3] = xi[3:]
+    return T
+
+
+def unpack6(c):
+    c = np.asarray(c, dtype=np.float64)
+    return np.array([[c[0], c[1], c[2]], [c[1], c[3], c[4]], [c[2], c[4], c[5]]])
+
+
+def frozen_residuals(xi12, Ti, Tj, mu, m):
+    """r_k(xi) = m_k - (T_j Exp xi_j)^-1 (T_i Exp xi_i) mu_k, (n, 3)."""
+    Ti_p = Ti @ se3_exp_right(xi12[:6])
+    Tj_p = Tj @ se3_exp_right(xi12[6:])
+    Tji = np.linalg.inv(Tj_p) @ Ti_p
+    q = mu @ Tji[:3, :3].T + Tji[:3, 3]
+    return m - q
+
+
+def fd_hessian_factor(src_xyz, src_cov, vmap, pose_i, pose_j, h=1e-6):
+    """H, b, e and per-point Jacobians from central differences of the
+    frozen residual, with Omega built from 4x4 algebra."""
+    out = oracle.linearize_factor(src_xyz, src_cov, vmap, pose_i, pose_j)
+    corr = out["corr"]
+    hit = corr >= 0
+    Ti, Tj = hom(pose_i), hom(pose_j)
+    Tji = np.linalg.inv(Tj) @ Ti
+    R = Tji[:3, :3]
+    mu = np.asarray(src_xyz, np.float64)[hit]
+    m = vmap.mean[corr[hit]].astype(np.float64)
+    n = mu.shape[0]
+    J = np.zeros((n, 3, 12))
+    for a in range(12):
+        d = np.zeros(12)
+        d[a] = h
+        J[:, :, a] = (frozen_residuals(d, Ti, Tj, mu, m) - frozen_residuals(-d, Ti, Tj, mu, m)) / (2 * h)
+    r0 = frozen_residuals(np.zeros(12), Ti, Tj, mu, m)
+    Om = np.empty((n, 3, 3))
+    cov = np.asarray(src_cov, np.float64)[hit]
+    vc = vmap.cov[corr[hit]].astype(np.float64)
+    for k in range(n):
+        Om[k] = np.linalg.inv(unpack6(vc[k]) + R @ unpack6(cov[k]) @ R.T)
+    H = np.einsum("nai,nab,nbj->ij", J, Om, J)
+    b = np.einsum("nai,nab,nb->i", J, Om, r0)
+    e = float(np.einsum("na,nab,nb->", r0, Om, r0))
+    return {"H": H, "b": b, "e": e, "J": J, "oracle": out}
+
+
+def fd_cost_gradient(src_xyz, src_cov, vmap, pose_i, pose_j, h=1e-6):
+    """Gradient of the frozen cost sum r^T Omega r by central differences."""
+    out = oracle.linearize_factor(src_xyz, src_cov, vmap, pose_i, pose_j)
+    corr = out["corr"]
+    hit = corr >= 0
+    Ti, Tj = hom(pose_i), hom(pose_j)
+    Tji = np.linalg.inv(Tj) @ Ti
+    R = Tji[:3, :3]
+    mu = np.asarray(src_xyz, np.float64)[hit]
+    m = vmap.mean[corr[hit]].astype(np.float64)
+    cov = np.asarray(src_cov, np.float64)[hit]
+    vc = vmap.cov[corr[hit]].astype(np.float64)
+    Om = np.stack([np.linalg.inv(unpack6(vc[k]) + R @ unpack6(cov[k]) @ R.T) for k in range(mu.shape[0])])
+
+    def cost(xi):
+        r = frozen_residuals(xi, Ti, Tj, mu, m)
+        return float(np.einsum("na,nab,nb->", r, Om, r))
+
+    g = np.zeros(12)
+    for a in range(12):
+        d = np.zeros(12)
+        d[a] = h
+        g[a] = (cost(d) - cost(-d)) / (2 * h)
+    return g, out
+
+
+def icp_normal_equations(src_xyz, vmap, pose_i, pose_j, corr, w):
+    """Point-to-point ICP Gauss-Newton system for isotropic weights w*I,
+    written with cross-product identities ([v]x^T [v]x = |v|^2 I - v v^T)."""
+    Tji = np.linalg.inv(hom(pose_j)) @ hom(pose_i)
+    R, t = Tji[:3, :3], Tji[:3, 3]
+    hit = corr >= 0
+    mu = np.asarray(src_xyz, np.float64)[hit]
+    m = vmap.mean[corr[hit]].astype(np.float64)
+    H = np.zeros((12, 12))
+    b = np.zeros(12)
+    e = 0.0
+    I3 = np.eye(3)
+
+    def sk(v):
+        return np.array([[0, -v[2], v[1]], [v[2], 0, -v[0]], [-v[1], v[0], 0]])
+
+    for k in range(mu.shape[0]):
+        u = mu[k]
+        q = R @ u + t
+        r = m[k] - q
+        rs = R.T @ r
+        Hii = np.block([[(u @ u) * I3 - np.outer(u, u), sk(u)], [-sk(u), I3]])
+        Hjj = np.block([[(q @ q) * I3 - np.outer(q, q), sk(q)], [-sk(q), I3]])
+        Hij = np.block([[sk(u) @ R.T @ sk(q), -sk(u) @ R.T], [R.T @ sk(q), -R.T]])
+        H[:6, :6] += Hii
+        H[6:, 6:] += Hjj
+        H[:6, 6:] += Hij
+        H[6:, :6] += Hij.T
+        b[:3] += np.cross(rs, u)
+        b[3:6] += -rs
+        b[6:9] += np.cross(q, r)
+        b[9:] += r
+        e += r @ r
+    return w * H, w * b, w * e
+
+
+def null_space_basis(pose_i, pose_j):
+    """Columns [Ad(T_i^-1) eta; Ad(T_j^-1) eta] for the six unit eta: a common
+    left motion of both poses leaves T_j^-1 T_i unchanged."""
+    def ad(T):
+        R, t = T[:3, :3], T[:3, 3]
+        S = np.array([[0, -t[2], t[1]], [t[2], 0, -t[0]], [-t[1], t[0], 0]])
+        A = np.zeros((6, 6))
+        A[:3, :3] = R
+        A[3:, :3] = S @ R
+        A[3:, 3:] = R
+        return A
+    Ai = ad(np.linalg.inv(hom(pose_i)))
+    Aj = ad(np.linalg.inv(hom(pose_j)))
+    return np.vstack([Ai, Aj])          # (12, 6)
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))

@@ -1,0 +1,288 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by plain
+mathematics (CPU only).
+
+  * voxel keys: hand-derived table (tests/golden/voxel_keys.txt);
+  * voxel map: brute-force grouping with exact rational arithmetic;
+  * correspondences: linear scan over every voxel box;
+  * relative pose: 4x4 inverse;
+  * H, b: central finite differences of the frozen residual;
+    gradient of the frozen cost = 2 b;
+  * structure: symmetry, positive semidefinite, six-dimensional gauge null
+    space, b orthogonal to it, invariance under a common rigid motion;
+  * isotropic covariances: point-to-point ICP normal equations;
+  * single-point factors derived by hand (tests/golden/single_point_factors.json);
+  * overlap: self overlap is 1, a far cloud 0, hits equal inliers.
+"""
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_single_factor, make_tiny_workload, pose_rows
+from tests.oracle_pins import (fd_cost_gradient, fd_hessian_factor, hom,
+                               icp_normal_equations, null_space_basis,
+                               rel_err, rows)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return make_single_factor()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return make_tiny_workload(seed=7, n_src=400, n_tgt=600, resolution=0.5)
+
+
+# ----------------------------------------------------------------- voxel keys
+
+def test_voxel_keys_golden():
+    rows_ = []
+    with open(os.path.join(GOLDEN, "voxel_keys.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                r, x, k = line.split()
+                rows_.append((float(r), float(x), int(k)))
+    for r, x, k in rows_:
+        s = oracle.voxel_scale(r)
+        got = oracle.voxel_keys(np.array([[x, 0.0, 0.0]], np.float32), s)[0, 0]
+        assert got == k, (r, x, got, k)
+
+
+def test_voxel_keys_reject_out_of_range_and_nonfinite():
+    s = oracle.voxel_scale(0.5)
+    with pytest.raises(OverflowError):
+        oracle.voxel_keys(np.array([[6e5, 0, 0]], np.float32), s)
+    with pytest.raises(FloatingPointError):
+        oracle.voxel_keys(np.array([[np.nan, 0, 0]], np.float32), s)
+    with pytest.raises(ValueError):
+        oracle.voxel_scale(0.0)
+    # the largest admissible key
+    k = oracle.voxel_keys(np.array([[524287.5, -524288.0, 0]], np.float32), s)
+    assert k[0, 0] == (1 << 20) - 1 and k[0, 1] == -(1 << 20)
+
+
+@pytest.mark.parametrize("r", [0.25, 0.5, 1.0])
+def test_voxelize_bruteforce_exact(tiny, r):
+    xyz, cov = tiny.targets[0]
+    # duplicate a few points so voxels with repeated points occur
+    xyz = np.concatenate([xyz, xyz[:20]])
+    cov = np.concatenate([cov, cov[:20]])
+    vm, inv = oracle.voxelize(xyz, cov, r)
+    groups = {}
+    for i in range(xyz.shape[0]):
+        key = tuple(math.floor(Fraction(float(v)) / Fraction(r)) for v in xyz[i])
+        groups.setdefault(key, []).append(i)
+    keys = sorted(groups)
+    assert vm.n_voxels == len(keys)
+    assert [tuple(k) for k in vm.keys.tolist()] == keys
+    for o, key in enumerate(keys):
+        idx = groups[key]
+        assert vm.count[o] == len(idx)
+        assert all(inv[i] == o for i in idx)
+        for arr, got in ((xyz, vm.mean[o]), (cov, vm.cov[o])):
+            exact = [sum(Fraction(float(arr[i, c])) for i in idx) / len(idx)
+                     for c in range(arr.shape[1])]
+            for c, ex in enumerate(exact):
+                # the stored FP32 value is a rounding of the exact mean
+                g = Fraction(float(got[c]))
+                ulp = Fraction(float(np.spacing(np.float32(abs(float(ex))) or np.float32(1e-30))))
+                assert abs(g - ex) <= ulp, (o, c, float(g), float(ex))
+
+
+def test_voxelize_empty():
+    vm, inv = oracle.voxelize(np.zeros((0, 3), np.float32), np.zeros((0, 6), np.float32), 0.5)
+    assert vm.n_voxels == 0 and inv.shape == (0,)
+
+
+# ------------------------------------------------------------ relative pose
+
+def test_relative_pose_matches_matrix_inverse(tiny):
+    pi, pj = tiny.poses[0], tiny.poses[1]
+    R, t = oracle.relative_pose(pi, pj)
+    T = np.linalg.inv(hom(pj)) @ hom(pi)
+    assert np.abs(R - T[:3, :3]).max() < 1e-14
+    assert np.abs(t - T[:3, 3]).max() < 1e-13
+
+
+def test_relative_pose_equal_poses_is_exact_identity(tiny):
+    R, t = oracle.relative_pose(tiny.poses[0], tiny.poses[0])
+    assert np.array_equal(R, np.eye(3)) and np.array_equal(t, np.zeros(3))
+
+
+# ---------------------------------------------------------- correspondences
+
+def test_lookup_transform_is_the_relative_motion(tiny):
+    xyz = tiny.sources[0][0]
+    R, t = oracle.relative_pose(tiny.poses[0], tiny.poses[1])
+    q = oracle.vgicp_oracle.lookup_transform_fp32(xyz, R, t)
+    T = np.linalg.inv(hom(tiny.poses[1])) @ hom(tiny.poses[0])
+    q64 = xyz.astype(np.float64) @ T[:3, :3].T + T[:3, 3]
+    scale = np.abs(xyz).max() + np.abs(T[:3, 3]).max()
+    assert np.abs(q - q64).max() < 8 * np.finfo(np.float32).eps * scale
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0])
+def test_lookup_linear_scan(tiny, r):
+    src, tgt = tiny.sources[0][0], tiny.targets[0]
+    vm, _ = oracle.voxelize(*tgt, r)
+    R, t = oracle.relative_pose(tiny.poses[0], tiny.poses[1])
+    corr = oracle.lookup(vm, src, R, t)
+    q = oracle.vgicp_oracle.lookup_transform_fp32(src, R, t).astype(np.float64)
+    lo = vm.keys.astype(np.float64) * r                # (V, 3) voxel boxes
+    inside = np.all((q[:, None, :] >= lo[None]) & (q[:, None, :] < lo[None] + r), axis=2)
+    want = np.where(inside.any(1), inside.argmax(1), -1)
+    assert inside.sum(1).max() <= 1
+    assert np.array_equal(corr, want)
+    assert (corr >= 0).sum() > 50
+
+
+def test_lookup_far_and_out_of_range_keys_miss(tiny):
+    src, tgt = tiny.sources[0][0], tiny.targets[0]
+    vm, _ = oracle.voxelize(*tgt, 0.5)
+    for shift in (1e4, 1e6, 1e30):
+        pj = hom(tiny.poses[1])
+        pj[0, 3] += shift
+        R, t = oracle.relative_pose(tiny.poses[0], rows(pj))
+        assert np.all(oracle.lookup(vm, src, R, t) == -1)
+
+
+# --------------------------------------------------------- Hessian factor
+
+def test_jacobians_hessian_and_b_match_finite_differences(tiny):
+    xyz, cov = tiny.sources[0]
+    vm, _ = oracle.voxelize(*tiny.targets[0], tiny.resolution)
+    fd = fd_hessian_factor(xyz, cov, vm, tiny.poses[0], tiny.poses[1])
+    out = fd["oracle"]
+    assert out["inliers"] > 50
+    assert rel_err(out["H"], fd["H"]) < 1e-7
+    assert rel_err(out["b"], fd["b"]) < 1e-7
+    assert abs(out["e"] - fd["e"]) <= 1e-12 * abs(fd["e"])
+    # per-point Jacobians
+    hit = out["corr"] >= 0
+    R, t = out["R"], out["t"]
+    mu = xyz[hit].astype(np.float64)
+    A, B = oracle.vgicp_oracle.jacobians(R, mu, mu @ R.T + t)
+    Jo = np.concatenate([A, B], 2)
+    assert np.abs(Jo - fd["J"]).max() < 1e-6 * max(1.0, np.abs(Jo).max())
+
+
+def test_frozen_cost_gradient_is_twice_b(tiny):
+    xyz, cov = tiny.sources[0]
+    vm, _ = oracle.voxelize(*tiny.targets[0], tiny.resolution)
+    g, out = fd_cost_gradient(xyz, cov, vm, tiny.poses[0], tiny.poses[1])
+    assert rel_err(g, 2 * out["b"]) < 1e-7
+
+
+def test_hessian_structure(cfg1):
+    vm, _ = oracle.voxelize(*cfg1.targets[0], cfg1.resolution)
+    out = oracle.linearize_factor(*cfg1.sources[0], vm, cfg1.poses[0], cfg1.poses[1])
+    H, b = out["H"], out["b"]
+    nH = np.linalg.norm(H)
+    assert np.abs(H - H.T).max() <= 1e-13 * nH
+    ev = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert ev.min() >= -1e-10 * ev.max()
+    N = null_space_basis(cfg1.poses[0], cfg1.poses[1])
+    assert np.linalg.norm(H @ N) <= 1e-10 * nH * np.linalg.norm(N)
+    assert np.abs(b @ N).max() <= 1e-10 * np.linalg.norm(b) * np.linalg.norm(N)
+    # exactly six gauge directions: rank 6
+    assert np.sum(ev > 1e-8 * ev.max()) == 6
+
+
+def test_invariance_under_common_rigid_motion(cfg1):
+    vm, _ = oracle.voxelize(*cfg1.targets[0], cfg1.resolution)
+    base = oracle.linearize_factor(*cfg1.sources[0], vm, cfg1.poses[0], cfg1.poses[1])
+    # a sign-flip rotation (180 degrees about z) keeps the relative pose bitwise
+    G = np.diag([-1.0, -1.0, 1.0, 1.0])
+    pi, pj = rows(G @ hom(cfg1.poses[0])), rows(G @ hom(cfg1.poses[1]))
+    flip = oracle.linearize_factor(*cfg1.sources[0], vm, pi, pj)
+    assert np.array_equal(flip["corr"], base["corr"])
+    assert np.array_equal(flip["H"], base["H"]) and flip["e"] == base["e"]
+    # a generic motion changes the relative pose only by rounding
+    from tests.oracle_pins import so3_exp
+    G = np.eye(4)
+    G[:3, :3] = so3_exp(np.array([0.3, -0.2, 0.5]))
+    G[:3, 3] = [3.0, -7.0, 1.5]
+    pi, pj = rows(G @ hom(cfg1.poses[0])), rows(G @ hom(cfg1.poses[1]))
+    gen = oracle.linearize_factor(*cfg1.sources[0], vm, pi, pj)
+    assert np.array_equal(gen["corr"], base["corr"])
+    assert rel_err(gen["H"], base["H"]) < 1e-12
+    assert rel_err(gen["b"], base["b"]) < 1e-10
+    assert abs(gen["e"] - base["e"]) < 1e-12 * base["e"]
+
+
+def test_isotropic_covariances_reduce_to_icp_normal_equations(tiny):
+    xyz, _ = tiny.sources[0]
+    txyz, _ = tiny.targets[0]
+    sig2, tau2 = 0.5, 0.25
+    cov_s = np.tile(np.array([sig2, 0, 0, sig2, 0, sig2], np.float32), (xyz.shape[0], 1))
+    cov_t = np.tile(np.array([tau2, 0, 0, tau2, 0, tau2], np.float32), (txyz.shape[0], 1))
+    vm, _ = oracle.voxelize(txyz, cov_t, tiny.resolution)
+    assert np.all(vm.cov[:, [0, 3, 5]] == tau2) and np.all(vm.cov[:, [1, 2, 4]] == 0)
+    out = oracle.linearize_factor(xyz, cov_s, vm, tiny.poses[0], tiny.poses[1])
+    H, b, e = icp_normal_equations(xyz, vm, tiny.poses[0], tiny.poses[1], out["corr"],
+                                   1.0 / (sig2 + tau2))
+    assert rel_err(out["H"], H) < 1e-12
+    assert rel_err(out["b"], b) < 1e-12
+    assert abs(out["e"] - e) < 1e-12 * e
+
+
+def test_single_point_golden():
+    with open(os.path.join(GOLDEN, "single_point_factors.json")) as fh:
+        cases = json.load(fh)["cases"]
+    eye6 = np.array([[1, 0, 0, 1, 0, 1]], np.float32)
+    for c in cases:
+        vm, _ = oracle.voxelize(np.array([c["target_point"]], np.float32), eye6, c["resolution"])
+        out = oracle.linearize_factor(np.array([c["mu"]], np.float32), eye6, vm,
+                                      np.array(c["pose_i"], float), np.array(c["pose_j"], float))
+        assert out["inliers"] == c["inliers"], c["name"]
+        assert np.allclose(out["b"], c["b"], atol=1e-15), c["name"]
+        assert abs(out["e"] - c["e"]) < 1e-15, c["name"]
+        if c["J_columns"] is None:
+            assert np.all(out["H"] == 0)
+        else:
+            J = np.array(c["J_columns"], float).T           # (3, 12)
+            assert np.allclose(out["H"], 0.5 * J.T @ J, atol=1e-15), c["name"]
+            assert np.allclose(out["b"], 0.5 * J.T @ np.array(c["residual"]), atol=1e-15)
+
+
+def test_empty_source_and_no_hits(tiny):
+    vm, _ = oracle.voxelize(*tiny.targets[0], 0.5)
+    out = oracle.linearize_factor(np.zeros((0, 3), np.float32), np.zeros((0, 6), np.float32),
+                                  vm, tiny.poses[0], tiny.poses[1])
+    assert out["inliers"] == 0 and out["e"] == 0.0 and not out["H"].any()
+    assert oracle.overlap_factor(np.zeros((0, 3), np.float32), vm, tiny.poses[0],
+                                 tiny.poses[1]) == (0, 0.0)
+
+
+# ----------------------------------------------------------------- overlap
+
+def test_overlap_self_far_and_hits_equal_inliers(cfg1):
+    xyz, cov = cfg1.targets[0]
+    vm, _ = oracle.voxelize(xyz, cov, cfg1.resolution)
+    assert oracle.overlap_factor(xyz, vm, cfg1.poses[0], cfg1.poses[0]) == (xyz.shape[0], 1.0)
+    far = hom(cfg1.poses[1])
+    far[:3, 3] += [1e4, 0, 0]
+    assert oracle.overlap_factor(xyz, vm, cfg1.poses[1], rows(far)) == (0, 0.0)
+    sx, sc = cfg1.sources[0]
+    hits, ov = oracle.overlap_factor(sx, vm, cfg1.poses[0], cfg1.poses[1])
+    out = oracle.linearize_factor(sx, sc, vm, cfg1.poses[0], cfg1.poses[1])
+    assert hits == out["inliers"] and ov == hits / sx.shape[0]
+
+
+def test_workload_driver_matches_per_factor():
+    w = make_tiny_workload(seed=3, n_src=[50, 80, 0], n_tgt=[90, 60, 70], resolution=0.5, n_factors=3)
+    maps = oracle.build_maps(w.targets, w.resolution)
+    res = oracle.linearize_workload(w.sources, maps, w.poses, w.factors)
+    for f, (s, t, pi, pj) in enumerate(w.factors):
+        one = oracle.linearize_factor(*w.sources[s], maps[t], w.poses[pi], w.poses[pj])
+        assert np.array_equal(res["H"][f], one["H"]) and res["inliers"][f] == one["inliers"]
+    assert res["inliers"][2] == 0
