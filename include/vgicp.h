@@ -1,0 +1,243 @@
+/*
+ * vgicp.h - C ABI of the VGICP matching-cost factor library for MI355X (gfx950).
+ *
+ * Implements the GPU part of Koide et al., "Globally Consistent 3D LiDAR
+ * Mapping with GPU-accelerated GICP Matching Cost Factors" (IEEE RA-L 2021):
+ *   - voxel maps of point clouds with per-point covariances   (Sec. III-A, VGICP
+ *     voxel data association)
+ *   - linearization of matching-cost factors into Hessian factors
+ *     H_ii, H_ij, H_jj, b_i, b_j and the cost e^M                (Sec. III-A, Eqs. (2)-(6))
+ *   - the matching cost alone, for trial steps                   (Sec. III-A, Eq. (3))
+ *   - the voxel overlap metric                                   (Sec. III-B, Eqs. (7)-(8))
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named in comments as "device" are HIP device pointers (for example
+ *     the data_ptr() of a torch tensor on the GPU); "host" pointers are read
+ *     before the call returns.
+ *   - Work is enqueued on the context's HIP stream.  Device outputs are valid
+ *     once that stream has been synchronized.  vgicp_voxelize is the one call
+ *     that synchronizes itself (it sizes the map).
+ *   - Every function returns VGICP_OK (0) or a negative status.  The message of
+ *     the last failure is available from vgicp_last_error(ctx) (or with a NULL
+ *     ctx for failures that had no valid context).  On failure no output is
+ *     specified and no handle is created.
+ *   - Arguments are validated on the host before anything is enqueued.
+ *   - Clouds are frame-local.  A cloud of n points is two SoA arrays:
+ *       xyz: float32 [3][n]  (x[0..n), then y[0..n), then z[0..n))
+ *       cov: float32 [6][n]  (planes xx, xy, xz, yy, yz, zz of the symmetric
+ *                              3x3 point covariance)
+ *     The caller owns them and keeps them alive while any factor set that
+ *     references them is used.
+ *   - A pose is 12 float64 values: R (3x3, row-major) then t; it maps sensor
+ *     coordinates to world coordinates, x_world = R x + t.
+ *   - Factor (i, j) matches the source cloud (in frame i) against the voxel map
+ *     of the target cloud (in frame j): every source point is carried into
+ *     frame j by T_j^-1 T_i and looked up in the single voxel that contains it.
+ *   - Hessian factors use right perturbations T <- T Exp(xi), xi = (omega, rho),
+ *     rotation first; the 12-vector order is [xi_i; xi_j], and
+ *       H = [[H_ii, H_ij], [H_ij^T, H_jj]],  b = [b_i; b_j],
+ *       e = sum_k e_k^T Omega_k e_k,  e_k = mu'_k - T_j^-1 T_i mu_k,
+ *       Omega_k = (C'_k + R C_k R^T)^-1,
+ *     with the correspondences and Omega_k frozen at the linearization point.
+ *   - One context per host thread; calls that share a context are serialized by
+ *     the caller.  No C++ exception crosses this interface.
+ */
+#ifndef VGICP_H
+#define VGICP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VGICP_OK 0
+#define VGICP_EINVAL (-1)     /* invalid argument                                  */
+#define VGICP_ENOMEM (-2)     /* device or host allocation failed                  */
+#define VGICP_ERANGE (-3)     /* a voxel key of a cloud lies outside [-2^20, 2^20) */
+#define VGICP_ENONFINITE (-4) /* a point coordinate is NaN or infinite             */
+#define VGICP_EHIP (-5)       /* a HIP runtime call failed                         */
+
+/* Accumulation of the per-point Hessian, gradient and cost terms. */
+#define VGICP_ACC_F32 0      /* FP32 per lane and across the workgroup              */
+#define VGICP_ACC_F32_COMP 1 /* FP32 with two-sum compensation                      */
+#define VGICP_ACC_F64 2      /* FP64 from the first per-point term                  */
+
+/* Residual e_k = mu'_k - T mu_k of the per-point terms.  The correspondence
+ * decision always uses the FP32 transform; these modes only change how the
+ * residual's rounding error is handled. */
+#define VGICP_RESID_FF 0  /* double-float transform (exact products by fma, two-sum): the
+                             residual is accurate to FP32 rounding of the residual itself */
+#define VGICP_RESID_F32 1 /* plain FP32 transform: absolute error ~ |mu| * 2^-23        */
+
+/* How the factors of one call are launched. */
+#define VGICP_SCHED_BATCHED 0    /* one launch over the tiles of all factors, one reduce   */
+#define VGICP_SCHED_PER_FACTOR 1 /* one linearize launch and one reduce launch per factor */
+
+typedef struct vgicp_context_s *vgicp_ctx;
+typedef struct vgicp_voxelmap_s *vgicp_map;
+typedef struct vgicp_factorset_s *vgicp_factorset;
+
+typedef struct {
+  const float *xyz; /* device, [3][n] */
+  const float *cov; /* device, [6][n] */
+  int64_t n;        /* number of points, >= 0 */
+} vgicp_cloud;
+
+/* One matching-cost factor (Eq. (1)): indices into the source-cloud list, the
+ * voxel-map list and the pose array. */
+typedef struct {
+  int32_t src;
+  int32_t tgt;
+  int32_t pose_i;
+  int32_t pose_j;
+} vgicp_factor;
+
+typedef struct {
+  int32_t accum;     /* VGICP_ACC_*                                                  */
+  int32_t schedule;  /* VGICP_SCHED_*                                                */
+  int32_t use_graph; /* nonzero: the batched schedule is captured once into a HIP
+                        graph per (poses, outputs) pointer set and replayed          */
+  int32_t resid;     /* VGICP_RESID_*                                                */
+} vgicp_opts;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int vgicp_version(void);
+
+/* Message of the last failure on ctx (ctx may be NULL: message of the last
+ * failure on this thread that had no valid context).  Never NULL. */
+const char *vgicp_last_error(vgicp_ctx ctx);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a
+ * hipStream_t; NULL means the default stream).  The stream is borrowed.
+ * Errors: EINVAL (out NULL, device out of range), EHIP. */
+int vgicp_ctx_create(int device, void *hip_stream, vgicp_ctx *out);
+
+/* Change the stream later calls enqueue on.  Errors: EINVAL. */
+int vgicp_ctx_set_stream(vgicp_ctx ctx, void *hip_stream);
+
+/* Wait for the context's stream.  Errors: EINVAL, EHIP. */
+int vgicp_ctx_synchronize(vgicp_ctx ctx);
+
+/* Kernel timing.  While enabled, later calls bracket each kernel they launch
+ * outside a HIP graph with a pair of HIP events on the context's stream; the
+ * durations are added per kernel kind.  vgicp_ctx_read_timing synchronizes the
+ * stream, folds the pending event pairs in and returns the total milliseconds
+ * and launch count of `kernel` since the last reset.  Errors: EINVAL, EHIP. */
+#define VGICP_KERNEL_LINEARIZE 0 /* per-tile linearization kernel            */
+#define VGICP_KERNEL_REDUCE 1    /* per-factor reduce / expand kernel          */
+#define VGICP_KERNEL_OVERLAP 2   /* per-tile overlap kernel                    */
+#define VGICP_KERNEL_EVALUATE 3  /* per-tile cost-only kernel                  */
+#define VGICP_KERNEL_KINDS 4
+int vgicp_ctx_set_timing(vgicp_ctx ctx, int enable);
+int vgicp_ctx_read_timing(vgicp_ctx ctx, int kernel, double *total_ms, int64_t *launches);
+int vgicp_ctx_reset_timing(vgicp_ctx ctx);
+
+/* Destroy a context and its workspace.  Maps and factor sets created from it
+ * must be freed first.  NULL is accepted. */
+int vgicp_ctx_destroy(vgicp_ctx ctx);
+
+/* --------------------------------------------------------------------------
+ * Voxel maps (Sec. III-A): the cloud is discretized at resolution r; voxel v
+ * holds the points whose key floor(fl32(x * fl32(1/r))) (per axis, FP32) equals
+ * its key.  Its mean is fl32 of the FP64 mean of those points, its covariance
+ * fl32 of the FP64 mean of their covariances (VGICP aggregates point
+ * distributions, it does not take the sample covariance of positions).  Voxel
+ * ordinals number the voxels in lexicographic (kx, ky, kz) key order.
+ * ------------------------------------------------------------------------ */
+
+/* Build the voxel map of `cloud` (host struct, device arrays) at `resolution`
+ * metres.  Synchronizes the stream once.  The map is library-owned device
+ * memory; free it with vgicp_map_free.  The cloud is not referenced after the
+ * call returns.
+ * Errors: EINVAL (NULL pointers with n > 0, n < 0, resolution not finite or
+ * <= 0), ENONFINITE, ERANGE, ENOMEM, EHIP. */
+int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out);
+
+/* Map facts: number of voxels, hash capacity (slots), device bytes held and the
+ * resolution.  Any output pointer may be NULL.  Errors: EINVAL. */
+int vgicp_map_info(vgicp_map map, int64_t *n_voxels, int64_t *capacity, int64_t *device_bytes,
+                   double *resolution);
+
+/* Copy the map out in ordinal order into device arrays: keys int32 [V][3],
+ * mean float32 [V][3], cov float32 [V][6], count int32 [V].  Any may be NULL.
+ * Enqueued on the stream.  Errors: EINVAL, EHIP. */
+int vgicp_map_export(vgicp_ctx ctx, vgicp_map map, int32_t *keys, float *mean, float *cov,
+                     int32_t *count);
+
+/* Free a map (NULL accepted).  The caller makes sure no enqueued work still
+ * reads it (synchronize first). */
+int vgicp_map_free(vgicp_map map);
+
+/* --------------------------------------------------------------------------
+ * Factor sets: the factor list F^M of Eq. (1) bound to its clouds and maps.
+ * Creating one validates every index and uploads the device tables once, so
+ * that each optimizer iteration only passes new poses.
+ * ------------------------------------------------------------------------ */
+
+/* sources: host array of n_sources cloud descriptors (device data, caller
+ * owned, must outlive the factor set); maps: host array of n_maps handles;
+ * factors: host array of n_factors rows; n_poses: length of the pose arrays
+ * later calls pass; tile_points: source points per workgroup tile (0 picks
+ * the default 4096; otherwise a multiple of 256 in [256, 1<<20]).
+ * Outputs of later calls are indexed in the order of `factors`.  Per-point
+ * outputs (corr) are laid out factor after factor, n_src points each.
+ * Errors: EINVAL (any index out of range, NULL pointers with nonzero counts,
+ * bad tile_points), ENOMEM, EHIP. */
+int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_sources,
+                           const vgicp_map *maps, int32_t n_maps, const vgicp_factor *factors,
+                           int64_t n_factors, int32_t n_poses, int32_t tile_points,
+                           vgicp_factorset *out);
+
+/* Factor-set facts; any output may be NULL.  Errors: EINVAL. */
+int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
+                         int64_t *total_points);
+
+/* Free a factor set and its captured graphs (NULL accepted). */
+int vgicp_factorset_destroy(vgicp_factorset fs);
+
+/* Host-side check of a factor list without any device (used by the factor-set
+ * constructor).  Errors: EINVAL with a message naming the first bad row. */
+int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
+                           const vgicp_factor *factors, int64_t n_factors);
+
+/* --------------------------------------------------------------------------
+ * Linearization (Sec. III-A, Eqs. (2)-(6)) and cost evaluation (Eq. (3)).
+ * ------------------------------------------------------------------------ */
+
+/* Linearize every factor of `fs` at `poses` (device float64 [n_poses][12]).
+ * Outputs (device): H float64 [n_factors][12][12] (row-major, symmetric),
+ * b float64 [n_factors][12], e float64 [n_factors], inliers int64 [n_factors]
+ * (points that fell in a voxel of the target map), and optionally corr int32
+ * [total_points] with the voxel ordinal of each source point or -1 (NULL to
+ * skip).  A factor with no inlier returns H = 0, b = 0, e = 0.
+ * opts may be NULL (FP32 accumulation, batched schedule, no graph, double-float residual).  Results
+ * are deterministic and do not depend on the schedule or on the other factors
+ * of the set.  Errors: EINVAL, EHIP. */
+int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                            const vgicp_opts *opts, double *H, double *b, double *e,
+                            int64_t *inliers, int32_t *corr);
+
+/* The cost e (device float64 [n_factors]) and inliers (device int64
+ * [n_factors]) alone, without Jacobians; equal to the e and inliers of
+ * vgicp_linearize_factors with the same accumulation.  Errors: EINVAL, EHIP. */
+int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                          const vgicp_opts *opts, double *e, int64_t *inliers);
+
+/* --------------------------------------------------------------------------
+ * Overlap (Sec. III-B, Eqs. (7)-(8)): for each factor row (i, j), hits = number
+ * of source points falling in a voxel of the target map under T_j^-1 T_i and
+ * overlap = hits / N (0 when N = 0).
+ * ------------------------------------------------------------------------ */
+
+/* hits: device int64 [n_factors]; overlap: device float64 [n_factors] (may be
+ * NULL).  Errors: EINVAL, EHIP. */
+int vgicp_overlap(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, int64_t *hits,
+                  double *overlap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VGICP_H */

@@ -1,0 +1,559 @@
+// Host runtime behind the C ABI in include/vgicp.h: argument validation,
+// contexts, voxel-map and factor-set handles, schedules and HIP graphs.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "vgicp_internal.hpp"
+
+namespace vgicp {
+int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out,
+                  std::string &msg);
+int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
+                    int32_t *count, std::string &msg);
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, bool lin,
+                            int64_t tb, int64_t te, const double *poses, int32_t *corr,
+                            hipStream_t st);
+hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
+                          const double *poses, hipStream_t st);
+hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
+                         int mode, double *H, double *b, double *e, int64_t *inl,
+                         double *overlap, hipStream_t st);
+}  // namespace vgicp
+
+using namespace vgicp;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+int fail(vgicp_ctx ctx, int code, const std::string &msg) {
+  if (ctx)
+    ctx->last_error = msg;
+  else
+    g_thread_error = msg;
+  return code;
+}
+
+int hip_fail(vgicp_ctx ctx, const char *what, hipError_t e) {
+  return fail(ctx, e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Make ctx's device current for the calling thread.
+int use_device(vgicp_ctx ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, "hipSetDevice", e);
+  return VGICP_OK;
+}
+
+constexpr int kDefaultTile = 4096;
+
+// Brackets one kernel launch with events when timing is on.
+struct TimedLaunch {
+  vgicp_ctx ctx;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(vgicp_ctx c, int k) : ctx(c), kind(k) {
+    if (!ctx->timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+        hipEventRecord(a, ctx->stream) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      a = b = nullptr;
+    }
+  }
+  void done() {
+    if (!a) return;
+    if (hipEventRecord(b, ctx->stream) == hipSuccess) {
+      ctx->pending[kind].emplace_back(a, b);
+    } else {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+    a = b = nullptr;
+  }
+};
+
+hipError_t fold_timing(vgicp_ctx ctx) {
+  hipError_t err = hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < VGICP_KERNEL_KINDS; ++k) {
+    for (auto &p : ctx->pending[k]) {
+      float ms = 0.f;
+      if (err == hipSuccess) {
+        err = hipEventElapsedTime(&ms, p.first, p.second);
+        if (err == hipSuccess) {
+          ctx->total_ms[k] += double(ms);
+          ctx->launches[k] += 1;
+        }
+      }
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    ctx->pending[k].clear();
+  }
+  return err;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vgicp_version(void) { return 100; }
+
+const char *vgicp_last_error(vgicp_ctx ctx) {
+  return ctx ? ctx->last_error.c_str() : g_thread_error.c_str();
+}
+
+int vgicp_ctx_create(int device, void *hip_stream, vgicp_ctx *out) {
+  if (!out) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(nullptr, "vgicp_ctx_create: hipGetDeviceCount", e);
+  if (device < 0 || device >= n)
+    return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_create: device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, "vgicp_ctx_create: hipSetDevice", e);
+  vgicp_ctx ctx = new (std::nothrow) vgicp_context_s();
+  if (!ctx) return fail(nullptr, VGICP_ENOMEM, "vgicp_ctx_create: out of host memory");
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  e = hipMalloc(&ctx->err_word, 256);
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->host_pinned, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) {
+    if (ctx->err_word) (void)hipFree(ctx->err_word);
+    if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    delete ctx;
+    return hip_fail(nullptr, "vgicp_ctx_create", e);
+  }
+  *out = ctx;
+  return VGICP_OK;
+}
+
+int vgicp_ctx_set_stream(vgicp_ctx ctx, void *hip_stream) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_set_stream: ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return VGICP_OK;
+}
+
+int vgicp_ctx_synchronize(vgicp_ctx ctx) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_synchronize: ctx is NULL");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, "hipStreamSynchronize", e);
+  return VGICP_OK;
+}
+
+int vgicp_ctx_set_timing(vgicp_ctx ctx, int enable) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_set_timing: ctx is NULL");
+  ctx->timing = enable != 0;
+  return VGICP_OK;
+}
+
+int vgicp_ctx_read_timing(vgicp_ctx ctx, int kernel, double *total_ms, int64_t *launches) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_read_timing: ctx is NULL");
+  if (kernel < 0 || kernel >= VGICP_KERNEL_KINDS)
+    return fail(ctx, VGICP_EINVAL, "vgicp_ctx_read_timing: unknown kernel kind");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  hipError_t e = fold_timing(ctx);
+  if (e != hipSuccess) return hip_fail(ctx, "vgicp_ctx_read_timing", e);
+  if (total_ms) *total_ms = ctx->total_ms[kernel];
+  if (launches) *launches = ctx->launches[kernel];
+  return VGICP_OK;
+}
+
+int vgicp_ctx_reset_timing(vgicp_ctx ctx) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_ctx_reset_timing: ctx is NULL");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  hipError_t e = fold_timing(ctx);
+  for (int k = 0; k < VGICP_KERNEL_KINDS; ++k) {
+    ctx->total_ms[k] = 0.0;
+    ctx->launches[k] = 0;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, "vgicp_ctx_reset_timing", e);
+  return VGICP_OK;
+}
+
+int vgicp_ctx_destroy(vgicp_ctx ctx) {
+  if (!ctx) return VGICP_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)fold_timing(ctx);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->err_word) (void)hipFree(ctx->err_word);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------------ maps
+
+int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_voxelize: ctx is NULL");
+  if (!out) return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: out is NULL");
+  *out = nullptr;
+  if (!cloud) return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: cloud is NULL");
+  if (cloud->n < 0) return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: n < 0");
+  if (cloud->n > INT32_MAX)
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: more than 2^31-1 points");
+  if (cloud->n > 0 && (!cloud->xyz || !cloud->cov))
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: NULL point arrays with n > 0");
+  if (!std::isfinite(resolution) || !(resolution > 0.0))
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: resolution must be finite and > 0");
+  const float s = float(1.0 / resolution);
+  if (!std::isfinite(s) || !(s > 0.0f))
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: 1/resolution is not a positive FP32 value");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  std::string msg;
+  rc = voxelize_impl(ctx, cloud, resolution, out, msg);
+  if (rc != VGICP_OK) return fail(ctx, rc, msg);
+  return VGICP_OK;
+}
+
+int vgicp_map_info(vgicp_map map, int64_t *n_voxels, int64_t *capacity, int64_t *device_bytes,
+                   double *resolution) {
+  if (!map) return fail(nullptr, VGICP_EINVAL, "vgicp_map_info: map is NULL");
+  if (n_voxels) *n_voxels = map->n_voxels;
+  if (capacity) *capacity = map->capacity;
+  if (device_bytes) *device_bytes = map->capacity * int64_t(sizeof(Slot));
+  if (resolution) *resolution = map->resolution;
+  return VGICP_OK;
+}
+
+int vgicp_map_export(vgicp_ctx ctx, vgicp_map map, int32_t *keys, float *mean, float *cov,
+                     int32_t *count) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_map_export: ctx is NULL");
+  if (!map) return fail(ctx, VGICP_EINVAL, "vgicp_map_export: map is NULL");
+  if (map->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, "vgicp_map_export: map lives on another device");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  std::string msg;
+  rc = map_export_impl(ctx, map, keys, mean, cov, count, msg);
+  if (rc != VGICP_OK) return fail(ctx, rc, msg);
+  return VGICP_OK;
+}
+
+int vgicp_map_free(vgicp_map map) {
+  if (!map) return VGICP_OK;
+  (void)hipSetDevice(map->device);
+  if (map->slots) (void)hipFree(map->slots);
+  delete map;
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------ factor sets
+
+int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
+                           const vgicp_factor *factors, int64_t n_factors) {
+  if (n_sources < 0 || n_maps < 0 || n_poses < 0 || n_factors < 0)
+    return fail(nullptr, VGICP_EINVAL, "vgicp_validate_factors: negative count");
+  if (n_factors > 0 && !factors)
+    return fail(nullptr, VGICP_EINVAL, "vgicp_validate_factors: factors is NULL");
+  if (n_factors > INT32_MAX)
+    return fail(nullptr, VGICP_EINVAL, "vgicp_validate_factors: more than 2^31-1 factors");
+  for (int64_t f = 0; f < n_factors; ++f) {
+    const vgicp_factor &x = factors[f];
+    const char *bad = nullptr;
+    if (x.src < 0 || x.src >= n_sources) bad = "src";
+    else if (x.tgt < 0 || x.tgt >= n_maps) bad = "tgt";
+    else if (x.pose_i < 0 || x.pose_i >= n_poses) bad = "pose_i";
+    else if (x.pose_j < 0 || x.pose_j >= n_poses) bad = "pose_j";
+    if (bad)
+      return fail(nullptr, VGICP_EINVAL,
+                  "vgicp_validate_factors: factor " + std::to_string(f) + " has " + bad +
+                      " out of range");
+  }
+  return VGICP_OK;
+}
+
+int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_sources,
+                           const vgicp_map *maps, int32_t n_maps, const vgicp_factor *factors,
+                           int64_t n_factors, int32_t n_poses, int32_t tile_points,
+                           vgicp_factorset *out) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_create: ctx is NULL");
+  if (!out) return fail(ctx, VGICP_EINVAL, "vgicp_factorset_create: out is NULL");
+  *out = nullptr;
+  if (n_sources > 0 && !sources)
+    return fail(ctx, VGICP_EINVAL, "vgicp_factorset_create: sources is NULL");
+  if (n_maps > 0 && !maps) return fail(ctx, VGICP_EINVAL, "vgicp_factorset_create: maps is NULL");
+  if (vgicp_validate_factors(n_sources, n_maps, n_poses, factors, n_factors) != VGICP_OK)
+    return fail(ctx, VGICP_EINVAL, g_thread_error);
+  if (tile_points == 0) tile_points = kDefaultTile;
+  if (tile_points < 256 || tile_points > (1 << 20) || tile_points % 256 != 0)
+    return fail(ctx, VGICP_EINVAL,
+                "vgicp_factorset_create: tile_points must be a multiple of 256 in [256, 2^20]");
+  for (int32_t s = 0; s < n_sources; ++s) {
+    const vgicp_cloud &c = sources[s];
+    if (c.n < 0 || c.n > INT32_MAX || (c.n > 0 && (!c.xyz || !c.cov)))
+      return fail(ctx, VGICP_EINVAL,
+                  "vgicp_factorset_create: source " + std::to_string(s) + " is invalid");
+  }
+  for (int32_t m = 0; m < n_maps; ++m)
+    if (!maps[m] || maps[m]->device != ctx->device)
+      return fail(ctx, VGICP_EINVAL,
+                  "vgicp_factorset_create: map " + std::to_string(m) + " is NULL or foreign");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+
+  auto *fs = new (std::nothrow) vgicp_factorset_s();
+  if (!fs) return fail(ctx, VGICP_ENOMEM, "vgicp_factorset_create: out of host memory");
+  fs->device = ctx->device;
+  fs->n_factors = n_factors;
+  fs->n_poses = n_poses;
+  fs->tile_points = tile_points;
+  fs->h_factors.resize(size_t(n_factors));
+
+  // Tile order: factors grouped by target map so that consecutive tiles (and
+  // therefore one XCD's share of the grid) reuse the same hash table.
+  std::vector<int64_t> order(static_cast<size_t>(n_factors));
+  std::iota(order.begin(), order.end(), int64_t(0));
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return factors[a].tgt < factors[b].tgt;
+  });
+  int64_t corr_off = 0;
+  for (int64_t f = 0; f < n_factors; ++f) {
+    const vgicp_factor &x = factors[f];
+    FactorDesc &d = fs->h_factors[size_t(f)];
+    std::memset(&d, 0, sizeof(d));
+    const vgicp_cloud &c = sources[x.src];
+    const vgicp_voxelmap_s *m = maps[x.tgt];
+    d.xyz = c.xyz;
+    d.cov = c.cov;
+    d.slots = m->slots;
+    d.n = c.n;
+    d.corr_offset = corr_off;
+    d.pose_i = x.pose_i;
+    d.pose_j = x.pose_j;
+    d.log2cap = m->log2cap;
+    d.scale = m->scale;
+    corr_off += c.n;
+  }
+  fs->total_points = corr_off;
+  std::vector<Tile> tiles;
+  for (int64_t f : order) {
+    FactorDesc &d = fs->h_factors[size_t(f)];
+    d.tile_begin = int32_t(tiles.size());
+    for (int64_t s = 0; s < d.n; s += tile_points) tiles.push_back(Tile{int32_t(f), int32_t(s)});
+    d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
+  }
+  fs->n_tiles = int64_t(tiles.size());
+
+  hipError_t e = hipSuccess;
+  const size_t fbytes = std::max<size_t>(1, fs->h_factors.size()) * sizeof(FactorDesc);
+  const size_t tbytes = std::max<size_t>(1, tiles.size()) * sizeof(Tile);
+  const size_t pbytes = std::max<size_t>(1, tiles.size()) * kPartialStride * sizeof(double);
+  e = hipMalloc(&fs->d_factors, fbytes);
+  if (e == hipSuccess) e = hipMalloc(&fs->d_tiles, tbytes);
+  if (e == hipSuccess) e = hipMalloc(&fs->d_partials, pbytes);
+  if (e == hipSuccess && n_factors > 0)
+    e = hipMemcpyAsync(fs->d_factors, fs->h_factors.data(), fs->h_factors.size() * sizeof(FactorDesc),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(fs->d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    vgicp_factorset_destroy(fs);
+    return hip_fail(ctx, "vgicp_factorset_create", e);
+  }
+  *out = fs;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
+                         int64_t *total_points) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_info: fs is NULL");
+  if (n_factors) *n_factors = fs->n_factors;
+  if (n_tiles) *n_tiles = fs->n_tiles;
+  if (total_points) *total_points = fs->total_points;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_destroy(vgicp_factorset fs) {
+  if (!fs) return VGICP_OK;
+  (void)hipSetDevice(fs->device);
+  for (auto &g : fs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (fs->d_factors) (void)hipFree(fs->d_factors);
+  if (fs->d_tiles) (void)hipFree(fs->d_tiles);
+  if (fs->d_partials) (void)hipFree(fs->d_partials);
+  delete fs;
+  return VGICP_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------- execution
+
+namespace {
+
+constexpr int kKindLinearize = 0;
+constexpr int kKindEvaluate = 1;
+
+int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const char *who) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  if (fs->n_factors > 0 && fs->n_poses > 0 && !poses)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": poses is NULL");
+  return use_device(ctx);
+}
+
+int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
+  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_FF};
+  if (opts) *o = *opts;
+  if (o->accum < VGICP_ACC_F32 || o->accum > VGICP_ACC_F64)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown accumulation");
+  if (o->schedule != VGICP_SCHED_BATCHED && o->schedule != VGICP_SCHED_PER_FACTOR)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown schedule");
+  if (o->resid != VGICP_RESID_FF && o->resid != VGICP_RESID_F32)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown residual mode");
+  return VGICP_OK;
+}
+
+// Enqueue the factors' tiles [tb, te) and the reduce of factors [f0, f0+nf).
+// `ctx` is NULL inside graph capture (no timing events there).
+hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum, int resid,
+                         const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
+                         double *H, double *b, double *e, int64_t *inl, int32_t *corr,
+                         hipStream_t st) {
+  const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
+  hipError_t err = hipSuccess;
+  if (ctx) {
+    TimedLaunch t(ctx, tk);
+    err = launch_linearize(fs, accum, resid, kind == kKindLinearize, tb, te, poses, corr, st);
+    t.done();
+  } else {
+    err = launch_linearize(fs, accum, resid, kind == kKindLinearize, tb, te, poses, corr, st);
+  }
+  if (err != hipSuccess) return err;
+  if (ctx) {
+    TimedLaunch t(ctx, VGICP_KERNEL_REDUCE);
+    err = launch_reduce(fs, f0, nf, poses, kind, H, b, e, inl, nullptr, st);
+    t.done();
+  } else {
+    err = launch_reduce(fs, f0, nf, poses, kind, H, b, e, inl, nullptr, st);
+  }
+  return err;
+}
+
+int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses,
+                const vgicp_opts &o, double *H, double *b, double *e, int64_t *inl,
+                int32_t *corr, const char *who) {
+  if (fs->n_factors == 0) return VGICP_OK;
+  hipStream_t st = ctx->stream;
+  hipError_t err = hipSuccess;
+  if (o.schedule == VGICP_SCHED_PER_FACTOR) {
+    for (int64_t f = 0; f < fs->n_factors && err == hipSuccess; ++f) {
+      const FactorDesc &d = fs->h_factors[size_t(f)];
+      err = enqueue_range(ctx, fs, kind, o.accum, o.resid, poses, d.tile_begin,
+                          int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st);
+    }
+    if (err != hipSuccess) return hip_fail(ctx, who, err);
+    return VGICP_OK;
+  }
+  if (!o.use_graph) {
+    err = enqueue_range(ctx, fs, kind, o.accum, o.resid, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
+                        inl, corr, st);
+    if (err != hipSuccess) return hip_fail(ctx, who, err);
+    return VGICP_OK;
+  }
+  if (st == nullptr)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": graph replay needs a non-default stream");
+  GraphEntry *g = nullptr;
+  for (auto &x : fs->graphs)
+    if (x.poses == poses && x.H == H && x.b == b && x.e == e && x.inl == inl && x.corr == corr &&
+        x.accum == o.accum && x.resid == o.resid && x.kind == kind)
+      g = &x;
+  if (!g) {
+    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, kind};
+    err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return hip_fail(ctx, "hipStreamBeginCapture", err);
+    hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, poses, 0, fs->n_tiles, 0,
+                                    fs->n_factors, H, b, e, inl, corr, st);
+    err = hipStreamEndCapture(st, &ng.graph);
+    if (lerr != hipSuccess) {
+      if (ng.graph) (void)hipGraphDestroy(ng.graph);
+      return hip_fail(ctx, who, lerr);
+    }
+    if (err != hipSuccess) return hip_fail(ctx, "hipStreamEndCapture", err);
+    err = hipGraphInstantiate(&ng.exec, ng.graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+      (void)hipGraphDestroy(ng.graph);
+      return hip_fail(ctx, "hipGraphInstantiate", err);
+    }
+    fs->graphs.push_back(ng);
+    g = &fs->graphs.back();
+  }
+  err = hipGraphLaunch(g->exec, st);
+  if (err != hipSuccess) return hip_fail(ctx, "hipGraphLaunch", err);
+  return VGICP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                            const vgicp_opts *opts, double *H, double *b, double *e,
+                            int64_t *inliers, int32_t *corr) {
+  const char *who = "vgicp_linearize_factors";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  vgicp_opts o;
+  rc = read_opts(ctx, opts, &o, who);
+  if (rc) return rc;
+  if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
+    return fail(ctx, VGICP_EINVAL, "vgicp_linearize_factors: an output pointer is NULL");
+  return run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, corr, who);
+}
+
+int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                          const vgicp_opts *opts, double *e, int64_t *inliers) {
+  const char *who = "vgicp_evaluate_errors";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  vgicp_opts o;
+  rc = read_opts(ctx, opts, &o, who);
+  if (rc) return rc;
+  if (fs->n_factors > 0 && (!e || !inliers))
+    return fail(ctx, VGICP_EINVAL, "vgicp_evaluate_errors: an output pointer is NULL");
+  return run_factors(ctx, fs, kKindEvaluate, poses, o, nullptr, nullptr, e, inliers, nullptr, who);
+}
+
+int vgicp_overlap(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, int64_t *hits,
+                  double *overlap) {
+  const char *who = "vgicp_overlap";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  if (fs->n_factors == 0) return VGICP_OK;
+  if (!hits) return fail(ctx, VGICP_EINVAL, "vgicp_overlap: hits is NULL");
+  hipError_t err;
+  {
+    TimedLaunch t(ctx, VGICP_KERNEL_OVERLAP);
+    err = launch_overlap(fs, 0, fs->n_tiles, poses, ctx->stream);
+    t.done();
+  }
+  if (err == hipSuccess) {
+    TimedLaunch t(ctx, VGICP_KERNEL_REDUCE);
+    err = launch_reduce(fs, 0, fs->n_factors, poses, 2, nullptr, nullptr, nullptr, hits, overlap,
+                        ctx->stream);
+    t.done();
+  }
+  if (err != hipSuccess) return hip_fail(ctx, who, err);
+  return VGICP_OK;
+}
+
+}  // extern "C"

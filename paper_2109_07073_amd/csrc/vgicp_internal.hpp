@@ -1,0 +1,141 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/vgicp.h"
+
+namespace vgicp {
+
+// ---------------------------------------------------------------- voxel keys
+// Keys are packed as three biased 21-bit fields (kx, ky, kz) in the low 63
+// bits, kx highest, so numeric order of packed keys is lexicographic key
+// order.  All-ones marks an empty hash slot (bit 63 is never set by a key).
+constexpr int kKeyBits = 21;
+constexpr int32_t kKeyLimit = 1 << 20;  // keys lie in [-2^20, 2^20)
+constexpr float kKeyLimitF = 1048576.0f;
+constexpr uint64_t kEmptyKey = ~0ull;
+
+__host__ __device__ inline uint64_t pack_key(int32_t kx, int32_t ky, int32_t kz) {
+  return (uint64_t(uint32_t(kx + kKeyLimit)) << (2 * kKeyBits)) |
+         (uint64_t(uint32_t(ky + kKeyLimit)) << kKeyBits) | uint64_t(uint32_t(kz + kKeyLimit));
+}
+
+__host__ __device__ inline int32_t key_field(uint64_t key, int which) {
+  const int shift = (2 - which) * kKeyBits;
+  return int32_t((key >> shift) & ((1u << kKeyBits) - 1)) - kKeyLimit;
+}
+
+// Multiplicative (Fibonacci) hash: the top log2cap bits of key * 2^64/phi.
+__host__ __device__ inline uint32_t hash_slot(uint64_t key, uint32_t log2cap) {
+  return uint32_t((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+}
+
+// One open-addressing slot, 64 bytes so that a slot never straddles a
+// 128-byte line.  The first three 16-byte words carry everything a lookup and
+// the per-point math read: key, voxel mean and the 6 covariance entries.
+struct alignas(64) Slot {
+  uint64_t key;
+  float mean[3];
+  float cov[6];  // xx xy xz yy yz zz
+  int32_t ordinal;
+  int32_t count;
+  int32_t pad[3];
+};
+static_assert(sizeof(Slot) == 64, "slot layout");
+
+// ---------------------------------------------------------------- factors
+// Per-factor device descriptor (read with uniform loads by every tile).
+struct FactorDesc {
+  const float *xyz;   // [3][n]
+  const float *cov;   // [6][n]
+  const Slot *slots;  // target hash table
+  int64_t n;          // source points
+  int64_t corr_offset;
+  int32_t pose_i;
+  int32_t pose_j;
+  uint32_t log2cap;
+  float scale;        // fl32(1/r) of the target map
+  int32_t tile_begin; // first tile of this factor in the tile table
+  int32_t n_tiles;
+  int32_t pad[2];
+};
+
+// One tile: `count` source points of factor `factor` starting at `start`.
+struct Tile {
+  int32_t factor;
+  int32_t start;
+};
+
+// Per-tile partial sums written by the linearize/evaluate kernels.
+//   [0, 21)  upper triangle (row-major) of the 6x6 source-frame Hessian
+//   [21, 27) source-frame gradient
+//   27       cost
+//   28       inliers
+constexpr int kPartialStride = 32;
+constexpr int kNumSums = 28;
+
+// Error bits of the device error word.
+constexpr uint32_t kErrNonFinite = 1u;
+constexpr uint32_t kErrRange = 2u;
+
+}  // namespace vgicp
+
+// Objects behind the opaque handles of the C ABI.
+struct vgicp_context_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // Growable scratch for voxelization.
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  uint32_t *err_word = nullptr;       // device
+  uint32_t *host_pinned = nullptr;    // pinned host word pair for small readbacks
+  int cu_count = 0;
+  // Kernel timing (see vgicp_ctx_set_timing).
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[VGICP_KERNEL_KINDS];
+  double total_ms[VGICP_KERNEL_KINDS] = {0, 0, 0, 0};
+  int64_t launches[VGICP_KERNEL_KINDS] = {0, 0, 0, 0};
+};
+
+struct vgicp_voxelmap_s {
+  int device = 0;
+  int64_t n_voxels = 0;
+  int64_t capacity = 0;
+  uint32_t log2cap = 0;
+  float scale = 0.f;
+  double resolution = 0.0;
+  vgicp::Slot *slots = nullptr;
+};
+
+struct GraphEntry {
+  const double *poses;
+  double *H, *b, *e;
+  int64_t *inl;
+  int32_t *corr;
+  int accum;
+  int resid;
+  int kind;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct vgicp_factorset_s {
+  int device = 0;
+  int64_t n_factors = 0;
+  int64_t n_tiles = 0;
+  int64_t total_points = 0;
+  int32_t n_poses = 0;
+  int32_t tile_points = 0;
+  vgicp::FactorDesc *d_factors = nullptr;  // device
+  vgicp::Tile *d_tiles = nullptr;          // device
+  double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
+  std::vector<vgicp::FactorDesc> h_factors;
+  std::vector<GraphEntry> graphs;
+};

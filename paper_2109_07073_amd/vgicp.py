@@ -1,0 +1,413 @@
+"""ctypes binding of libvgicp.so (C ABI in include/vgicp.h).
+
+Argument marshalling only: every step of voxelization, linearization, cost
+evaluation and overlap runs in the library's HIP kernels.  Device memory and
+streams come from PyTorch-ROCm tensors; clouds are passed as SoA tensors
+xyz float32 (3, n) and cov float32 (6, n) on the GPU.
+
+The library must be built (python -m paper_2109_07073_amd.build); importing
+this module without it raises ImportError.  There is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvgicp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vgicp.h")
+
+OK, EINVAL, ENOMEM, ERANGE, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5
+ACC = {"f32": 0, "f32_comp": 1, "f64": 2}
+KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
+SCHED = {"batched": 0, "per_factor": 1}
+RESID = {"ff": 0, "f32": 1}
+
+
+class VgicpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class CCloud(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("cov", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class CFactor(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("tgt", ctypes.c_int32),
+                ("pose_i", ctypes.c_int32), ("pose_j", ctypes.c_int32)]
+
+
+class COpts(ctypes.Structure):
+    _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_P = ctypes.POINTER
+
+_PROTOS = {
+    "vgicp_version": (ctypes.c_int, []),
+    "vgicp_last_error": (ctypes.c_char_p, [_vp]),
+    "vgicp_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, _P(_vp)]),
+    "vgicp_ctx_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "vgicp_ctx_synchronize": (ctypes.c_int, [_vp]),
+    "vgicp_ctx_destroy": (ctypes.c_int, [_vp]),
+    "vgicp_ctx_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vgicp_ctx_read_timing": (ctypes.c_int, [_vp, ctypes.c_int, _P(_dbl), _P(_i64)]),
+    "vgicp_ctx_reset_timing": (ctypes.c_int, [_vp]),
+    "vgicp_voxelize": (ctypes.c_int, [_vp, _P(CCloud), _dbl, _P(_vp)]),
+    "vgicp_map_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_dbl)]),
+    "vgicp_map_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "vgicp_map_free": (ctypes.c_int, [_vp]),
+    "vgicp_factorset_create": (ctypes.c_int, [_vp, _P(CCloud), _i32, _P(_vp), _i32, _P(CFactor),
+                                              _i64, _i32, _i32, _P(_vp)]),
+    "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
+    "vgicp_factorset_destroy": (ctypes.c_int, [_vp]),
+    "vgicp_validate_factors": (ctypes.c_int, [_i32, _i32, _i32, _P(CFactor), _i64]),
+    "vgicp_linearize_factors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp]),
+    "vgicp_evaluate_errors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp]),
+    "vgicp_overlap": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+}
+
+
+def header_symbols() -> list[str]:
+    """Entry points declared in include/vgicp.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(vgicp_\w+)\s*\(", text, re.M)))
+
+
+def load_library() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2109_07073_amd.build`")
+    # PyTorch-ROCm ships its own libamdhip64.so.7 / libhsa-runtime64.so.1.  Loading
+    # torch first makes the dynamic loader bind libvgicp.so to that same runtime
+    # (matched by SONAME), so torch's device pointers and streams are valid in
+    # the library.  Two HIP runtimes in one process do not share devices.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _err(ctx_ptr) -> str:
+    m = _lib.vgicp_last_error(ctx_ptr)
+    return m.decode() if m else ""
+
+
+def _check(code: int, ctx_ptr=None):
+    if code != OK:
+        raise VgicpError(code, _err(ctx_ptr))
+
+
+def validate_factors(n_sources: int, n_maps: int, n_poses: int, factors) -> None:
+    """Host-only validation of a factor list (no device needed)."""
+    arr, n = _factor_array(factors)
+    _check(_lib.vgicp_validate_factors(n_sources, n_maps, n_poses, arr, n))
+
+
+def _factor_array(factors):
+    f = np.ascontiguousarray(np.asarray(factors, dtype=np.int32).reshape(-1, 4))
+    arr = (CFactor * max(1, f.shape[0]))()
+    for k, row in enumerate(f):
+        arr[k] = CFactor(*[int(v) for v in row])
+    return arr, int(f.shape[0])
+
+
+# ---------------------------------------------------------------- torch glue
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_tensor(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def cloud_to_device(xyz, cov, device="cuda"):
+    """(n,3)/(n,6) float32 host arrays -> SoA device tensors (3,n), (6,n)."""
+    torch = _torch()
+    x = torch.from_numpy(np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(-1, 3).T))
+    c = torch.from_numpy(np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6).T))
+    return x.to(device).contiguous(), c.to(device).contiguous()
+
+
+def clouds_to_device(clouds, device="cuda"):
+    """Upload many (xyz (n,3), cov (n,6)) host clouds into one device buffer and
+    return SoA views (3,n)/(6,n) per cloud, plus the buffer."""
+    torch = _torch()
+    sizes = [int(np.asarray(x).reshape(-1, 3).shape[0]) for x, _ in clouds]
+    total = int(sum(sizes))
+    host = np.empty(9 * total, dtype=np.float32)
+    views, off = [], 0
+    for (x, c), n in zip(clouds, sizes):
+        host[off:off + 3 * n] = np.asarray(x, np.float32).reshape(-1, 3).T.reshape(-1)
+        host[off + 3 * n:off + 9 * n] = np.asarray(c, np.float32).reshape(-1, 6).T.reshape(-1)
+        views.append((off, n))
+        off += 9 * n
+    buf = torch.from_numpy(host).to(device)
+    out = [(buf[o:o + 3 * n].view(3, n), buf[o + 3 * n:o + 9 * n].view(6, n)) for o, n in views]
+    return out, buf
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(_lib.vgicp_ctx_create(self.device, _stream_handle(self.stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(_lib.vgicp_ctx_set_stream(self._h, _stream_handle(stream)), self._h)
+
+    def synchronize(self):
+        _check(_lib.vgicp_ctx_synchronize(self._h), self._h)
+
+    def set_timing(self, enable: bool = True):
+        """Bracket each kernel launch (outside graphs) with HIP events."""
+        _check(_lib.vgicp_ctx_set_timing(self._h, int(bool(enable))), self._h)
+
+    def reset_timing(self):
+        _check(_lib.vgicp_ctx_reset_timing(self._h), self._h)
+
+    def read_timing(self, kernel: str):
+        """(total milliseconds, launches) of a kernel kind since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.vgicp_ctx_read_timing(self._h, KERNELS[kernel], ctypes.byref(ms),
+                                          ctypes.byref(n)), self._h)
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.vgicp_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VoxelMap:
+    def __init__(self, ctx: Context, handle):
+        self._ctx = ctx
+        self._h = handle
+        nv, cap, nb, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(_lib.vgicp_map_info(handle, ctypes.byref(nv), ctypes.byref(cap), ctypes.byref(nb),
+                                   ctypes.byref(r)))
+        self.n_voxels, self.capacity = nv.value, cap.value
+        self.device_bytes, self.resolution = nb.value, r.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """Voxels in ordinal order: keys int32 (V,3), mean (V,3), cov (V,6), count (V,)."""
+        torch = _torch()
+        V = self.n_voxels
+        dev = f"cuda:{self._ctx.device}"
+        keys = torch.empty((V, 3), dtype=torch.int32, device=dev)
+        mean = torch.empty((V, 3), dtype=torch.float32, device=dev)
+        cov = torch.empty((V, 6), dtype=torch.float32, device=dev)
+        cnt = torch.empty((V,), dtype=torch.int32, device=dev)
+        _check(_lib.vgicp_map_export(self._ctx.handle, self._h, keys.data_ptr(), mean.data_ptr(),
+                                     cov.data_ptr(), cnt.data_ptr()), self._ctx.handle)
+        return {"keys": keys, "mean": mean, "cov": cov, "count": cnt}
+
+    def free(self):
+        if getattr(self, "_h", None):
+            _lib.vgicp_map_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def voxelize(ctx: Context, xyz, cov, resolution: float) -> VoxelMap:
+    """Voxel map of a device cloud (xyz (3,n), cov (6,n) float32 tensors)."""
+    torch = _torch()
+    n = int(xyz.shape[1]) if xyz.dim() == 2 else -1
+    _dev_tensor(xyz, torch.float32, (3, n), "xyz")
+    _dev_tensor(cov, torch.float32, (6, n), "cov")
+    c = CCloud(xyz.data_ptr() if n else None, cov.data_ptr() if n else None, n)
+    h = ctypes.c_void_p()
+    _check(_lib.vgicp_voxelize(ctx.handle, ctypes.byref(c), float(resolution), ctypes.byref(h)),
+           ctx.handle)
+    return VoxelMap(ctx, h)
+
+
+class FactorSet:
+    """Factor list bound to its source clouds and target maps.
+
+    sources: list of (xyz (3,n), cov (6,n)) device tensors (kept alive here);
+    maps: list of VoxelMap; factors: (F, 4) rows (src, tgt, pose_i, pose_j)."""
+
+    def __init__(self, ctx: Context, sources, maps, factors, n_poses: int, tile_points: int = 0):
+        torch = _torch()
+        self._ctx = ctx
+        self._sources = list(sources)
+        self._maps = list(maps)
+        cl = (CCloud * max(1, len(self._sources)))()
+        for k, (x, c) in enumerate(self._sources):
+            n = int(x.shape[1])
+            _dev_tensor(x, torch.float32, (3, n), f"sources[{k}].xyz")
+            _dev_tensor(c, torch.float32, (6, n), f"sources[{k}].cov")
+            cl[k] = CCloud(x.data_ptr() if n else None, c.data_ptr() if n else None, n)
+        mp = (ctypes.c_void_p * max(1, len(self._maps)))()
+        for k, m in enumerate(self._maps):
+            mp[k] = m.handle
+        arr, nf = _factor_array(factors)
+        self.factors = np.asarray(factors, dtype=np.int32).reshape(-1, 4).copy()
+        self.n_poses = int(n_poses)
+        h = ctypes.c_void_p()
+        _check(_lib.vgicp_factorset_create(ctx.handle, cl, len(self._sources), mp, len(self._maps),
+                                           arr, nf, self.n_poses, int(tile_points), ctypes.byref(h)),
+               ctx.handle)
+        self._h = h
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.vgicp_factorset_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        self.n_factors, self.n_tiles, self.total_points = a.value, b.value, c.value
+        self.source_sizes = np.array([int(self._sources[s][0].shape[1]) for s in self.factors[:, 0]],
+                                     dtype=np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.vgicp_factorset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "ff") -> COpts:
+    if accum not in ACC:
+        raise ValueError(f"accum must be one of {sorted(ACC)}")
+    if schedule not in SCHED:
+        raise ValueError(f"schedule must be one of {sorted(SCHED)}")
+    if resid not in RESID:
+        raise ValueError(f"resid must be one of {sorted(RESID)}")
+    return COpts(ACC[accum], SCHED[schedule], int(bool(use_graph)), RESID[resid])
+
+
+def _check_poses(fs: FactorSet, poses):
+    torch = _torch()
+    return _dev_tensor(poses, torch.float64, (fs.n_poses, 12), "poses")
+
+
+def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
+                      schedule: str = "batched", use_graph: bool = False,
+                      with_corr: bool = False, out=None, resid: str = "ff"):
+    """Hessian factors of every factor at `poses` (float64 (P, 12) device).
+    Returns dict of device tensors H (F,12,12), b (F,12), e (F,), inliers (F,)
+    and corr (total_points,) when asked.  `out` may supply the same dict of
+    preallocated tensors (needed for graph replay with stable pointers)."""
+    torch = _torch()
+    _check_poses(fs, poses)
+    dev = f"cuda:{ctx.device}"
+    F = fs.n_factors
+    if out is None:
+        out = {"H": torch.empty((F, 12, 12), dtype=torch.float64, device=dev),
+               "b": torch.empty((F, 12), dtype=torch.float64, device=dev),
+               "e": torch.empty((F,), dtype=torch.float64, device=dev),
+               "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
+        if with_corr:
+            out["corr"] = torch.empty((fs.total_points,), dtype=torch.int32, device=dev)
+    _dev_tensor(out["H"], torch.float64, (F, 12, 12), "H")
+    _dev_tensor(out["b"], torch.float64, (F, 12), "b")
+    _dev_tensor(out["e"], torch.float64, (F,), "e")
+    _dev_tensor(out["inliers"], torch.int64, (F,), "inliers")
+    corr = out.get("corr")
+    if corr is not None:
+        _dev_tensor(corr, torch.int32, (fs.total_points,), "corr")
+    o = _opts(accum, schedule, use_graph, resid)
+    _check(_lib.vgicp_linearize_factors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
+                                        out["H"].data_ptr(), out["b"].data_ptr(),
+                                        out["e"].data_ptr(), out["inliers"].data_ptr(),
+                                        corr.data_ptr() if corr is not None else None),
+           ctx.handle)
+    return out
+
+
+def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
+                    schedule: str = "batched", use_graph: bool = False, out=None,
+                    resid: str = "ff"):
+    """Matching cost e (F,) and inliers (F,) without Jacobians."""
+    torch = _torch()
+    _check_poses(fs, poses)
+    dev = f"cuda:{ctx.device}"
+    F = fs.n_factors
+    if out is None:
+        out = {"e": torch.empty((F,), dtype=torch.float64, device=dev),
+               "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
+    o = _opts(accum, schedule, use_graph, resid)
+    _check(_lib.vgicp_evaluate_errors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
+                                      out["e"].data_ptr(), out["inliers"].data_ptr()), ctx.handle)
+    return out
+
+
+def overlap(ctx: Context, fs: FactorSet, poses, out=None):
+    """Overlap hit counts (F,) int64 and rates (F,) float64 (Eqs. (7)-(8))."""
+    torch = _torch()
+    _check_poses(fs, poses)
+    dev = f"cuda:{ctx.device}"
+    F = fs.n_factors
+    if out is None:
+        out = {"hits": torch.empty((F,), dtype=torch.int64, device=dev),
+               "overlap": torch.empty((F,), dtype=torch.float64, device=dev)}
+    _check(_lib.vgicp_overlap(ctx.handle, fs.handle, poses.data_ptr(), out["hits"].data_ptr(),
+                              out["overlap"].data_ptr()), ctx.handle)
+    return out

@@ -1,0 +1,94 @@
+"""The C ABI library loads, exports every entry point of include/vgicp.h and
+rejects bad arguments on the host before touching a device (CPU only)."""
+
+import ctypes
+import subprocess
+
+import pytest
+
+vg = pytest.importorskip("paper_2109_07073_amd.vgicp", reason="libvgicp.so not built")
+
+
+def test_every_header_symbol_is_exported():
+    names = vg.header_symbols()
+    assert len(names) >= 17
+    out = subprocess.run(["nm", "-D", "--defined-only", vg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = vg.lib()
+    for n in names:
+        assert getattr(lib, n) is not None
+    assert set(vg._PROTOS) == set(names)
+
+
+def test_version_and_last_error_never_null():
+    lib = vg.lib()
+    assert lib.vgicp_version() >= 100
+    assert lib.vgicp_last_error(None) is not None
+
+
+@pytest.mark.parametrize("row,what", [
+    ((-1, 0, 0, 1), "src"), ((2, 0, 0, 1), "src"),
+    ((0, -1, 0, 1), "tgt"), ((0, 3, 0, 1), "tgt"),
+    ((0, 0, -1, 1), "pose_i"), ((0, 0, 4, 1), "pose_i"),
+    ((0, 0, 0, 4), "pose_j"), ((0, 0, 0, -7), "pose_j"),
+])
+def test_validate_factors_rejects_out_of_range(row, what):
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.validate_factors(2, 3, 4, [(0, 0, 0, 1), row])
+    assert ex.value.code == vg.EINVAL
+    assert "factor 1" in str(ex.value) and what in str(ex.value)
+
+
+def test_validate_factors_accepts_good_and_empty_lists():
+    vg.validate_factors(2, 3, 4, [(1, 2, 3, 0), (0, 0, 0, 0)])
+    vg.validate_factors(0, 0, 0, [])
+
+
+def test_validate_factors_null_and_negative_counts():
+    lib = vg.lib()
+    assert lib.vgicp_validate_factors(1, 1, 1, None, 3) == vg.EINVAL
+    assert lib.vgicp_validate_factors(-1, 1, 1, None, 0) == vg.EINVAL
+    assert lib.vgicp_validate_factors(1, 1, 1, None, -2) == vg.EINVAL
+
+
+def test_null_handles_are_rejected_without_a_device():
+    lib = vg.lib()
+    h = ctypes.c_void_p()
+    assert lib.vgicp_ctx_create(0, None, None) == vg.EINVAL
+    assert lib.vgicp_voxelize(None, None, 0.5, ctypes.byref(h)) == vg.EINVAL
+    assert lib.vgicp_map_info(None, None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_map_export(None, None, None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_factorset_create(None, None, 0, None, 0, None, 0, 0, 0, ctypes.byref(h)) == vg.EINVAL
+    assert lib.vgicp_factorset_info(None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_linearize_factors(None, None, None, None, None, None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_evaluate_errors(None, None, None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_overlap(None, None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_ctx_synchronize(None) == vg.EINVAL
+    assert lib.vgicp_ctx_set_stream(None, None) == vg.EINVAL
+    # freeing NULL handles is allowed
+    assert lib.vgicp_map_free(None) == vg.OK
+    assert lib.vgicp_factorset_destroy(None) == vg.OK
+    assert lib.vgicp_ctx_destroy(None) == vg.OK
+    assert b"NULL" in lib.vgicp_last_error(None)
+
+
+def test_context_creation_without_gpu_fails_cleanly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = vg.lib()
+    h = ctypes.c_void_p()
+    rc = lib.vgicp_ctx_create(0, None, ctypes.byref(h))
+    assert rc in (vg.EHIP, vg.EINVAL) and not h.value
+
+
+def test_library_shares_the_hip_runtime_of_torch():
+    """libvgicp.so must bind to the HIP runtime PyTorch already loaded; two HIP
+    runtimes in one process do not share devices or pointers."""
+    import os
+    with open(f"/proc/{os.getpid()}/maps") as fh:
+        libs = {line.split()[-1] for line in fh if "libamdhip64" in line}
+    assert len(libs) == 1, libs

@@ -1,0 +1,289 @@
+"""Parity of the HIP path with the FP64 oracle (GPU).
+
+Integer outputs (voxel keys and counts, correspondences, inliers, overlap
+hits) must be bit-exact; the FP32 voxel payload is compared bit-exactly too
+(both sides sum in FP64 in point order and round once).  H, b and e must lie
+within a relative 1e-5 (Frobenius norm per factor) of the FP64 oracle for
+every accumulation variant."""
+
+import numpy as np
+import pytest
+
+from synth import make_scan_workload, make_single_factor, make_tiny_workload, pose_rows
+from tests.gpu_helpers import (TOL, GpuWorkload, assert_linearize_parity,
+                               oracle_results)
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ACCS = ["f32", "f32_comp", "f64"]
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2109_07073_amd import vgicp
+    return vgicp
+
+
+@pytest.fixture(scope="module")
+def ctx(vg):
+    return vg.Context(0)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return make_single_factor()
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    sizes = [0, 1, 255, 256, 257, 4095, 4096, 4097, 9000, 513, 3]
+    tgts = [50, 700, 1, 2000, 900, 3000, 0, 2500, 4000, 800, 10]
+    return make_tiny_workload(seed=21, n_src=sizes, n_tgt=tgts, resolution=0.5,
+                              n_factors=len(sizes), half=6.0, height=3.0)
+
+
+@pytest.fixture(scope="module")
+def scans():
+    return make_scan_workload(cfg=2, n_frames=6, n_factors=8, n_target=20000, workers=4)
+
+
+@pytest.fixture(scope="module")
+def scans40():
+    """40 factors of the 100-frame, 500-factor scan workload (20,000 points each)."""
+    w = make_scan_workload(cfg=2, n_frames=100, n_factors=500, n_target=20000, workers=8)
+    w.factors = w.factors[::12][:40].copy()
+    return w
+
+
+# ------------------------------------------------------------------ voxelize
+
+def _export_np(m):
+    return {k: v.cpu().numpy() for k, v in m.export().items()}
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 0.3, 2.0])
+def test_voxelize_bitexact(vg, ctx, ragged, r):
+    for k in (1, 5, 8, 9):
+        xyz, cov = ragged.targets[k]
+        dx, dc = vg.cloud_to_device(xyz, cov)
+        m = vg.voxelize(ctx, dx, dc, r)
+        ref, _ = oracle.voxelize(xyz, cov, r)
+        assert m.n_voxels == ref.n_voxels
+        assert m.capacity >= 2 * m.n_voxels and (m.capacity & (m.capacity - 1)) == 0
+        got = _export_np(m)
+        assert np.array_equal(got["keys"], ref.keys.astype(np.int32))
+        assert np.array_equal(got["count"], ref.count.astype(np.int32))
+        assert np.array_equal(got["mean"].view(np.uint32), ref.mean.view(np.uint32))
+        assert np.array_equal(got["cov"].view(np.uint32), ref.cov.view(np.uint32))
+
+
+def test_voxelize_scan_frames_bitexact(vg, ctx, scans):
+    for xyz, cov in scans.targets[:3]:
+        m = vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), scans.resolution)
+        ref, _ = oracle.voxelize(xyz, cov, scans.resolution)
+        got = _export_np(m)
+        assert np.array_equal(got["keys"], ref.keys.astype(np.int32))
+        assert np.array_equal(got["count"], ref.count.astype(np.int32))
+        assert np.array_equal(got["mean"].view(np.uint32), ref.mean.view(np.uint32))
+        assert np.array_equal(got["cov"].view(np.uint32), ref.cov.view(np.uint32))
+
+
+def test_voxelize_empty_and_single_point(vg, ctx):
+    import torch
+    z3 = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
+    z6 = torch.zeros((6, 0), dtype=torch.float32, device="cuda")
+    m = vg.voxelize(ctx, z3, z6, 0.5)
+    assert m.n_voxels == 0
+    xyz = np.array([[0.25, -0.75, 3.5]], np.float32)
+    cov = np.array([[1, 0, 0, 1, 0, 1]], np.float32)
+    m = vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.5)
+    got = _export_np(m)
+    assert m.n_voxels == 1 and got["keys"].tolist() == [[0, -2, 7]]
+    assert np.array_equal(got["mean"], xyz) and got["count"].tolist() == [1]
+
+
+def test_voxelize_rejects_nonfinite_and_out_of_range(vg, ctx):
+    xyz = np.zeros((300, 3), np.float32)
+    cov = np.tile(np.array([1, 0, 0, 1, 0, 1], np.float32), (300, 1))
+    bad = xyz.copy()
+    bad[123, 1] = np.nan
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.voxelize(ctx, *vg.cloud_to_device(bad, cov), 0.5)
+    assert ex.value.code == vg.ENONFINITE
+    bad = xyz.copy()
+    bad[7, 0] = 6e5        # key 1.2e6 >= 2^20 at r = 0.5
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.voxelize(ctx, *vg.cloud_to_device(bad, cov), 0.5)
+    assert ex.value.code == vg.ERANGE
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.0)
+    assert ex.value.code == vg.EINVAL
+    # the context stays usable
+    m = vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.5)
+    assert m.n_voxels == 1
+
+
+# ------------------------------------------------------ correspondences, H/b/e
+
+@pytest.mark.parametrize("accum", ACCS)
+def test_cfg1_single_factor(vg, ctx, cfg1, accum):
+    g = GpuWorkload(vg, ctx, cfg1)
+    got = g.linearize(accum=accum, with_corr=True)
+    _, ref = oracle_results(cfg1)
+    assert np.array_equal(got["corr"], ref["corr"][0].astype(np.int32))
+    worst = assert_linearize_parity(got, ref)
+    print(f"cfg1 {accum}: worst relative error {worst}")
+    H = got["H"][0]
+    assert np.array_equal(H, H.T)
+
+
+@pytest.mark.parametrize("tile", [0, 256, 1024])
+@pytest.mark.parametrize("accum", ACCS)
+def test_ragged_factors(vg, ctx, ragged, accum, tile):
+    g = GpuWorkload(vg, ctx, ragged, tile_points=tile)
+    got = g.linearize(accum=accum, with_corr=True)
+    _, ref = oracle_results(ragged)
+    assert np.array_equal(got["corr"], np.concatenate(ref["corr"]).astype(np.int32))
+    assert_linearize_parity(got, ref)
+    assert got["inliers"][0] == 0 and got["inliers"][6] == 0   # empty source / empty map
+
+
+@pytest.mark.parametrize("accum", ACCS)
+def test_scan_factors(vg, ctx, scans, accum):
+    g = GpuWorkload(vg, ctx, scans)
+    got = g.linearize(accum=accum, with_corr=True)
+    _, ref = oracle_results(scans)
+    assert np.array_equal(got["corr"], np.concatenate(ref["corr"]).astype(np.int32))
+    worst = assert_linearize_parity(got, ref)
+    print(f"scans {accum}: worst relative error {worst}")
+
+
+@pytest.fixture(scope="module")
+def scans40_ref(scans40):
+    return oracle_results(scans40)[1]
+
+
+@pytest.mark.parametrize("accum", ACCS)
+def test_scan_factors_40_double_float_residual(vg, ctx, scans40, scans40_ref, accum):
+    g = GpuWorkload(vg, ctx, scans40)
+    got = g.linearize(accum=accum, resid="ff")
+    worst = assert_linearize_parity(got, scans40_ref)
+    print(f"40 scan factors {accum}/ff: worst relative error {worst}")
+
+
+def test_plain_fp32_residual_is_the_looser_variant(vg, ctx, scans40, scans40_ref):
+    """The plain FP32 residual keeps bit-exact counts; its b error is bounded
+    by the transform's rounding (|mu| up to 80 m), checked at 1e-4."""
+    g = GpuWorkload(vg, ctx, scans40)
+    got = g.linearize(accum="f64", resid="f32")
+    worst = assert_linearize_parity(got, scans40_ref, tol=1e-4)
+    print(f"40 scan factors f64/f32-residual: worst relative error {worst}")
+    ff = g.linearize(accum="f64", resid="ff")
+    assert np.array_equal(ff["inliers"], got["inliers"])
+
+
+def test_schedules_graph_and_repeats_are_bitwise_identical(vg, ctx, ragged):
+    import torch
+    g = GpuWorkload(vg, ctx, ragged)
+    base = g.linearize()
+    per = g.linearize(schedule="per_factor")
+    again = g.linearize()
+    for k in ("H", "b", "e", "inliers"):
+        assert np.array_equal(base[k], per[k]), k
+        assert np.array_equal(base[k], again[k]), k
+    # graph replay on a side stream, with eager work between replays
+    side = torch.cuda.Stream()
+    gctx = vg.Context(0, stream=side)
+    F = g.fs.n_factors
+    out = {"H": torch.empty((F, 12, 12), dtype=torch.float64, device="cuda"),
+           "b": torch.empty((F, 12), dtype=torch.float64, device="cuda"),
+           "e": torch.empty((F,), dtype=torch.float64, device="cuda"),
+           "inliers": torch.empty((F,), dtype=torch.int64, device="cuda")}
+    fs2 = vg.FactorSet(gctx, g.src, g.maps, g.factors, g.poses.shape[0])
+    for rep in range(4):
+        for v in out.values():
+            v.zero_()
+        torch.cuda.synchronize()
+        vg.linearize_factors(gctx, fs2, g.poses, use_graph=True, out=out)
+        gctx.synchronize()
+        for k in ("H", "b", "e", "inliers"):
+            assert np.array_equal(out[k].cpu().numpy(), base[k]), (rep, k)
+        _ = g.linearize(accum="f64")        # unrelated eager work between replays
+
+
+def test_results_do_not_depend_on_the_batch(vg, ctx, ragged):
+    g = GpuWorkload(vg, ctx, ragged)
+    full = g.linearize()
+    for f in (3, 8, 9):
+        alone = GpuWorkload(vg, ctx, ragged, factors=ragged.factors[f:f + 1])
+        one = alone.linearize()
+        for k in ("H", "b", "e", "inliers"):
+            assert np.array_equal(one[k][0], full[k][f]), (f, k)
+
+
+@pytest.mark.parametrize("accum", ACCS)
+def test_evaluate_matches_linearize(vg, ctx, scans, accum):
+    g = GpuWorkload(vg, ctx, scans)
+    lin = g.linearize(accum=accum)
+    ev = g.evaluate(accum=accum)
+    assert np.array_equal(ev["inliers"], lin["inliers"])
+    assert np.array_equal(ev["e"], lin["e"])
+    per = g.evaluate(accum=accum, schedule="per_factor")
+    assert np.array_equal(per["e"], lin["e"])
+
+
+# ------------------------------------------------------------------ overlap
+
+def test_overlap_bitexact(vg, ctx, scans, ragged):
+    for w in (scans, ragged):
+        g = GpuWorkload(vg, ctx, w)
+        got = g.overlap()
+        maps = oracle.build_maps(w.targets, w.resolution)
+        hits, ov = oracle.overlap_workload(w.sources, maps, w.poses, w.factors)
+        assert np.array_equal(got["hits"], hits)
+        assert np.array_equal(got["overlap"], ov)
+        lin = g.linearize()
+        assert np.array_equal(lin["inliers"], got["hits"])
+
+
+def test_self_overlap_is_one_and_far_is_zero(vg, ctx, scans):
+    import torch
+    from tests.oracle_pins import hom, rows
+    xyz, cov = scans.targets[0]
+    d = vg.cloud_to_device(xyz, cov)
+    m = vg.voxelize(ctx, *d, scans.resolution)
+    far = hom(scans.poses[0])
+    far[:3, 3] += [1e4, 0, 0]
+    poses = torch.from_numpy(np.stack([scans.poses[0], rows(far)])).to("cuda")
+    fs = vg.FactorSet(ctx, [d], [m], [(0, 0, 0, 0), (0, 0, 0, 1)], 2)
+    out = vg.overlap(ctx, fs, poses)
+    ctx.synchronize()
+    assert out["hits"].tolist() == [xyz.shape[0], 0]
+    assert out["overlap"].tolist() == [1.0, 0.0]
+
+
+def test_empty_factor_set_is_a_no_op(vg, ctx, cfg1):
+    import torch
+    g = GpuWorkload(vg, ctx, cfg1)
+    fs = vg.FactorSet(ctx, g.src, g.maps, np.zeros((0, 4), np.int32), 2)
+    out = vg.linearize_factors(ctx, fs, g.poses)
+    assert out["H"].shape == (0, 12, 12)
+    ctx.synchronize()
+
+
+def test_bad_arguments_raise(vg, ctx, cfg1):
+    import torch
+    g = GpuWorkload(vg, ctx, cfg1)
+    with pytest.raises(vg.VgicpError):
+        vg.FactorSet(ctx, g.src, g.maps, [(0, 1, 0, 1)], 2)
+    with pytest.raises(vg.VgicpError):
+        vg.FactorSet(ctx, g.src, g.maps, [(0, 0, 0, 1)], 2, tile_points=100)
+    with pytest.raises(ValueError):
+        vg.linearize_factors(ctx, g.fs, g.poses.float())
+    with pytest.raises(ValueError):
+        vg.linearize_factors(ctx, g.fs, g.poses[:1])
+    with pytest.raises(vg.VgicpError):       # graph replay needs a side stream
+        vg.linearize_factors(ctx, g.fs, g.poses, use_graph=True)
