@@ -63,29 +63,16 @@ __device__ __forceinline__ void lookup_transform(const float R[9], const float t
 
 // Global-address-space views: loads through them compile to global_load_*
 // (flat loads would also tie up the LDS counter).
-typedef const float __attribute__((address_space(1))) gfloat;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef const float __attribute__((address_space(1))) gfloat;
 typedef const f32x4 __attribute__((address_space(1))) gfloat4;
 typedef const uint64_t __attribute__((address_space(1))) gu64;
 
-// One source point: position and covariance (xx xy xz yy yz zz).
-struct SrcPoint {
-  float x, y, z;
-  float c[6];
-};
-
-template <bool COV>
-__device__ __forceinline__ void load_point(const float *px, const float *pc, int64_t n, int64_t i,
-                                           SrcPoint &p) {
-  gfloat *gx = (gfloat *)px;
-  p.x = __builtin_nontemporal_load(gx + i);
-  p.y = __builtin_nontemporal_load(gx + n + i);
-  p.z = __builtin_nontemporal_load(gx + 2 * n + i);
-  if constexpr (COV) {
-    gfloat *gc = (gfloat *)pc;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) p.c[a] = __builtin_nontemporal_load(gc + a * n + i);
-  }
+__device__ __forceinline__ void load_xyz(const float *px, int64_t n, int64_t i, float p[3]) {
+  gfloat *g = (gfloat *)px;
+  p[0] = __builtin_nontemporal_load(g + i);
+  p[1] = __builtin_nontemporal_load(g + n + i);
+  p[2] = __builtin_nontemporal_load(g + 2 * n + i);
 }
 
 // Packed key and home slot of the voxel holding q (ok = false when a key
@@ -106,56 +93,27 @@ __device__ __forceinline__ VoxelKey voxel_key(const float q[3], float s, uint32_
   return r;
 }
 
-// The first 48 bytes of a slot: key (w0.xy), mean (w0.zw, w1.x), covariance
-// (w1.yzw, w2.xyz), ordinal (w2.w).
-struct SlotData {
-  f32x4 w0, w1, w2;
-};
-
-__device__ __forceinline__ void load_slot(const Slot *slots, uint32_t h, SlotData &d) {
-  gfloat4 *p = (gfloat4 *)(slots + h);
-  d.w0 = p[0];
-  d.w1 = p[1];
-  d.w2 = p[2];
-}
-
-__device__ __forceinline__ uint64_t slot_key(const SlotData &d) {
-  return (uint64_t(__float_as_uint(d.w0.y)) << 32) | uint64_t(__float_as_uint(d.w0.x));
-}
-
-// Linear probing from a speculatively loaded home slot: true when `key` is
-// found (d then holds its slot), false at the first empty slot.  At most
-// `capacity` slots are visited.
-__device__ __forceinline__ bool resolve_slot(const Slot *slots, uint32_t log2cap, uint64_t key,
-                                             uint32_t h, SlotData &d) {
-  uint64_t k = slot_key(d);
-  if (k != key && k != kEmptyKey) {
-    // Rare: keep probing.  The full wait at the end leaves no slot load in
-    // flight on this path, so the common path's waits stay exact (they only
-    // need the home slot, not the prefetched next point).
-    const uint32_t mask = (1u << log2cap) - 1u;
-    for (uint32_t p = 0; p < mask; ++p) {
-      h = (h + 1u) & mask;
-      load_slot(slots, h, d);
-      k = slot_key(d);
-      if (k == key || k == kEmptyKey) break;
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-  }
-  return k == key;
-}
-
-// Key-only probing for the overlap count.
-__device__ __forceinline__ bool contains_key(const Slot *slots, uint32_t log2cap, uint64_t key,
-                                             uint32_t h) {
+// Finish a linear probe whose home slot h held k0: the slot of `key` or -1
+// at the first empty slot.  At most `capacity` slots are visited.
+__device__ __forceinline__ int find_slot(const uint64_t *keys, uint32_t log2cap, uint64_t key,
+                                         uint32_t h, uint64_t k0) {
+  if (k0 == key) return int(h);
+  if (k0 == kEmptyKey) return -1;
+  // Rare: keep probing.  The full wait at the end leaves no load of this path
+  // in flight, so the common path's waits stay exact.
+  int r = -1;
   const uint32_t mask = (1u << log2cap) - 1u;
-  for (uint32_t p = 0; p <= mask; ++p) {
-    const uint64_t k = *(gu64 *)(&slots[h].key);
-    if (k == key) return true;
-    if (k == kEmptyKey) return false;
+  for (uint32_t p = 0; p < mask; ++p) {
     h = (h + 1u) & mask;
+    const uint64_t k = *(gu64 *)(keys + h);
+    if (k == key) {
+      r = int(h);
+      break;
+    }
+    if (k == kEmptyKey) break;
   }
-  return false;
+  __builtin_amdgcn_s_waitcnt(0);
+  return r;
 }
 
 // ---------------------------------------------------------------- sums
@@ -271,7 +229,7 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &err) 
 // is unchanged.
 __device__ __forceinline__ void transform_error(const float R[9], const float Rlo[9],
                                                 const float t[3], const float tlo[3], float x,
-                                                float y, float z, float qerr[3]) {
+                                                float y, float z, float q[3], float qerr[3]) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -285,6 +243,7 @@ __device__ __forceinline__ void transform_error(const float R[9], const float Rl
     two_sum(s2, t[r], s3, d3);
     const float lo = __builtin_fmaf(Rlo[3 * r], x, __builtin_fmaf(Rlo[3 * r + 1], y,
                                                                   Rlo[3 * r + 2] * z));
+    q[r] = s3;
     qerr[r] = ((e0 + e1) + (e2 + d1)) + ((d2 + d3) + (tlo[r] + lo));
   }
 }
@@ -347,66 +306,73 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const float R[9],
                                                    float my, float mz, const float c[6],
                                                    const float q[3], const float qerr[3],
                                                    const float m[3], const float S[6]) {
+  // Contraction is off and every fused multiply-add is explicit, so the cost
+  // comes out bit-identical in the linearization and the cost-only kernels.
+#pragma clang fp contract(off)
+#define FMA __builtin_fmaf
   // residual e_k = mu' - T mu (target frame), rotated into the source frame;
   // m - q is exact when the two are within a factor of two, and qerr carries
   // the transform's rounding error (zero for the plain FP32 residual)
   const float e0 = (m[0] - q[0]) - qerr[0];
   const float e1 = (m[1] - q[1]) - qerr[1];
   const float e2 = (m[2] - q[2]) - qerr[2];
-  const float r0 = R[0] * e0 + R[3] * e1 + R[6] * e2;
-  const float r1 = R[1] * e0 + R[4] * e1 + R[7] * e2;
-  const float r2 = R[2] * e0 + R[5] * e1 + R[8] * e2;
+  const float r0 = FMA(R[6], e2, FMA(R[3], e1, R[0] * e0));
+  const float r1 = FMA(R[7], e2, FMA(R[4], e1, R[1] * e0));
+  const float r2 = FMA(R[8], e2, FMA(R[5], e1, R[2] * e0));
   // W = C' R, then F' = R^T W + C (symmetric, upper triangle)
-  const float W00 = S[0] * R[0] + S[1] * R[3] + S[2] * R[6];
-  const float W01 = S[0] * R[1] + S[1] * R[4] + S[2] * R[7];
-  const float W02 = S[0] * R[2] + S[1] * R[5] + S[2] * R[8];
-  const float W10 = S[1] * R[0] + S[3] * R[3] + S[4] * R[6];
-  const float W11 = S[1] * R[1] + S[3] * R[4] + S[4] * R[7];
-  const float W12 = S[1] * R[2] + S[3] * R[5] + S[4] * R[8];
-  const float W20 = S[2] * R[0] + S[4] * R[3] + S[5] * R[6];
-  const float W21 = S[2] * R[1] + S[4] * R[4] + S[5] * R[7];
-  const float W22 = S[2] * R[2] + S[4] * R[5] + S[5] * R[8];
-  const float f00 = (R[0] * W00 + R[3] * W10 + R[6] * W20) + c[0];
-  const float f01 = (R[0] * W01 + R[3] * W11 + R[6] * W21) + c[1];
-  const float f02 = (R[0] * W02 + R[3] * W12 + R[6] * W22) + c[2];
-  const float f11 = (R[1] * W01 + R[4] * W11 + R[7] * W21) + c[3];
-  const float f12 = (R[1] * W02 + R[4] * W12 + R[7] * W22) + c[4];
-  const float f22 = (R[2] * W02 + R[5] * W12 + R[8] * W22) + c[5];
+  const float W00 = FMA(S[2], R[6], FMA(S[1], R[3], S[0] * R[0]));
+  const float W01 = FMA(S[2], R[7], FMA(S[1], R[4], S[0] * R[1]));
+  const float W02 = FMA(S[2], R[8], FMA(S[1], R[5], S[0] * R[2]));
+  const float W10 = FMA(S[4], R[6], FMA(S[3], R[3], S[1] * R[0]));
+  const float W11 = FMA(S[4], R[7], FMA(S[3], R[4], S[1] * R[1]));
+  const float W12 = FMA(S[4], R[8], FMA(S[3], R[5], S[1] * R[2]));
+  const float W20 = FMA(S[5], R[6], FMA(S[4], R[3], S[2] * R[0]));
+  const float W21 = FMA(S[5], R[7], FMA(S[4], R[4], S[2] * R[1]));
+  const float W22 = FMA(S[5], R[8], FMA(S[4], R[5], S[2] * R[2]));
+  const float f00 = FMA(R[6], W20, FMA(R[3], W10, FMA(R[0], W00, c[0])));
+  const float f01 = FMA(R[6], W21, FMA(R[3], W11, FMA(R[0], W01, c[1])));
+  const float f02 = FMA(R[6], W22, FMA(R[3], W12, FMA(R[0], W02, c[2])));
+  const float f11 = FMA(R[7], W21, FMA(R[4], W11, FMA(R[1], W01, c[3])));
+  const float f12 = FMA(R[7], W22, FMA(R[4], W12, FMA(R[1], W02, c[4])));
+  const float f22 = FMA(R[8], W22, FMA(R[5], W12, FMA(R[2], W02, c[5])));
   // Omega' = F'^-1 by the adjugate
-  const float a00 = f11 * f22 - f12 * f12;
-  const float a01 = f02 * f12 - f01 * f22;
-  const float a02 = f01 * f12 - f02 * f11;
-  const float a11 = f00 * f22 - f02 * f02;
-  const float a12 = f01 * f02 - f00 * f12;
-  const float a22 = f00 * f11 - f01 * f01;
-  const float det = f00 * a00 + f01 * a01 + f02 * a02;
+  const float a00 = FMA(f11, f22, -(f12 * f12));
+  const float a01 = FMA(f02, f12, -(f01 * f22));
+  const float a02 = FMA(f01, f12, -(f02 * f11));
+  const float a11 = FMA(f00, f22, -(f02 * f02));
+  const float a12 = FMA(f01, f02, -(f00 * f12));
+  const float a22 = FMA(f00, f11, -(f01 * f01));
+  const float det = FMA(f02, a02, FMA(f01, a01, f00 * a00));
   if (!((f00 > 0.f) & (a22 > 0.f) & (det > 0.f))) return;  // not positive definite
   const float inv = 1.0f / det;
   const float o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
   const float o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
   // g = Omega' r
-  const float g0 = o00 * r0 + o01 * r1 + o02 * r2;
-  const float g1 = o01 * r0 + o11 * r1 + o12 * r2;
-  const float g2 = o02 * r0 + o12 * r1 + o22 * r2;
-  acc.add(LIN ? 27 : 0, r0 * g0 + r1 * g1 + r2 * g2);
+  const float g0 = FMA(o02, r2, FMA(o01, r1, o00 * r0));
+  const float g1 = FMA(o12, r2, FMA(o11, r1, o01 * r0));
+  const float g2 = FMA(o22, r2, FMA(o12, r1, o02 * r0));
+  acc.add(LIN ? 27 : 0, FMA(r2, g2, FMA(r1, g1, r0 * g0)));
   if constexpr (LIN) {
     // M = [mu]x Omega' (column c = mu x Omega'_c): the (omega, rho) block
-    const float M00 = my * o02 - mz * o01, M10 = mz * o00 - mx * o02, M20 = mx * o01 - my * o00;
-    const float M01 = my * o12 - mz * o11, M11 = mz * o01 - mx * o12, M21 = mx * o11 - my * o01;
-    const float M02 = my * o22 - mz * o12, M12 = mz * o02 - mx * o22, M22 = mx * o12 - my * o02;
+    const float M00 = FMA(my, o02, -(mz * o01)), M10 = FMA(mz, o00, -(mx * o02));
+    const float M20 = FMA(mx, o01, -(my * o00));
+    const float M01 = FMA(my, o12, -(mz * o11)), M11 = FMA(mz, o01, -(mx * o12));
+    const float M21 = FMA(mx, o11, -(my * o01));
+    const float M02 = FMA(my, o22, -(mz * o12)), M12 = FMA(mz, o02, -(mx * o22));
+    const float M22 = FMA(mx, o12, -(my * o02));
     // (omega, omega) block [mu]x^T Omega' [mu]x, row r = mu x (row r of M)
-    acc.add(0, my * M02 - mz * M01);
-    acc.add(1, mz * M00 - mx * M02);
-    acc.add(2, mx * M01 - my * M00);
+    acc.add(0, FMA(my, M02, -(mz * M01)));
+    acc.add(1, FMA(mz, M00, -(mx * M02)));
+    acc.add(2, FMA(mx, M01, -(my * M00)));
     acc.add(3, M00);
     acc.add(4, M01);
     acc.add(5, M02);
-    acc.add(6, mz * M10 - mx * M12);
-    acc.add(7, mx * M11 - my * M10);
+    acc.add(6, FMA(mz, M10, -(mx * M12)));
+    acc.add(7, FMA(mx, M11, -(my * M10)));
     acc.add(8, M10);
     acc.add(9, M11);
     acc.add(10, M12);
-    acc.add(11, mx * M21 - my * M20);
+    acc.add(11, FMA(mx, M21, -(my * M20)));
     acc.add(12, M20);
     acc.add(13, M21);
     acc.add(14, M22);
@@ -417,13 +383,14 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const float R[9],
     acc.add(19, o12);
     acc.add(20, o22);
     // gradient J'^T Omega' r = (g x mu, -g)
-    acc.add(21, g1 * mz - g2 * my);
-    acc.add(22, g2 * mx - g0 * mz);
-    acc.add(23, g0 * my - g1 * mx);
+    acc.add(21, FMA(g1, mz, -(g2 * my)));
+    acc.add(22, FMA(g2, mx, -(g0 * mz)));
+    acc.add(23, FMA(g0, my, -(g1 * mx)));
     acc.add(24, -g0);
     acc.add(25, -g1);
     acc.add(26, -g2);
   }
+#undef FMA
 }
 
 // ---------------------------------------------------------------- tiles
@@ -464,9 +431,89 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
   return k;
 }
 
+// Pending hits of one wave, a ring in LDS (structure of arrays).  A lookup
+// phase appends the lanes that found their voxel; the math then runs on full
+// batches of 64 hits, so misses cost no math lanes.
+constexpr int kChunk = 4;                    // lookup passes per phase
+constexpr uint32_t kRing = 64 * kChunk + 64;  // >= 63 left over + 64 * kChunk appended
+
+struct HitQueue {
+  float x[kRing], y[kRing], z[kRing];
+  int32_t idx[kRing];   // point index in the source cloud
+  int32_t slot[kRing];  // slot of its voxel in the target map
+};
+
+__device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
+  e += d;  // e < kRing and d < kRing, so one wrap suffices
+  return e >= kRing ? e - kRing : e;
+}
+
+// One batch of hits held in registers between its loads and its math.
+struct Batch {
+  float x, y, z;
+  int32_t idx;
+  float c[6];    // point covariance
+  f32x4 w0, w1;  // payload: mean (w0.xyz), cov xx..yz (w0.w, w1)
+  float czz;     // payload: cov zz
+  int32_t ord;   // payload: voxel ordinal (loaded only for the corr output)
+};
+
+// Reads the entry of each lane and issues its 9 global loads (no branches:
+// dead lanes of a partial batch read entry `head`, point 0 and slot 0).  Only
+// words that are used are loaded: a dead destination register could be
+// reused while its load is in flight, which forces an early wait.
+template <bool CORR>
+__device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t e, bool live,
+                                           const float *pc, int64_t n, const Payload *payload) {
+  B.x = Q.x[e];
+  B.y = Q.y[e];
+  B.z = Q.z[e];
+  const int32_t idx = Q.idx[e];
+  const int32_t slot = Q.slot[e];
+  B.idx = live ? idx : 0;
+  gfloat *gc = (gfloat *)pc;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) B.c[a] = __builtin_nontemporal_load(gc + a * n + B.idx);
+  const Payload *pl = payload + (live ? slot : 0);
+  gfloat4 *gp = (gfloat4 *)pl;
+  B.w0 = gp[0];
+  B.w1 = gp[1];
+  B.czz = *(gfloat *)(&pl->cov[5]);
+  if constexpr (CORR) B.ord = *(const int32_t __attribute__((address_space(1))) *)(&pl->ordinal);
+  // keep the other batch's math below these loads (hoisting it would make it
+  // wait for that batch's loads before these are issued)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <bool LIN, bool FF, bool CORR, typename SumsT>
+__device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
+                                           int32_t *pcorr) {
+  if constexpr (CORR) pcorr[B.idx] = B.ord;
+  const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
+  const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
+  float q[3], qerr[3] = {0.f, 0.f, 0.f};
+  if constexpr (FF) {
+    transform_error(k.R, k.Rlo, k.t, k.tlo, B.x, B.y, B.z, q, qerr);
+  } else {
+    lookup_transform(k.R, k.t, B.x, B.y, B.z, q);
+  }
+  add_correspondence<LIN>(acc, k.R, B.x, B.y, B.z, B.c, q, qerr, m, S);
+}
+
 // Linearization (LIN) or cost evaluation (!LIN) of one tile per block.
 // FF: residual from the double-float transform (else plain FP32).
-template <int ACC, bool LIN, bool FF>
+// CORR: also write each point's voxel ordinal (or -1).
+//
+// Each wave alternates two phases over its 64-point columns of the tile:
+//   lookup: kChunk passes of transform + key, one key load and the prefetch
+//           of the next pass's coordinates (a fixed set of loads per pass, so
+//           the key wait never waits for the prefetch); hits are appended to
+//           the wave's ring;
+//   math:   the full batches of 64 hits, double-buffered: a batch's payload
+//           and covariance gathers are in flight during the previous batch's
+//           math.
+// The last partial batch runs at the end of the tile.
+template <int ACC, bool LIN, bool FF, bool CORR>
 __global__ void __launch_bounds__(kBlock)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_points,
@@ -476,6 +523,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   using SumsT = Sums<ACC, N>;
   __shared__ typename SumsT::lds_t lds[kWaves * N];
   __shared__ int lds_cnt[kWaves];
+  __shared__ HitQueue queues[kWaves];
 
   const int64_t tile = block_tile(tile_base);
   if (tile >= tile_end) return;
@@ -485,50 +533,118 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const int64_t n = fd.n;
   const float *__restrict__ px = fd.xyz;
   const float *__restrict__ pc = fd.cov;
-  const Slot *__restrict__ slots = fd.slots;
+  const uint64_t *__restrict__ keys = fd.keys;
+  const Payload *__restrict__ payload = fd.payload;
   const int64_t begin = td.start;
   const int64_t end = min(begin + int64_t(tile_points), n);
-  int32_t *__restrict__ pcorr = corr ? corr + fd.corr_offset : nullptr;
+  int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset : nullptr;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  HitQueue &Q = queues[wave];
 
   SumsT acc;
   acc.zero();
-  int inl = 0;
-  // Software pipeline: the next point's HBM loads are issued after the
-  // current point's slot load, so they are in flight during the lookup and
-  // the math (vector loads return in order, so the slot can be waited for
-  // without waiting for the prefetch).
-  SrcPoint cur, nxt;
-  int64_t i = begin + threadIdx.x;
-  if (i < end) load_point<true>(px, pc, n, i, cur);
-  for (; i < end; i += kBlock) {
-    float q[3];
-    lookup_transform(k.R, k.t, cur.x, cur.y, cur.z, q);
-    const VoxelKey vk = voxel_key(q, fd.scale, fd.log2cap);
-    // Both loads are unconditional (an out-of-range key reads its hash slot,
-    // the last iteration re-reads the tile's last point) so that the wait for
-    // the slot leaves exactly the nine prefetch loads in flight.
-    SlotData d;
-    load_slot(slots, vk.h, d);
-    load_point<true>(px, pc, n, min(i + kBlock, end - 1), nxt);
-    const bool hit = vk.ok && resolve_slot(slots, fd.log2cap, vk.key, vk.h, d);
-    if (pcorr) pcorr[i] = hit ? __float_as_int(d.w2.w) : -1;
-    if (hit) {
-      ++inl;
-      const float m[3] = {d.w0.z, d.w0.w, d.w1.x};
-      const float S[6] = {d.w1.y, d.w1.z, d.w1.w, d.w2.x, d.w2.y, d.w2.z};
-      float qerr[3] = {0.f, 0.f, 0.f};
-      if constexpr (FF) transform_error(k.R, k.Rlo, k.t, k.tlo, cur.x, cur.y, cur.z, qerr);
-      add_correspondence<LIN>(acc, k.R, cur.x, cur.y, cur.z, cur.c, q, qerr, m, S);
+  uint32_t head = 0, count = 0;  // wave-uniform ring state
+  uint32_t hits = 0;             // wave-uniform hit count
+
+  // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead).
+  float cur[kChunk][3];
+  int64_t base = begin + wave * 64;
+  if (base < end) {
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+      load_xyz(px, n, min(base + p * kBlock + lane, end - 1), cur[p]);
+  }
+  while (base < end) {
+    // ---- lookup phase: the keys of all kChunk passes are in flight at once,
+    // then the next chunk's coordinates; keys are then resolved in order, so
+    // each wait leaves the later keys and the whole prefetch in flight.
+    VoxelKey vk[kChunk];
+    uint64_t k0[kChunk];
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) {
+      float q[3];
+      lookup_transform(k.R, k.t, cur[p][0], cur[p][1], cur[p][2], q);
+      vk[p] = voxel_key(q, fd.scale, fd.log2cap);
     }
-    cur = nxt;
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) k0[p] = *(gu64 *)(keys + vk[p].h);
+    __builtin_amdgcn_sched_barrier(0);
+    float nxt[kChunk][3];
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+      load_xyz(px, n, min(base + (kChunk + p) * kBlock + lane, end - 1), nxt[p]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) {
+      const int64_t i = base + p * kBlock + lane;
+      const bool valid = i < end;
+      const int hs = find_slot(keys, fd.log2cap, vk[p].key, vk[p].h, k0[p]);
+      const int h = (valid && vk[p].ok) ? hs : -1;
+      if constexpr (CORR) {
+        if (valid && h < 0) pcorr[i] = -1;
+      }
+      const uint64_t mask = __ballot(h >= 0);
+      if (h >= 0) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+            uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+        const uint32_t e = ring_add(ring_add(head, count), below);
+        Q.x[e] = cur[p][0];
+        Q.y[e] = cur[p][1];
+        Q.z[e] = cur[p][2];
+        Q.idx[e] = int32_t(i);
+        Q.slot[e] = h;
+      }
+      const uint32_t got = uint32_t(__popcll(mask));
+      count += got;
+      hits += got;
+    }
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cur[p][a] = nxt[p][a];
+    base += kChunk * kBlock;
+    __builtin_amdgcn_wave_barrier();
+    // ---- math phase: full batches, double-buffered
+    const uint32_t nb = count / 64;
+    if (nb > 0) {
+      // unrolled by two so that the buffers swap roles without copies (a
+      // copy would wait for the loads it copies)
+      Batch A, B;
+      batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
+      head = ring_add(head, 64);
+      uint32_t bi = 1;
+      for (; bi + 1 < nb; bi += 2) {
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
+        head = ring_add(head, 64);
+        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+        batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
+        head = ring_add(head, 64);
+        batch_math<LIN, FF, CORR>(acc, B, k, pcorr);
+      }
+      if (bi < nb) {
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
+        head = ring_add(head, 64);
+        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+        batch_math<LIN, FF, CORR>(acc, B, k, pcorr);
+      } else {
+        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+      }
+      count -= nb * 64;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (count > 0) {  // last partial batch: dead lanes add nothing
+    const bool live = uint32_t(lane) < count;
+    Batch A;
+    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, pc, n, payload);
+    if (live) batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
   }
 
   acc.wave_reduce();
-  inl = wave_sum(inl);
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == kLastLane) {
+  if (lane == kLastLane) {
     acc.store(lds, wave);
-    lds_cnt[wave] = inl;
+    lds_cnt[wave] = int(hits);
   }
   __syncthreads();
   double *__restrict__ out = partials + tile * kPartialStride;
@@ -542,7 +658,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   }
 }
 
-// Overlap hit counts of one tile per block (Eq. (7)).
+// Overlap hit counts of one tile per block (Eq. (7)): keys only.
 __global__ void __launch_bounds__(kBlock)
 k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
           int64_t tile_base, int64_t tile_end, int32_t tile_points,
@@ -558,16 +674,42 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   const int64_t begin = td.start;
   const int64_t end = min(begin + int64_t(tile_points), n);
   int hits = 0;
-  SrcPoint cur, nxt;
-  int64_t i = begin + threadIdx.x;
-  if (i < end) load_point<false>(px, nullptr, n, i, cur);
-  for (; i < end; i += kBlock) {
-    float q[3];
-    lookup_transform(k.R, k.t, cur.x, cur.y, cur.z, q);
-    const VoxelKey vk = voxel_key(q, fd.scale, fd.log2cap);
-    load_point<false>(px, nullptr, n, min(i + kBlock, end - 1), nxt);
-    hits += vk.ok && contains_key(fd.slots, fd.log2cap, vk.key, vk.h);
-    cur = nxt;
+  const float *__restrict__ pk = px;
+  float cur[kChunk][3];
+  int64_t base = begin + int64_t(threadIdx.x & ~63);
+  const int lane = threadIdx.x & 63;
+  if (base < end) {
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+      load_xyz(pk, n, min(base + p * kBlock + lane, end - 1), cur[p]);
+  }
+  for (; base < end; base += kChunk * kBlock) {
+    VoxelKey vk[kChunk];
+    uint64_t k0[kChunk];
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) {
+      float q[3];
+      lookup_transform(k.R, k.t, cur[p][0], cur[p][1], cur[p][2], q);
+      vk[p] = voxel_key(q, fd.scale, fd.log2cap);
+    }
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) k0[p] = *(gu64 *)(fd.keys + vk[p].h);
+    __builtin_amdgcn_sched_barrier(0);
+    float nxt[kChunk][3];
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+      load_xyz(pk, n, min(base + (kChunk + p) * kBlock + lane, end - 1), nxt[p]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p) {
+      const bool valid = base + p * kBlock + lane < end;
+      const int hs = find_slot(fd.keys, fd.log2cap, vk[p].key, vk[p].h, k0[p]);
+      hits += (valid && vk[p].ok && hs >= 0) ? 1 : 0;
+    }
+#pragma unroll
+    for (int p = 0; p < kChunk; ++p)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cur[p][a] = nxt[p][a];
   }
   hits = wave_sum(hits);
   if ((threadIdx.x & 63) == kLastLane) lds_cnt[threadIdx.x >> 6] = hits;
@@ -685,8 +827,13 @@ template <int ACC, bool LIN, bool FF>
 static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                              const double *poses, int32_t *corr, hipStream_t st) {
   if (te <= tb) return hipSuccess;
-  k_linearize<ACC, LIN, FF><<<xcd_grid(te - tb), kBlock, 0, st>>>(
-      fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr);
+  if (corr) {
+    k_linearize<ACC, LIN, FF, true><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr);
+  } else {
+    k_linearize<ACC, LIN, FF, false><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -223,7 +223,8 @@ int vgicp_map_info(vgicp_map map, int64_t *n_voxels, int64_t *capacity, int64_t 
   if (!map) return fail(nullptr, VGICP_EINVAL, "vgicp_map_info: map is NULL");
   if (n_voxels) *n_voxels = map->n_voxels;
   if (capacity) *capacity = map->capacity;
-  if (device_bytes) *device_bytes = map->capacity * int64_t(sizeof(Slot));
+  if (device_bytes)
+    *device_bytes = map->capacity * int64_t(sizeof(uint64_t) + sizeof(Payload));
   if (resolution) *resolution = map->resolution;
   return VGICP_OK;
 }
@@ -245,7 +246,7 @@ int vgicp_map_export(vgicp_ctx ctx, vgicp_map map, int32_t *keys, float *mean, f
 int vgicp_map_free(vgicp_map map) {
   if (!map) return VGICP_OK;
   (void)hipSetDevice(map->device);
-  if (map->slots) (void)hipFree(map->slots);
+  if (map->buffer) (void)hipFree(map->buffer);
   delete map;
   return VGICP_OK;
 }
@@ -328,7 +329,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     const vgicp_voxelmap_s *m = maps[x.tgt];
     d.xyz = c.xyz;
     d.cov = c.cov;
-    d.slots = m->slots;
+    d.keys = m->keys;
+    d.payload = m->payload;
     d.n = c.n;
     d.corr_offset = corr_off;
     d.pose_i = x.pose_i;

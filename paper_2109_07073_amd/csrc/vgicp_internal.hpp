@@ -36,25 +36,28 @@ __host__ __device__ inline uint32_t hash_slot(uint64_t key, uint32_t log2cap) {
   return uint32_t((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// One open-addressing slot, 64 bytes so that a slot never straddles a
-// 128-byte line.  The first three 16-byte words carry everything a lookup and
-// the per-point math read: key, voxel mean and the 6 covariance entries.
-struct alignas(64) Slot {
-  uint64_t key;
+// A voxel map is an open-addressed table in two arrays indexed by slot:
+//   keys[cap]     packed voxel keys (kEmptyKey for empty slots), probed by
+//                 every lookup; 16 keys share a 128-byte line, so the lines a
+//                 factor's misses touch are few;
+//   payload[cap]  the voxel's statistics, read only when the key matched.
+// A payload is 64 bytes so that it never straddles a 128-byte line.
+struct alignas(64) Payload {
   float mean[3];
   float cov[6];  // xx xy xz yy yz zz
   int32_t ordinal;
   int32_t count;
-  int32_t pad[3];
+  int32_t pad[5];
 };
-static_assert(sizeof(Slot) == 64, "slot layout");
+static_assert(sizeof(Payload) == 64, "payload layout");
 
 // ---------------------------------------------------------------- factors
 // Per-factor device descriptor (read with uniform loads by every tile).
 struct FactorDesc {
-  const float *xyz;   // [3][n]
-  const float *cov;   // [6][n]
-  const Slot *slots;  // target hash table
+  const float *xyz;        // [3][n]
+  const float *cov;        // [6][n]
+  const uint64_t *keys;    // target map: slot keys
+  const Payload *payload;  // target map: slot payloads
   int64_t n;          // source points
   int64_t corr_offset;
   int32_t pose_i;
@@ -63,7 +66,6 @@ struct FactorDesc {
   float scale;        // fl32(1/r) of the target map
   int32_t tile_begin; // first tile of this factor in the tile table
   int32_t n_tiles;
-  int32_t pad[2];
 };
 
 // One tile: `count` source points of factor `factor` starting at `start`.
@@ -111,7 +113,9 @@ struct vgicp_voxelmap_s {
   uint32_t log2cap = 0;
   float scale = 0.f;
   double resolution = 0.0;
-  vgicp::Slot *slots = nullptr;
+  void *buffer = nullptr;             // one allocation: keys, then payloads
+  uint64_t *keys = nullptr;
+  vgicp::Payload *payload = nullptr;
 };
 
 struct GraphEntry {

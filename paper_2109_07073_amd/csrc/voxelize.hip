@@ -1,9 +1,10 @@
 // Voxel-map construction on gfx950 (Sec. III-A, VGICP voxel data association).
 //
-// A cloud becomes an open-addressed hash table of 64-byte slots keyed by the
-// packed voxel key.  Each slot carries the voxel mean and the mean of the
-// point covariances (the VGICP aggregation of point distributions), both
-// accumulated in FP64 in point order and rounded once to FP32.
+// A cloud becomes an open-addressed hash table keyed by the packed voxel key
+// (a key array and a payload array indexed by slot).  Each payload carries
+// the voxel mean and the mean of the point covariances (the VGICP aggregation
+// of point distributions), both accumulated in FP64 in point order and
+// rounded once to FP32.
 //
 // Steps: keys -> radix sort of (key, point index) -> segment heads -> scan
 // -> segment starts -> [one host sync to size the table] -> FP64 segment sums
@@ -61,19 +62,9 @@ k_segment_starts(const uint32_t *__restrict__ head, const uint32_t *__restrict__
   if (i == n - 1) seg[ord1[i]] = uint32_t(n);
 }
 
-__global__ void __launch_bounds__(256) k_fill_empty(Slot *__restrict__ slots, int64_t cap) {
+__global__ void __launch_bounds__(256) k_fill_empty(uint64_t *__restrict__ keys, int64_t cap) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= cap) return;
-  Slot s;
-  s.key = kEmptyKey;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) s.mean[a] = 0.f;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) s.cov[a] = 0.f;
-  s.ordinal = -1;
-  s.count = 0;
-  s.pad[0] = s.pad[1] = s.pad[2] = 0;
-  slots[i] = s;
+  if (i < cap) keys[i] = kEmptyKey;
 }
 
 // One thread per voxel: sequential FP64 sums over the voxel's points in point
@@ -81,8 +72,8 @@ __global__ void __launch_bounds__(256) k_fill_empty(Slot *__restrict__ slots, in
 __global__ void __launch_bounds__(256)
 k_build_slots(const float *__restrict__ xyz, const float *__restrict__ cov, int64_t n,
               const uint64_t *__restrict__ sorted_keys, const uint32_t *__restrict__ sorted_idx,
-              const uint32_t *__restrict__ seg, int64_t n_voxels, Slot *__restrict__ slots,
-              uint32_t log2cap) {
+              const uint32_t *__restrict__ seg, int64_t n_voxels, uint64_t *__restrict__ keys,
+              Payload *__restrict__ payload, uint32_t log2cap) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n_voxels) return;
   const uint32_t b = seg[v], e = seg[v + 1];
@@ -100,32 +91,37 @@ k_build_slots(const float *__restrict__ xyz, const float *__restrict__ cov, int6
   const uint32_t mask = (1u << log2cap) - 1u;
   uint32_t h = hash_slot(key, log2cap);
   for (uint32_t probe = 0; probe <= mask; ++probe) {
-    const unsigned long long prev = atomicCAS(
-        reinterpret_cast<unsigned long long *>(&slots[h].key), (unsigned long long)kEmptyKey,
-        (unsigned long long)key);
+    const unsigned long long prev =
+        atomicCAS(reinterpret_cast<unsigned long long *>(&keys[h]),
+                  (unsigned long long)kEmptyKey, (unsigned long long)key);
     if (prev == kEmptyKey) break;
     h = (h + 1u) & mask;
   }
-  Slot &s = slots[h];
+  Payload pl;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) s.mean[a] = float(sm[a] / cnt);
+  for (int a = 0; a < 3; ++a) pl.mean[a] = float(sm[a] / cnt);
 #pragma unroll
-  for (int a = 0; a < 6; ++a) s.cov[a] = float(sc[a] / cnt);
-  s.ordinal = int32_t(v);
-  s.count = int32_t(e - b);
+  for (int a = 0; a < 6; ++a) pl.cov[a] = float(sc[a] / cnt);
+  pl.ordinal = int32_t(v);
+  pl.count = int32_t(e - b);
+#pragma unroll
+  for (int a = 0; a < 5; ++a) pl.pad[a] = 0;
+  payload[h] = pl;
 }
 
 __global__ void __launch_bounds__(256)
-k_export(const Slot *__restrict__ slots, int64_t cap, int32_t *__restrict__ keys,
-         float *__restrict__ mean, float *__restrict__ cov, int32_t *__restrict__ count) {
+k_export(const uint64_t *__restrict__ keys_tab, const Payload *__restrict__ payload, int64_t cap,
+         int32_t *__restrict__ keys, float *__restrict__ mean, float *__restrict__ cov,
+         int32_t *__restrict__ count) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= cap) return;
-  const Slot s = slots[i];
-  if (s.key == kEmptyKey) return;
+  const uint64_t key = keys_tab[i];
+  if (key == kEmptyKey) return;
+  const Payload s = payload[i];
   const int64_t o = s.ordinal;
   if (keys) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(s.key, a);
+    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(key, a);
   }
   if (mean) {
 #pragma unroll
@@ -290,21 +286,26 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
   m->log2cap = log2cap;
   m->scale = s;
   m->resolution = resolution;
-  hipError_t e = hipMalloc(&m->slots, size_t(cap) * sizeof(Slot));
+  const size_t key_bytes = (size_t(cap) * sizeof(uint64_t) + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(&m->buffer, key_bytes + size_t(cap) * sizeof(Payload));
+  if (e == hipSuccess) {
+    m->keys = static_cast<uint64_t *>(m->buffer);
+    m->payload = reinterpret_cast<Payload *>(static_cast<char *>(m->buffer) + key_bytes);
+  }
   if (e != hipSuccess) {
     delete m;
     msg = std::string("vgicp_voxelize: hipMalloc of the hash table: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP;
   }
-  k_fill_empty<<<grid_for(cap), 256, 0, st>>>(m->slots, cap);
+  k_fill_empty<<<grid_for(cap), 256, 0, st>>>(m->keys, cap);
   if (n_voxels > 0) {
     k_build_slots<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.keys_out,
-                                                       sc.idx_out, sc.seg, n_voxels, m->slots,
-                                                       log2cap);
+                                                       sc.idx_out, sc.seg, n_voxels, m->keys,
+                                                       m->payload, log2cap);
   }
   e = hipGetLastError();
   if (e != hipSuccess) {
-    (void)hipFree(m->slots);
+    (void)hipFree(m->buffer);
     delete m;
     msg = std::string("vgicp_voxelize: kernel launch: ") + hipGetErrorString(e);
     return VGICP_EHIP;
@@ -316,8 +317,8 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg) {
   if (m->n_voxels == 0) return VGICP_OK;
-  k_export<<<grid_for(m->capacity), 256, 0, ctx->stream>>>(m->slots, m->capacity, keys, mean, cov,
-                                                           count);
+  k_export<<<grid_for(m->capacity), 256, 0, ctx->stream>>>(m->keys, m->payload, m->capacity, keys,
+                                                           mean, cov, count);
   HIP_TRY(hipGetLastError());
   return VGICP_OK;
 }
