@@ -58,6 +58,7 @@ extern "C" {
 #define VGICP_ERANGE (-3)     /* a voxel key of a cloud lies outside [-2^20, 2^20) */
 #define VGICP_ENONFINITE (-4) /* a point coordinate is NaN or infinite             */
 #define VGICP_EHIP (-5)       /* a HIP runtime call failed                         */
+#define VGICP_EFULL (-6)      /* a server's memory budget would be exceeded        */
 
 /* Accumulation of the per-point Hessian, gradient and cost terms. */
 #define VGICP_ACC_F32 0      /* FP32 per lane and across the workgroup              */
@@ -100,6 +101,11 @@ typedef struct {
   int32_t use_graph; /* nonzero: the batched schedule is captured once into a HIP
                         graph per (poses, outputs) pointer set and replayed          */
   int32_t resid;     /* VGICP_RESID_*                                                */
+  float fp64_kappa;  /* > 0: points whose FP32 fused covariance F' = R^T C' R + C has a
+                        condition estimate trace^3 / (27 det) above this value (or is not
+                        positive definite in FP32) form and invert F' in FP64;
+                        0 = FP32 always                                               */
+  int32_t reserved;  /* must be 0                                                    */
 } vgicp_opts;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -235,6 +241,87 @@ int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses
  * NULL).  Errors: EINVAL, EHIP. */
 int vgicp_overlap(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, int64_t *hits,
                   double *overlap);
+
+/* --------------------------------------------------------------------------
+ * Serving: continuous batching of factor requests over resident keyframes.
+ *
+ * The paper's optimizer issues every cost task of an iteration to the GPU,
+ * synchronizes once and collects the results (Sec. III-D).  A server keeps the
+ * keyframes (clouds and voxel maps) resident in device memory under a byte
+ * budget and serves requests from several optimizers at once: requests that
+ * arrive while batches are on the device are admitted into the next batch as
+ * soon as a batch slot frees up, and up to `inflight` batches run on their own
+ * streams at the same time.  A factor's result depends only on its own points
+ * and tiles, so it is bit-identical whether its request ran alone or in a mix.
+ * All functions are thread-safe.
+ * ------------------------------------------------------------------------ */
+
+typedef struct vgicp_server_s *vgicp_server;
+
+#define VGICP_REQ_LINEARIZE 0 /* outputs H, b, e, inliers                  */
+#define VGICP_REQ_EVALUATE 1  /* outputs e, inliers                        */
+#define VGICP_REQ_OVERLAP 2   /* outputs inliers (= hits), overlap         */
+
+typedef struct {
+  int64_t memory_budget_bytes; /* device bytes for resident frames; 0 = no limit     */
+  int32_t max_batch_factors;   /* factors per batch (slot size), >= 1               */
+  int32_t max_batch_points;    /* source points per batch, >= 1                     */
+  int32_t max_batch_poses;     /* poses per batch, >= 1                             */
+  int32_t inflight;            /* batches on the device at once, 1..8                */
+  int32_t tile_points;         /* 0 = default (as vgicp_factorset_create)           */
+  int32_t reserved;            /* must be 0                                         */
+  vgicp_opts opts;             /* accumulation, residual, kappa of every batch
+                                  (schedule and use_graph are ignored)              */
+} vgicp_server_config;
+
+/* Create a server on HIP device `device` with its own streams and worker
+ * thread.  Errors: EINVAL, ENOMEM, EHIP. */
+int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server *out);
+
+/* Stop the worker after the submitted requests complete and free everything
+ * (NULL accepted). */
+int vgicp_server_destroy(vgicp_server srv);
+
+/* Message of the last failure on srv. */
+const char *vgicp_server_last_error(vgicp_server srv);
+
+/* Register a keyframe: host SoA arrays h_xyz [3][n] and h_cov [6][n] are copied
+ * to server-owned device memory and voxelized at `resolution`.  Returns its id.
+ * Errors: EINVAL, ENONFINITE, ERANGE, EFULL (the frame would exceed the memory
+ * budget; nothing is kept), ENOMEM, EHIP. */
+int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_cov, int64_t n,
+                           double resolution, int32_t *frame_id);
+
+/* Remove a keyframe once every request that references it has completed.
+ * Errors: EINVAL (unknown id). */
+int vgicp_server_remove_frame(vgicp_server srv, int32_t frame_id);
+
+/* Device bytes held by resident frames, and the budget (0 = no limit). */
+int vgicp_server_memory(vgicp_server srv, int64_t *used_bytes, int64_t *budget_bytes);
+
+/* Submit a request of `kind` over n factors (src and tgt are frame ids, pose_i
+ * and pose_j index h_poses [n_poses][12]).  Factors and poses are copied before
+ * the call returns.  The host output arrays (H [n][144], b [n][12], e [n],
+ * inliers [n], overlap [n]; those the kind does not produce may be NULL) must
+ * stay valid until the request completes.  Returns a ticket.
+ * Errors: EINVAL (unknown frame, index out of range, NULL outputs, more poses
+ * than max_batch_poses). */
+int vgicp_server_submit(vgicp_server srv, int kind, const vgicp_factor *factors, int64_t n,
+                        const double *h_poses, int32_t n_poses, double *H, double *b, double *e,
+                        int64_t *inliers, double *overlap, int64_t *ticket);
+
+/* Nonzero in *done once the request's outputs are written.  Errors: EINVAL. */
+int vgicp_server_poll(vgicp_server srv, int64_t ticket, int *done);
+
+/* Block until the request completes; *latency_ms (may be NULL) receives the
+ * time from submit to outputs written.  Errors: EINVAL, EHIP (a batch failed). */
+int vgicp_server_wait(vgicp_server srv, int64_t ticket, double *latency_ms);
+
+/* Counters: batches launched and requests completed so far, the largest number
+ * of requests merged into one batch, and the largest number of batches that
+ * were on the device at once.  Any pointer may be NULL. */
+int vgicp_server_stats(vgicp_server srv, int64_t *batches, int64_t *requests,
+                       int64_t *max_requests_per_batch, int64_t *max_inflight);
 
 #ifdef __cplusplus
 }

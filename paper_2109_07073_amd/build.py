@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvgicp.so")
 ARCH = os.environ.get("VGICP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip"]
+SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

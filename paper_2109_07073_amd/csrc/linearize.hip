@@ -296,19 +296,76 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
   }
 };
 
+// ---------------------------------------------------------------- factor constants
+struct FactorConsts {
+  float R[9];    // fl32(R)
+  float t[3];    // fl32(t)
+  float Rlo[9];  // fl32(R - fl32(R))
+  float tlo[3];  // fl32(t - fl32(t))
+  double R64[9]; // R itself, for the FP64 fused covariance of ill-conditioned points
+};
+
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // ---------------------------------------------------------------- per point
 // Adds one correspondence.  R is the FP32 relative rotation, (mx, my, mz) the
 // source point, c its covariance, q its FP32 transform, m / S the voxel mean
 // and covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
 // the cost are added; without it only the cost.
-template <bool LIN, typename SumsT>
-__device__ __forceinline__ void add_correspondence(SumsT &acc, const float R[9], float mx,
-                                                   float my, float mz, const float c[6],
-                                                   const float q[3], const float qerr[3],
-                                                   const float m[3], const float S[6]) {
+// Omega' = (R^T C' R + C)^-1 formed and inverted in FP64 from the FP32 inputs
+// and the FP64 relative rotation, rounded to FP32.  Used for ill-conditioned
+// points, where forming F' in FP32 already loses the small eigenvalue.
+// Returns false when F' is not positive definite.
+__device__ __noinline__ bool fused_information_fp64(const double R[9], const float S[6],
+                                                    const float c[6], float o[6]) {
+  const double s0 = S[0], s1 = S[1], s2 = S[2], s3 = S[3], s4 = S[4], s5 = S[5];
+  double W[9];
+#pragma unroll
+  for (int col = 0; col < 3; ++col) {
+    const double r0 = R[col], r1 = R[3 + col], r2 = R[6 + col];
+    W[col] = s0 * r0 + s1 * r1 + s2 * r2;
+    W[3 + col] = s1 * r0 + s3 * r1 + s4 * r2;
+    W[6 + col] = s2 * r0 + s4 * r1 + s5 * r2;
+  }
+  auto f = [&](int a, int b, double cc) {
+    return R[a] * W[b] + R[3 + a] * W[3 + b] + R[6 + a] * W[6 + b] + cc;
+  };
+  const double f00 = f(0, 0, c[0]), f01 = f(0, 1, c[1]), f02 = f(0, 2, c[2]);
+  const double f11 = f(1, 1, c[3]), f12 = f(1, 2, c[4]), f22 = f(2, 2, c[5]);
+  const double a00 = f11 * f22 - f12 * f12, a01 = f02 * f12 - f01 * f22;
+  const double a02 = f01 * f12 - f02 * f11, a11 = f00 * f22 - f02 * f02;
+  const double a12 = f01 * f02 - f00 * f12, a22 = f00 * f11 - f01 * f01;
+  const double det = f00 * a00 + f01 * a01 + f02 * a02;
+  if (!(f00 > 0.0 && a22 > 0.0 && det > 0.0)) return false;
+  const double inv = 1.0 / det;
+  o[0] = float(a00 * inv);
+  o[1] = float(a01 * inv);
+  o[2] = float(a02 * inv);
+  o[3] = float(a11 * inv);
+  o[4] = float(a12 * inv);
+  o[5] = float(a22 * inv);
+  return true;
+}
+
+// Adds one correspondence.  k holds the FP32 relative rotation (and its FP64
+// value), (mx, my, mz) is the source point, c its covariance, q its FP32
+// transform and qerr that transform's rounding error, m / S the voxel mean
+// and covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
+// the cost are added; without it only the cost.  With KAPPA, points whose
+// FP32 fused covariance is not positive definite or has a condition estimate
+// trace^3 / (27 det) above `kappa` take the FP64 fused covariance.
+template <bool LIN, bool KAPPA, typename SumsT>
+__device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConsts &k,
+                                                   float kappa, float mx, float my, float mz,
+                                                   const float c[6], const float q[3],
+                                                   const float qerr[3], const float m[3],
+                                                   const float S[6]) {
   // Contraction is off and every fused multiply-add is explicit, so the cost
   // comes out bit-identical in the linearization and the cost-only kernels.
 #pragma clang fp contract(off)
+  const float *R = k.R;
 #define FMA __builtin_fmaf
   // residual e_k = mu' - T mu (target frame), rotated into the source frame;
   // m - q is exact when the two are within a factor of two, and qerr carries
@@ -343,10 +400,23 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const float R[9],
   const float a12 = FMA(f01, f02, -(f00 * f12));
   const float a22 = FMA(f00, f11, -(f01 * f01));
   const float det = FMA(f02, a02, FMA(f01, a01, f00 * a00));
-  if (!((f00 > 0.f) & (a22 > 0.f) & (det > 0.f))) return;  // not positive definite
-  const float inv = 1.0f / det;
-  const float o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
-  const float o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
+  float o00, o01, o02, o11, o12, o22;
+  const bool pd32 = (f00 > 0.f) & (a22 > 0.f) & (det > 0.f);
+  bool wide = false;
+  if constexpr (KAPPA) {
+    const float tr = (f00 + f11) + f22;
+    wide = !pd32 || (tr * tr * tr > (27.0f * kappa) * det);
+  }
+  if (wide) {
+    float o[6];
+    if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
+    o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
+  } else {
+    if (!pd32) return;  // not positive definite
+    const float inv = 1.0f / det;
+    o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
+    o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
+  }
   // g = Omega' r
   const float g0 = FMA(o02, r2, FMA(o01, r1, o00 * r0));
   const float g1 = FMA(o12, r2, FMA(o11, r1, o01 * r0));
@@ -402,17 +472,6 @@ __device__ __forceinline__ int64_t block_tile(int64_t tile_base) {
   return tile_base + int64_t(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
 }
 
-struct FactorConsts {
-  float R[9];    // fl32(R)
-  float t[3];    // fl32(t)
-  float Rlo[9];  // fl32(R - fl32(R))
-  float tlo[3];  // fl32(t - fl32(t))
-};
-
-__device__ __forceinline__ float uniform_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-
 __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
                                                       const double *__restrict__ poses) {
   double R[9], t[3];
@@ -422,6 +481,11 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
   for (int i = 0; i < 9; ++i) {
     k.R[i] = uniform_f(float(R[i]));
     k.Rlo[i] = uniform_f(float(R[i] - double(k.R[i])));
+    const long long b = __double_as_longlong(R[i]);
+    const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+    k.R64[i] = __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                    static_cast<long long>(static_cast<unsigned>(lo)));
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -485,9 +549,9 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <bool LIN, bool FF, bool CORR, typename SumsT>
+template <bool LIN, bool FF, bool CORR, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
-                                           int32_t *pcorr) {
+                                           float kappa, int32_t *pcorr) {
   if constexpr (CORR) pcorr[B.idx] = B.ord;
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
@@ -497,12 +561,14 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
   } else {
     lookup_transform(k.R, k.t, B.x, B.y, B.z, q);
   }
-  add_correspondence<LIN>(acc, k.R, B.x, B.y, B.z, B.c, q, qerr, m, S);
+  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, q, qerr, m, S);
 }
 
 // Linearization (LIN) or cost evaluation (!LIN) of one tile per block.
 // FF: residual from the double-float transform (else plain FP32).
 // CORR: also write each point's voxel ordinal (or -1).
+// KAPPA: ill-conditioned points take the FP64 fused covariance (see
+// add_correspondence).
 //
 // Each wave alternates two phases over its 64-point columns of the tile:
 //   lookup: kChunk passes of transform + key, one key load and the prefetch
@@ -513,12 +579,12 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //           and covariance gathers are in flight during the previous batch's
 //           math.
 // The last partial batch runs at the end of the tile.
-template <int ACC, bool LIN, bool FF, bool CORR>
+template <int ACC, bool LIN, bool FF, bool CORR, bool KAPPA>
 __global__ void __launch_bounds__(kBlock)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_points,
             const double *__restrict__ poses, double *__restrict__ partials,
-            int32_t *__restrict__ corr) {
+            int32_t *__restrict__ corr, float kappa) {
   constexpr int N = LIN ? kNumSums : 1;
   using SumsT = Sums<ACC, N>;
   __shared__ typename SumsT::lds_t lds[kWaves * N];
@@ -617,18 +683,18 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR>(acc, B, k, pcorr);
+        batch_math<LIN, FF, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
-        batch_math<LIN, FF, CORR>(acc, B, k, pcorr);
+        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, FF, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       } else {
-        batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
       }
       count -= nb * 64;
     }
@@ -638,7 +704,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     const bool live = uint32_t(lane) < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, pc, n, payload);
-    if (live) batch_math<LIN, FF, CORR>(acc, A, k, pcorr);
+    if (live) batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
   }
 
   acc.wave_reduce();
@@ -823,43 +889,53 @@ k_reduce(const FactorDesc *__restrict__ factors, int64_t factor_base,
 // ---------------------------------------------------------------- launchers
 static inline unsigned xcd_grid(int64_t tiles) { return unsigned(((tiles + 7) / 8) * 8); }
 
-template <int ACC, bool LIN, bool FF>
+template <int ACC, bool LIN, bool FF, bool KAPPA>
 static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                             const double *poses, int32_t *corr, hipStream_t st) {
+                             const double *poses, int32_t *corr, float kappa, hipStream_t st) {
   if (te <= tb) return hipSuccess;
   if (corr) {
-    k_linearize<ACC, LIN, FF, true><<<xcd_grid(te - tb), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr);
+    k_linearize<ACC, LIN, FF, true, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr, kappa);
   } else {
-    k_linearize<ACC, LIN, FF, false><<<xcd_grid(te - tb), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, nullptr);
+    k_linearize<ACC, LIN, FF, false, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, nullptr,
+        kappa);
   }
   return hipGetLastError();
 }
 
-template <int ACC>
+template <int ACC, bool KAPPA>
 static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool ff, int64_t tb,
-                             int64_t te, const double *poses, int32_t *corr, hipStream_t st) {
+                             int64_t te, const double *poses, int32_t *corr, float kappa,
+                             hipStream_t st) {
   if (lin) {
-    return ff ? launch_lin<ACC, true, true>(fs, tb, te, poses, corr, st)
-              : launch_lin<ACC, true, false>(fs, tb, te, poses, corr, st);
+    return ff ? launch_lin<ACC, true, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
+              : launch_lin<ACC, true, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
   }
-  return ff ? launch_lin<ACC, false, true>(fs, tb, te, poses, corr, st)
-            : launch_lin<ACC, false, false>(fs, tb, te, poses, corr, st);
+  return ff ? launch_lin<ACC, false, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
+            : launch_lin<ACC, false, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
 }
 
-hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, bool lin,
-                            int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st) {
-  const bool ff = resid == VGICP_RESID_FF;
+template <bool KAPPA>
+static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool ff, int64_t tb,
+                           int64_t te, const double *poses, int32_t *corr, float kappa,
+                           hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F64:
-      return launch_acc<VGICP_ACC_F64>(fs, lin, ff, tb, te, poses, corr, st);
+      return launch_acc<VGICP_ACC_F64, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
     case VGICP_ACC_F32_COMP:
-      return launch_acc<VGICP_ACC_F32_COMP>(fs, lin, ff, tb, te, poses, corr, st);
+      return launch_acc<VGICP_ACC_F32_COMP, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
     default:
-      return launch_acc<VGICP_ACC_F32>(fs, lin, ff, tb, te, poses, corr, st);
+      return launch_acc<VGICP_ACC_F32, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
   }
+}
+
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
+                            bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
+                            hipStream_t st) {
+  const bool ff = resid == VGICP_RESID_FF;
+  if (kappa > 0.f) return launch_k<true>(fs, accum, lin, ff, tb, te, poses, corr, kappa, st);
+  return launch_k<false>(fs, accum, lin, ff, tb, te, poses, corr, 0.f, st);
 }
 
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,

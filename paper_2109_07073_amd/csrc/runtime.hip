@@ -14,8 +14,8 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
                   std::string &msg);
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg);
-hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, bool lin,
-                            int64_t tb, int64_t te, const double *poses, int32_t *corr,
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
+                            bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
                             hipStream_t st);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st);
@@ -414,7 +414,7 @@ int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const c
 }
 
 int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
-  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_FF};
+  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_FF, 0.0f, 0};
   if (opts) *o = *opts;
   if (o->accum < VGICP_ACC_F32 || o->accum > VGICP_ACC_F64)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown accumulation");
@@ -422,23 +422,28 @@ int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown schedule");
   if (o->resid != VGICP_RESID_FF && o->resid != VGICP_RESID_F32)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown residual mode");
+  if (!(o->fp64_kappa >= 0.0f) || !std::isfinite(o->fp64_kappa))
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": fp64_kappa must be finite and >= 0");
+  if (o->reserved != 0) return fail(ctx, VGICP_EINVAL, std::string(who) + ": reserved must be 0");
   return VGICP_OK;
 }
 
 // Enqueue the factors' tiles [tb, te) and the reduce of factors [f0, f0+nf).
 // `ctx` is NULL inside graph capture (no timing events there).
 hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum, int resid,
-                         const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
+                         float kappa, const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
                          double *H, double *b, double *e, int64_t *inl, int32_t *corr,
                          hipStream_t st) {
   const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
   hipError_t err = hipSuccess;
   if (ctx) {
     TimedLaunch t(ctx, tk);
-    err = launch_linearize(fs, accum, resid, kind == kKindLinearize, tb, te, poses, corr, st);
+    err = launch_linearize(fs, accum, resid, kappa, kind == kKindLinearize, tb, te, poses, corr,
+                           st);
     t.done();
   } else {
-    err = launch_linearize(fs, accum, resid, kind == kKindLinearize, tb, te, poses, corr, st);
+    err = launch_linearize(fs, accum, resid, kappa, kind == kKindLinearize, tb, te, poses, corr,
+                           st);
   }
   if (err != hipSuccess) return err;
   if (ctx) {
@@ -460,14 +465,14 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   if (o.schedule == VGICP_SCHED_PER_FACTOR) {
     for (int64_t f = 0; f < fs->n_factors && err == hipSuccess; ++f) {
       const FactorDesc &d = fs->h_factors[size_t(f)];
-      err = enqueue_range(ctx, fs, kind, o.accum, o.resid, poses, d.tile_begin,
+      err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, d.tile_begin,
                           int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st);
     }
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
   }
   if (!o.use_graph) {
-    err = enqueue_range(ctx, fs, kind, o.accum, o.resid, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
+    err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
                         inl, corr, st);
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
@@ -477,13 +482,13 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   GraphEntry *g = nullptr;
   for (auto &x : fs->graphs)
     if (x.poses == poses && x.H == H && x.b == b && x.e == e && x.inl == inl && x.corr == corr &&
-        x.accum == o.accum && x.resid == o.resid && x.kind == kind)
+        x.accum == o.accum && x.resid == o.resid && x.kappa == o.fp64_kappa && x.kind == kind)
       g = &x;
   if (!g) {
-    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, kind};
+    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fp64_kappa, kind};
     err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(ctx, "hipStreamBeginCapture", err);
-    hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, poses, 0, fs->n_tiles, 0,
+    hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, 0, fs->n_tiles, 0,
                                     fs->n_factors, H, b, e, inl, corr, st);
     err = hipStreamEndCapture(st, &ng.graph);
     if (lerr != hipSuccess) {

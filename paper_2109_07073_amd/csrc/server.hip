@@ -1,0 +1,705 @@
+// Continuous-batching server over resident keyframes (vgicp_server_* in
+// include/vgicp.h).
+//
+// One worker thread owns `inflight` batch slots, each with its own stream,
+// device tables and pinned staging.  Requests are queued by vgicp_server_submit;
+// the worker packs queued requests of one kind, FIFO, into the next free slot
+// (splitting a request across batches when it does not fit), uploads the
+// slot's factor/tile/pose tables, launches the same kernels as the factor-set
+// path and copies the outputs back.  A host function enqueued after each batch
+// wakes the worker, which scatters the outputs into the requests' buffers.
+// New requests are admitted while earlier batches are still running.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+
+#include "vgicp_internal.hpp"
+
+namespace vgicp {
+int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out,
+                  std::string &msg);
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
+                            bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
+                            hipStream_t st);
+hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
+                          const double *poses, hipStream_t st);
+hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
+                         int mode, double *H, double *b, double *e, int64_t *inl,
+                         double *overlap, hipStream_t st);
+}  // namespace vgicp
+
+using namespace vgicp;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr int kDefaultTile = 4096;
+
+struct Frame {
+  bool live = false;
+  float *cloud = nullptr;  // device: xyz [3][n] then cov [6][n]
+  int64_t n = 0;
+  vgicp_map map = nullptr;
+  int64_t bytes = 0;
+  int64_t users = 0;       // factors of queued or running requests that read it
+  bool remove_pending = false;
+};
+
+struct Request {
+  int64_t ticket = 0;
+  int kind = 0;
+  std::vector<vgicp_factor> factors;
+  std::vector<double> poses;  // [n_poses][12]
+  double *H = nullptr, *b = nullptr, *e = nullptr, *overlap = nullptr;
+  int64_t *inliers = nullptr;
+  int64_t next = 0;       // first factor not yet put in a batch
+  int64_t remaining = 0;  // factors whose outputs are not written yet
+  Clock::time_point t_submit;
+  double latency_ms = 0.0;
+  bool done = false;
+  bool failed = false;
+};
+
+// A contiguous run of one request's factors inside a batch.
+struct Chunk {
+  std::shared_ptr<Request> req;
+  int64_t first;      // factor index in the request
+  int64_t count;
+  int64_t batch_pos;  // position of the first factor in the batch
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  // device
+  FactorDesc *d_factors = nullptr;
+  Tile *d_tiles = nullptr;
+  double *d_partials = nullptr;
+  double *d_poses = nullptr;
+  double *d_H = nullptr, *d_b = nullptr, *d_e = nullptr, *d_ov = nullptr;
+  int64_t *d_inl = nullptr;
+  // pinned host staging
+  FactorDesc *h_factors = nullptr;
+  Tile *h_tiles = nullptr;
+  double *h_poses = nullptr;
+  double *h_H = nullptr, *h_b = nullptr, *h_e = nullptr, *h_ov = nullptr;
+  int64_t *h_inl = nullptr;
+  // batch in flight
+  bool busy = false;
+  bool finished = false;
+  hipError_t err = hipSuccess;
+  int kind = 0;
+  int64_t n_factors = 0;
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> frames_used;  // one entry per factor (source and target)
+  uint64_t seq = 0;
+};
+
+}  // namespace
+
+struct vgicp_server_s {
+  int device = 0;
+  vgicp_server_config cfg{};
+  int tile_points = kDefaultTile;
+  int64_t max_tiles = 0;
+  vgicp_context_s ingest;  // stream + scratch for voxelization
+  std::mutex mu;
+  std::condition_variable cv;       // worker wake-up
+  std::condition_variable done_cv;  // request completion
+  std::deque<std::shared_ptr<Request>> pending;
+  std::unordered_map<int64_t, std::shared_ptr<Request>> requests;
+  std::vector<Frame> frames;
+  std::vector<Slot> slots;
+  int64_t used_bytes = 0;
+  int64_t next_ticket = 1;
+  uint64_t batch_seq = 0;
+  bool stop = false;
+  std::thread worker;
+  std::mutex ingest_mu;  // one voxelization at a time (the ingest scratch is shared)
+  std::string last_error;
+  std::mutex err_mu;
+  // stats
+  int64_t n_batches = 0, n_completed = 0, max_req_per_batch = 0, max_inflight = 0;
+};
+
+namespace {
+
+int srv_fail(vgicp_server s, int code, const std::string &msg) {
+  if (s) {
+    std::lock_guard<std::mutex> g(s->err_mu);
+    s->last_error = msg;
+  }
+  return code;
+}
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+  return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, count) * sizeof(T));
+}
+template <typename T>
+hipError_t host_alloc(T **p, size_t count) {
+  return hipHostMalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, count) * sizeof(T),
+                       hipHostMallocDefault);
+}
+
+void free_slot(Slot &s) {
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  for (void *p : {(void *)s.d_factors, (void *)s.d_tiles, (void *)s.d_partials, (void *)s.d_poses,
+                  (void *)s.d_H, (void *)s.d_b, (void *)s.d_e, (void *)s.d_ov, (void *)s.d_inl})
+    if (p) (void)hipFree(p);
+  for (void *p : {(void *)s.h_factors, (void *)s.h_tiles, (void *)s.h_poses, (void *)s.h_H,
+                  (void *)s.h_b, (void *)s.h_e, (void *)s.h_ov, (void *)s.h_inl})
+    if (p) (void)hipHostFree(p);
+}
+
+hipError_t alloc_slot(Slot &s, int64_t F, int64_t T, int64_t P) {
+  hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = dev_alloc(&s.d_factors, F);
+  if (e == hipSuccess) e = dev_alloc(&s.d_tiles, T);
+  if (e == hipSuccess) e = dev_alloc(&s.d_partials, T * kPartialStride);
+  if (e == hipSuccess) e = dev_alloc(&s.d_poses, P * 12);
+  if (e == hipSuccess) e = dev_alloc(&s.d_H, F * 144);
+  if (e == hipSuccess) e = dev_alloc(&s.d_b, F * 12);
+  if (e == hipSuccess) e = dev_alloc(&s.d_e, F);
+  if (e == hipSuccess) e = dev_alloc(&s.d_ov, F);
+  if (e == hipSuccess) e = dev_alloc(&s.d_inl, F);
+  if (e == hipSuccess) e = host_alloc(&s.h_factors, F);
+  if (e == hipSuccess) e = host_alloc(&s.h_tiles, T);
+  if (e == hipSuccess) e = host_alloc(&s.h_poses, P * 12);
+  if (e == hipSuccess) e = host_alloc(&s.h_H, F * 144);
+  if (e == hipSuccess) e = host_alloc(&s.h_b, F * 12);
+  if (e == hipSuccess) e = host_alloc(&s.h_e, F);
+  if (e == hipSuccess) e = host_alloc(&s.h_ov, F);
+  if (e == hipSuccess) e = host_alloc(&s.h_inl, F);
+  return e;
+}
+
+struct DoneArgs {
+  vgicp_server srv;
+  size_t slot;
+};
+
+void on_batch_done(void *p) {
+  DoneArgs *a = static_cast<DoneArgs *>(p);
+  {
+    std::lock_guard<std::mutex> g(a->srv->mu);
+    a->srv->slots[a->slot].finished = true;
+  }
+  a->srv->cv.notify_all();
+  delete a;
+}
+
+int64_t request_points(const vgicp_server_s *srv, const vgicp_factor &f) {
+  return srv->frames[size_t(f.src)].n;
+}
+
+// Drop the frame references of a request that will not run.
+void release_frames_of(vgicp_server srv, const Request &r) {
+  for (int64_t k = r.next; k < int64_t(r.factors.size()); ++k) {
+    srv->frames[size_t(r.factors[size_t(k)].src)].users -= 1;
+    srv->frames[size_t(r.factors[size_t(k)].tgt)].users -= 1;
+  }
+}
+
+// Pack queued requests of the kind at the head of the queue into slot `si`
+// and launch it.  Called with the lock held.
+void launch_batch(vgicp_server srv, size_t si) {
+  Slot &s = srv->slots[si];
+  s.chunks.clear();
+  s.frames_used.clear();
+  const int kind = srv->pending.front()->kind;
+  const int64_t F = srv->cfg.max_batch_factors;
+  const int64_t Pmax = srv->cfg.max_batch_poses;
+  const int64_t tp = srv->tile_points;
+  int64_t nf = 0, nt = 0, npose = 0, npts = 0;
+  while (!srv->pending.empty()) {
+    auto req = srv->pending.front();
+    if (req->kind != kind) break;
+    const int64_t req_poses = int64_t(req->poses.size() / 12);
+    if (npose + req_poses > Pmax) break;
+    const int64_t pose_base = npose;
+    int64_t first = req->next, count = 0;
+    while (req->next < int64_t(req->factors.size()) && nf < F) {
+      const vgicp_factor &x = req->factors[size_t(req->next)];
+      const int64_t n = request_points(srv, x);
+      const int64_t tiles = (n + tp - 1) / tp;
+      if (nf > 0 && (npts + n > srv->cfg.max_batch_points || nt + tiles > srv->max_tiles)) break;
+      FactorDesc &d = s.h_factors[nf];
+      std::memset(&d, 0, sizeof(d));
+      const Frame &src = srv->frames[size_t(x.src)];
+      const Frame &tgt = srv->frames[size_t(x.tgt)];
+      d.xyz = src.cloud;
+      d.cov = src.cloud + 3 * src.n;
+      d.keys = tgt.map->keys;
+      d.payload = tgt.map->payload;
+      d.n = src.n;
+      d.pose_i = int32_t(pose_base + x.pose_i);
+      d.pose_j = int32_t(pose_base + x.pose_j);
+      d.log2cap = tgt.map->log2cap;
+      d.scale = tgt.map->scale;
+      d.tile_begin = int32_t(nt);
+      for (int64_t st = 0; st < n; st += tp) s.h_tiles[nt++] = Tile{int32_t(nf), int32_t(st)};
+      d.n_tiles = int32_t(nt - d.tile_begin);
+      s.frames_used.push_back(x.src);
+      s.frames_used.push_back(x.tgt);
+      npts += n;
+      ++nf;
+      ++count;
+      ++req->next;
+    }
+    if (count == 0) break;  // the slot is full
+    std::memcpy(s.h_poses + npose * 12, req->poses.data(), req->poses.size() * sizeof(double));
+    npose += req_poses;
+    s.chunks.push_back(Chunk{req, first, count, nf - count});
+    if (req->next == int64_t(req->factors.size())) {
+      srv->pending.pop_front();
+    } else {
+      break;  // the rest of this request goes to the next batch
+    }
+  }
+  if (nf == 0) {  // cannot happen for validated requests; never spin on one
+    auto req = srv->pending.front();
+    srv->pending.pop_front();
+    release_frames_of(srv, *req);
+    req->failed = true;
+    req->done = true;
+    ++srv->n_completed;
+    srv->done_cv.notify_all();
+    return;
+  }
+  s.kind = kind;
+  s.n_factors = nf;
+  s.busy = true;
+  s.finished = false;
+  s.err = hipSuccess;
+  s.seq = ++srv->batch_seq;
+  ++srv->n_batches;
+  srv->max_req_per_batch = std::max<int64_t>(srv->max_req_per_batch, int64_t(s.chunks.size()));
+  int64_t inflight = 0;
+  for (const Slot &o : srv->slots) inflight += o.busy ? 1 : 0;
+  srv->max_inflight = std::max(srv->max_inflight, inflight);
+
+  vgicp_factorset_s view;
+  view.device = srv->device;
+  view.n_factors = nf;
+  view.n_tiles = nt;
+  view.tile_points = int32_t(tp);
+  view.d_factors = s.d_factors;
+  view.d_tiles = s.d_tiles;
+  view.d_partials = s.d_partials;
+  const hipStream_t st = s.stream;
+  const vgicp_opts &o = srv->cfg.opts;
+  hipError_t e = hipMemcpyAsync(s.d_factors, s.h_factors, size_t(nf) * sizeof(FactorDesc),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nt > 0)
+    e = hipMemcpyAsync(s.d_tiles, s.h_tiles, size_t(nt) * sizeof(Tile), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && npose > 0)
+    e = hipMemcpyAsync(s.d_poses, s.h_poses, size_t(npose) * 12 * sizeof(double),
+                       hipMemcpyHostToDevice, st);
+  if (kind == VGICP_REQ_OVERLAP) {
+    if (e == hipSuccess) e = launch_overlap(&view, 0, nt, s.d_poses, st);
+    if (e == hipSuccess)
+      e = launch_reduce(&view, 0, nf, s.d_poses, 2, nullptr, nullptr, nullptr, s.d_inl, s.d_ov, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s.h_ov, s.d_ov, size_t(nf) * sizeof(double), hipMemcpyDeviceToHost, st);
+  } else {
+    const bool lin = kind == VGICP_REQ_LINEARIZE;
+    if (e == hipSuccess)
+      e = launch_linearize(&view, o.accum, o.resid, o.fp64_kappa, lin, 0, nt, s.d_poses, nullptr,
+                           st);
+    if (e == hipSuccess)
+      e = launch_reduce(&view, 0, nf, s.d_poses, lin ? 0 : 1, s.d_H, s.d_b, s.d_e, s.d_inl,
+                        nullptr, st);
+    if (e == hipSuccess && lin) {
+      e = hipMemcpyAsync(s.h_H, s.d_H, size_t(nf) * 144 * sizeof(double), hipMemcpyDeviceToHost,
+                         st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s.h_b, s.d_b, size_t(nf) * 12 * sizeof(double),
+                           hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s.h_e, s.d_e, size_t(nf) * sizeof(double), hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.h_inl, s.d_inl, size_t(nf) * sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipLaunchHostFunc(st, on_batch_done, new DoneArgs{srv, si});
+  if (e != hipSuccess) {
+    s.err = e;
+    s.finished = true;  // retired as failed by the worker
+  }
+}
+
+void release_frames(vgicp_server srv, const std::vector<int32_t> &used) {
+  for (int32_t f : used) srv->frames[size_t(f)].users -= 1;
+}
+
+void free_frame(Frame &fr) {
+  if (fr.map) vgicp_map_free(fr.map);
+  if (fr.cloud) (void)hipFree(fr.cloud);
+  fr = Frame();
+}
+
+// Scatter a finished batch into its requests.  Called with the lock held;
+// frames whose removal was pending are moved to `to_free` (freed by the caller
+// after it drops the lock: the completion callback takes the lock, so no
+// blocking HIP call may run under it).
+void retire(vgicp_server srv, Slot &s, std::vector<Frame> &to_free) {
+  const bool ok = s.err == hipSuccess;
+  for (const Chunk &c : s.chunks) {
+    Request &r = *c.req;
+    if (ok) {
+      for (int64_t k = 0; k < c.count; ++k) {
+        const int64_t f = c.first + k, p = c.batch_pos + k;
+        if (r.inliers) r.inliers[f] = s.h_inl[p];
+        if (s.kind == VGICP_REQ_OVERLAP) {
+          if (r.overlap) r.overlap[f] = s.h_ov[p];
+        } else {
+          if (r.e) r.e[f] = s.h_e[p];
+          if (s.kind == VGICP_REQ_LINEARIZE) {
+            std::memcpy(r.H + f * 144, s.h_H + p * 144, 144 * sizeof(double));
+            std::memcpy(r.b + f * 12, s.h_b + p * 12, 12 * sizeof(double));
+          }
+        }
+      }
+    } else {
+      r.failed = true;
+    }
+    r.remaining -= c.count;
+    if (r.remaining == 0 && !r.done) {
+      r.done = true;
+      r.latency_ms =
+          std::chrono::duration<double, std::milli>(Clock::now() - r.t_submit).count();
+      ++srv->n_completed;
+    }
+  }
+  release_frames(srv, s.frames_used);
+  for (Frame &fr : srv->frames)
+    if (fr.live && fr.remove_pending && fr.users == 0) {
+      srv->used_bytes -= fr.bytes;
+      to_free.push_back(fr);
+      fr = Frame();
+    }
+  s.chunks.clear();
+  s.frames_used.clear();
+  s.busy = false;
+  s.finished = false;
+}
+
+void worker_loop(vgicp_server srv) {
+  (void)hipSetDevice(srv->device);
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    bool progressed = false;
+    std::vector<Frame> to_free;
+    // retire finished batches
+    for (Slot &s : srv->slots) {
+      if (!s.busy || !s.finished) continue;
+      if (s.err == hipSuccess) {
+        const hipError_t q = hipStreamQuery(s.stream);
+        if (q != hipSuccess && q != hipErrorNotReady) s.err = q;
+      }
+      retire(srv, s, to_free);
+      progressed = true;
+    }
+    if (progressed) srv->done_cv.notify_all();
+    if (!to_free.empty()) {
+      lk.unlock();
+      for (Frame &fr : to_free) free_frame(fr);
+      lk.lock();
+    }
+    // admit queued requests into free slots
+    for (size_t i = 0; i < srv->slots.size() && !srv->pending.empty(); ++i) {
+      if (!srv->slots[i].busy) {
+        launch_batch(srv, i);
+        progressed = true;
+      }
+    }
+    bool any_busy = false;
+    for (const Slot &s : srv->slots) any_busy |= s.busy;
+    if (srv->stop && srv->pending.empty() && !any_busy) break;
+    if (!progressed) srv->cv.wait(lk);
+  }
+}
+
+std::shared_ptr<Request> find_request(vgicp_server srv, int64_t ticket) {
+  auto it = srv->requests.find(ticket);
+  return it == srv->requests.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server *out) {
+  if (!out || !cfg) return VGICP_EINVAL;
+  *out = nullptr;
+  if (cfg->max_batch_factors < 1 || cfg->max_batch_points < 1 || cfg->max_batch_poses < 1 ||
+      cfg->inflight < 1 || cfg->inflight > 8 || cfg->memory_budget_bytes < 0 ||
+      cfg->reserved != 0)
+    return VGICP_EINVAL;
+  int tp = cfg->tile_points ? cfg->tile_points : kDefaultTile;
+  if (tp < 256 || tp > (1 << 20) || tp % 256 != 0) return VGICP_EINVAL;
+  const vgicp_opts &o = cfg->opts;
+  if (o.accum < VGICP_ACC_F32 || o.accum > VGICP_ACC_F64 ||
+      (o.resid != VGICP_RESID_FF && o.resid != VGICP_RESID_F32) || !(o.fp64_kappa >= 0.0f) ||
+      !std::isfinite(o.fp64_kappa) || o.reserved != 0)
+    return VGICP_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VGICP_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return VGICP_EHIP;
+  auto *srv = new (std::nothrow) vgicp_server_s();
+  if (!srv) return VGICP_ENOMEM;
+  srv->device = device;
+  srv->cfg = *cfg;
+  srv->tile_points = tp;
+  srv->max_tiles = (int64_t(cfg->max_batch_points) + tp - 1) / tp + cfg->max_batch_factors;
+  srv->ingest.device = device;
+  hipError_t e = hipStreamCreateWithFlags(&srv->ingest.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&srv->ingest.err_word, 256);
+  if (e == hipSuccess) e = hipHostMalloc(&srv->ingest.host_pinned, 64, hipHostMallocDefault);
+  srv->slots.resize(size_t(cfg->inflight));
+  for (Slot &s : srv->slots)
+    if (e == hipSuccess) e = alloc_slot(s, cfg->max_batch_factors, srv->max_tiles,
+                                        cfg->max_batch_poses);
+  if (e != hipSuccess) {
+    for (Slot &s : srv->slots) free_slot(s);
+    if (srv->ingest.stream) (void)hipStreamDestroy(srv->ingest.stream);
+    if (srv->ingest.err_word) (void)hipFree(srv->ingest.err_word);
+    if (srv->ingest.host_pinned) (void)hipHostFree(srv->ingest.host_pinned);
+    delete srv;
+    return e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP;
+  }
+  srv->worker = std::thread(worker_loop, srv);
+  *out = srv;
+  return VGICP_OK;
+}
+
+int vgicp_server_destroy(vgicp_server srv) {
+  if (!srv) return VGICP_OK;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  (void)hipSetDevice(srv->device);
+  for (Slot &s : srv->slots) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    free_slot(s);
+  }
+  for (Frame &fr : srv->frames)
+    if (fr.live) free_frame(fr);
+  if (srv->ingest.stream) (void)hipStreamSynchronize(srv->ingest.stream);
+  if (srv->ingest.scratch) (void)hipFree(srv->ingest.scratch);
+  if (srv->ingest.stream) (void)hipStreamDestroy(srv->ingest.stream);
+  if (srv->ingest.err_word) (void)hipFree(srv->ingest.err_word);
+  if (srv->ingest.host_pinned) (void)hipHostFree(srv->ingest.host_pinned);
+  delete srv;
+  return VGICP_OK;
+}
+
+const char *vgicp_server_last_error(vgicp_server srv) {
+  static const char *none = "";
+  if (!srv) return "vgicp_server_last_error: server is NULL";
+  std::lock_guard<std::mutex> g(srv->err_mu);
+  return srv->last_error.empty() ? none : srv->last_error.c_str();
+}
+
+int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_cov, int64_t n,
+                           double resolution, int32_t *frame_id) {
+  if (!srv) return VGICP_EINVAL;
+  if (!frame_id) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: frame_id is NULL");
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!h_xyz || !h_cov)))
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: bad cloud");
+  if (!std::isfinite(resolution) || !(resolution > 0.0))
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: bad resolution");
+  if (hipSetDevice(srv->device) != hipSuccess)
+    return srv_fail(srv, VGICP_EHIP, "vgicp_server_add_frame: hipSetDevice");
+  Frame fr;
+  fr.n = n;
+  const size_t cloud_bytes = size_t(9) * size_t(std::max<int64_t>(n, 1)) * sizeof(float);
+  hipError_t e = hipMalloc(&fr.cloud, cloud_bytes);
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpy(fr.cloud, h_xyz, size_t(3 * n) * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpy(fr.cloud + 3 * n, h_cov, size_t(6 * n) * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (fr.cloud) (void)hipFree(fr.cloud);
+    return srv_fail(srv, e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP,
+                    std::string("vgicp_server_add_frame: ") + hipGetErrorString(e));
+  }
+  vgicp_cloud c{fr.cloud, fr.cloud + 3 * n, n};
+  std::string msg;
+  int rc;
+  {
+    std::lock_guard<std::mutex> g(srv->ingest_mu);
+    rc = voxelize_impl(&srv->ingest, &c, resolution, &fr.map, msg);
+    if (rc == VGICP_OK && hipStreamSynchronize(srv->ingest.stream) != hipSuccess) {
+      rc = VGICP_EHIP;
+      msg = "vgicp_server_add_frame: voxelization failed";
+    }
+  }
+  if (rc != VGICP_OK) {
+    (void)hipFree(fr.cloud);
+    return srv_fail(srv, rc, msg);
+  }
+  fr.bytes = int64_t(cloud_bytes) +
+             fr.map->capacity * int64_t(sizeof(uint64_t) + sizeof(Payload));
+  fr.live = true;
+  std::unique_lock<std::mutex> g(srv->mu);
+  if (srv->cfg.memory_budget_bytes > 0 && srv->used_bytes + fr.bytes > srv->cfg.memory_budget_bytes) {
+    g.unlock();
+    free_frame(fr);
+    return srv_fail(srv, VGICP_EFULL, "vgicp_server_add_frame: memory budget exceeded");
+  }
+  srv->used_bytes += fr.bytes;
+  int32_t id = -1;
+  for (size_t i = 0; i < srv->frames.size(); ++i)
+    if (!srv->frames[i].live) {
+      id = int32_t(i);
+      break;
+    }
+  if (id < 0) {
+    id = int32_t(srv->frames.size());
+    srv->frames.emplace_back();
+  }
+  srv->frames[size_t(id)] = fr;
+  *frame_id = id;
+  return VGICP_OK;
+}
+
+int vgicp_server_remove_frame(vgicp_server srv, int32_t frame_id) {
+  if (!srv) return VGICP_EINVAL;
+  Frame gone;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (frame_id < 0 || size_t(frame_id) >= srv->frames.size() ||
+        !srv->frames[size_t(frame_id)].live || srv->frames[size_t(frame_id)].remove_pending)
+      return srv_fail(srv, VGICP_EINVAL, "vgicp_server_remove_frame: unknown frame");
+    Frame &fr = srv->frames[size_t(frame_id)];
+    if (fr.users > 0) {
+      fr.remove_pending = true;  // freed when its last request retires
+      return VGICP_OK;
+    }
+    srv->used_bytes -= fr.bytes;
+    gone = fr;
+    fr = Frame();
+  }
+  (void)hipSetDevice(srv->device);
+  free_frame(gone);
+  return VGICP_OK;
+}
+
+int vgicp_server_memory(vgicp_server srv, int64_t *used_bytes, int64_t *budget_bytes) {
+  if (!srv) return VGICP_EINVAL;
+  std::lock_guard<std::mutex> g(srv->mu);
+  if (used_bytes) *used_bytes = srv->used_bytes;
+  if (budget_bytes) *budget_bytes = srv->cfg.memory_budget_bytes;
+  return VGICP_OK;
+}
+
+int vgicp_server_submit(vgicp_server srv, int kind, const vgicp_factor *factors, int64_t n,
+                        const double *h_poses, int32_t n_poses, double *H, double *b, double *e,
+                        int64_t *inliers, double *overlap, int64_t *ticket) {
+  if (!srv) return VGICP_EINVAL;
+  if (!ticket) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: ticket is NULL");
+  if (kind < VGICP_REQ_LINEARIZE || kind > VGICP_REQ_OVERLAP)
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: unknown kind");
+  if (n < 0 || (n > 0 && !factors) || n_poses < 0 || (n_poses > 0 && !h_poses))
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: bad factor or pose arrays");
+  if (n_poses > srv->cfg.max_batch_poses)
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: more poses than max_batch_poses");
+  if (n > 0 && !inliers) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: inliers is NULL");
+  if (n > 0 && kind == VGICP_REQ_LINEARIZE && (!H || !b || !e))
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: H, b or e is NULL");
+  if (n > 0 && kind == VGICP_REQ_EVALUATE && !e)
+    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: e is NULL");
+  for (int64_t k = 0; k < int64_t(n_poses) * 12; ++k)
+    if (!std::isfinite(h_poses[k]))
+      return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: non-finite pose");
+  auto req = std::make_shared<Request>();
+  req->kind = kind;
+  req->factors.assign(factors, factors + n);
+  req->poses.assign(h_poses, h_poses + size_t(n_poses) * 12);
+  req->H = H;
+  req->b = b;
+  req->e = e;
+  req->inliers = inliers;
+  req->overlap = overlap;
+  req->remaining = n;
+  req->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    for (const vgicp_factor &x : req->factors) {
+      auto bad_frame = [&](int32_t f) {
+        return f < 0 || size_t(f) >= srv->frames.size() || !srv->frames[size_t(f)].live ||
+               srv->frames[size_t(f)].remove_pending;
+      };
+      if (bad_frame(x.src) || bad_frame(x.tgt) || x.pose_i < 0 || x.pose_i >= n_poses ||
+          x.pose_j < 0 || x.pose_j >= n_poses)
+        return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: factor references an unknown "
+                                           "frame or pose");
+      if (srv->frames[size_t(x.src)].n > srv->cfg.max_batch_points)
+        return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: a source frame has more points "
+                                           "than max_batch_points");
+    }
+    for (const vgicp_factor &x : req->factors) {
+      srv->frames[size_t(x.src)].users += 1;
+      srv->frames[size_t(x.tgt)].users += 1;
+    }
+    req->ticket = srv->next_ticket++;
+    *ticket = req->ticket;
+    srv->requests[req->ticket] = req;
+    if (n == 0) {
+      req->done = true;
+      ++srv->n_completed;
+    } else {
+      srv->pending.push_back(req);
+    }
+  }
+  srv->cv.notify_all();
+  return VGICP_OK;
+}
+
+int vgicp_server_poll(vgicp_server srv, int64_t ticket, int *done) {
+  if (!srv || !done) return VGICP_EINVAL;
+  std::lock_guard<std::mutex> g(srv->mu);
+  auto r = find_request(srv, ticket);
+  if (!r) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_poll: unknown ticket");
+  *done = r->done ? 1 : 0;
+  return VGICP_OK;
+}
+
+int vgicp_server_wait(vgicp_server srv, int64_t ticket, double *latency_ms) {
+  if (!srv) return VGICP_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto r = find_request(srv, ticket);
+  if (!r) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_wait: unknown ticket");
+  srv->done_cv.wait(lk, [&] { return r->done; });
+  if (latency_ms) *latency_ms = r->latency_ms;
+  const bool failed = r->failed;
+  srv->requests.erase(ticket);
+  if (failed) return srv_fail(srv, VGICP_EHIP, "vgicp_server_wait: a batch of the request failed");
+  return VGICP_OK;
+}
+
+int vgicp_server_stats(vgicp_server srv, int64_t *batches, int64_t *requests,
+                       int64_t *max_requests_per_batch, int64_t *max_inflight) {
+  if (!srv) return VGICP_EINVAL;
+  std::lock_guard<std::mutex> g(srv->mu);
+  if (batches) *batches = srv->n_batches;
+  if (requests) *requests = srv->n_completed;
+  if (max_requests_per_batch) *max_requests_per_batch = srv->max_req_per_batch;
+  if (max_inflight) *max_inflight = srv->max_inflight;
+  return VGICP_OK;
+}
+
+}  // extern "C"

@@ -125,6 +125,7 @@ struct GraphEntry {
   int32_t *corr;
   int accum;
   int resid;
+  float kappa;
   int kind;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -21,7 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvgicp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vgicp.h")
 
-OK, EINVAL, ENOMEM, ERANGE, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, ERANGE, ENONFINITE, EHIP, EFULL = 0, -1, -2, -3, -4, -5, -6
+REQ = {"linearize": 0, "evaluate": 1, "overlap": 2}
 ACC = {"f32": 0, "f32_comp": 1, "f64": 2}
 KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
@@ -45,7 +46,15 @@ class CFactor(ctypes.Structure):
 
 class COpts(ctypes.Structure):
     _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32),
+                ("fp64_kappa", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch_factors", ctypes.c_int32),
+                ("max_batch_points", ctypes.c_int32), ("max_batch_poses", ctypes.c_int32),
+                ("inflight", ctypes.c_int32), ("tile_points", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("opts", COpts)]
 
 
 _vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -73,6 +82,17 @@ _PROTOS = {
     "vgicp_linearize_factors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp]),
     "vgicp_evaluate_errors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp]),
     "vgicp_overlap": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vgicp_server_create": (ctypes.c_int, [ctypes.c_int, _P(CServerConfig), _P(_vp)]),
+    "vgicp_server_destroy": (ctypes.c_int, [_vp]),
+    "vgicp_server_last_error": (ctypes.c_char_p, [_vp]),
+    "vgicp_server_add_frame": (ctypes.c_int, [_vp, _vp, _vp, _i64, _dbl, _P(_i32)]),
+    "vgicp_server_remove_frame": (ctypes.c_int, [_vp, _i32]),
+    "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
+    "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
+                                           _vp, _vp, _vp, _vp, _P(_i64)]),
+    "vgicp_server_poll": (ctypes.c_int, [_vp, _i64, _P(ctypes.c_int)]),
+    "vgicp_server_wait": (ctypes.c_int, [_vp, _i64, _P(_dbl)]),
+    "vgicp_server_stats": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)]),
 }
 
 
@@ -333,14 +353,16 @@ class FactorSet:
             pass
 
 
-def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "ff") -> COpts:
+def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "ff",
+          fp64_kappa: float = 0.0) -> COpts:
     if accum not in ACC:
         raise ValueError(f"accum must be one of {sorted(ACC)}")
     if schedule not in SCHED:
         raise ValueError(f"schedule must be one of {sorted(SCHED)}")
     if resid not in RESID:
         raise ValueError(f"resid must be one of {sorted(RESID)}")
-    return COpts(ACC[accum], SCHED[schedule], int(bool(use_graph)), RESID[resid])
+    return COpts(ACC[accum], SCHED[schedule], int(bool(use_graph)), RESID[resid],
+                 float(fp64_kappa), 0)
 
 
 def _check_poses(fs: FactorSet, poses):
@@ -350,7 +372,8 @@ def _check_poses(fs: FactorSet, poses):
 
 def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                       schedule: str = "batched", use_graph: bool = False,
-                      with_corr: bool = False, out=None, resid: str = "ff"):
+                      with_corr: bool = False, out=None, resid: str = "ff",
+                      fp64_kappa: float = 0.0):
     """Hessian factors of every factor at `poses` (float64 (P, 12) device).
     Returns dict of device tensors H (F,12,12), b (F,12), e (F,), inliers (F,)
     and corr (total_points,) when asked.  `out` may supply the same dict of
@@ -373,7 +396,7 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     corr = out.get("corr")
     if corr is not None:
         _dev_tensor(corr, torch.int32, (fs.total_points,), "corr")
-    o = _opts(accum, schedule, use_graph, resid)
+    o = _opts(accum, schedule, use_graph, resid, fp64_kappa)
     _check(_lib.vgicp_linearize_factors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                         out["H"].data_ptr(), out["b"].data_ptr(),
                                         out["e"].data_ptr(), out["inliers"].data_ptr(),
@@ -384,7 +407,7 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
 
 def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                     schedule: str = "batched", use_graph: bool = False, out=None,
-                    resid: str = "ff"):
+                    resid: str = "ff", fp64_kappa: float = 0.0):
     """Matching cost e (F,) and inliers (F,) without Jacobians."""
     torch = _torch()
     _check_poses(fs, poses)
@@ -393,7 +416,7 @@ def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     if out is None:
         out = {"e": torch.empty((F,), dtype=torch.float64, device=dev),
                "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
-    o = _opts(accum, schedule, use_graph, resid)
+    o = _opts(accum, schedule, use_graph, resid, fp64_kappa)
     _check(_lib.vgicp_evaluate_errors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                       out["e"].data_ptr(), out["inliers"].data_ptr()), ctx.handle)
     return out
@@ -411,3 +434,105 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
     _check(_lib.vgicp_overlap(ctx.handle, fs.handle, poses.data_ptr(), out["hits"].data_ptr(),
                               out["overlap"].data_ptr()), ctx.handle)
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+
+class ServerRequest:
+    """A submitted request: host output arrays are filled when it completes."""
+
+    def __init__(self, server, kind, n):
+        self.server = server
+        self.kind = kind
+        self.inliers = np.zeros(n, dtype=np.int64)
+        self.e = np.zeros(n, dtype=np.float64)
+        self.H = np.zeros((n, 12, 12), dtype=np.float64) if kind == "linearize" else None
+        self.b = np.zeros((n, 12), dtype=np.float64) if kind == "linearize" else None
+        self.overlap = np.zeros(n, dtype=np.float64) if kind == "overlap" else None
+        self.ticket = None
+        self.latency_ms = None
+
+    def done(self) -> bool:
+        d = ctypes.c_int()
+        _check_srv(_lib.vgicp_server_poll(self.server._h, self.ticket, ctypes.byref(d)), self.server)
+        return bool(d.value)
+
+    def wait(self):
+        lat = ctypes.c_double()
+        _check_srv(_lib.vgicp_server_wait(self.server._h, self.ticket, ctypes.byref(lat)), self.server)
+        self.latency_ms = lat.value
+        return self
+
+
+def _check_srv(code, server):
+    if code != OK:
+        msg = _lib.vgicp_server_last_error(server._h if server is not None else None)
+        raise VgicpError(code, msg.decode() if msg else "")
+
+
+class Server:
+    """Continuous-batching server over resident keyframes (vgicp_server_*).
+
+    Frames are host clouds (xyz (n,3), cov (n,6) float32) copied to the device
+    and voxelized once; requests over frame ids and host poses are batched by
+    the library's worker thread."""
+
+    def __init__(self, device=0, memory_budget_bytes=0, max_batch_factors=4096,
+                 max_batch_points=1 << 27, max_batch_poses=65536, inflight=2, tile_points=0,
+                 accum="f32", resid="ff", fp64_kappa=0.0):
+        cfg = CServerConfig(int(memory_budget_bytes), int(max_batch_factors), int(max_batch_points),
+                            int(max_batch_poses), int(inflight), int(tile_points), 0,
+                            _opts(accum, "batched", False, resid, fp64_kappa))
+        h = ctypes.c_void_p()
+        code = _lib.vgicp_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
+        if code != OK:
+            raise VgicpError(code, "vgicp_server_create failed")
+        self._h = h
+        self._requests = []
+
+    def add_frame(self, xyz, cov, resolution: float) -> int:
+        x = np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(-1, 3).T)
+        c = np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6).T)
+        fid = ctypes.c_int32()
+        _check_srv(_lib.vgicp_server_add_frame(self._h, x.ctypes.data, c.ctypes.data, x.shape[1],
+                                               float(resolution), ctypes.byref(fid)), self)
+        return fid.value
+
+    def remove_frame(self, frame_id: int):
+        _check_srv(_lib.vgicp_server_remove_frame(self._h, int(frame_id)), self)
+
+    def memory(self):
+        used, budget = ctypes.c_int64(), ctypes.c_int64()
+        _check_srv(_lib.vgicp_server_memory(self._h, ctypes.byref(used), ctypes.byref(budget)), self)
+        return used.value, budget.value
+
+    def submit(self, kind: str, factors, poses) -> ServerRequest:
+        arr, n = _factor_array(factors)
+        p = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 12))
+        r = ServerRequest(self, kind, n)
+        t = ctypes.c_int64()
+        ptr = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
+        r._keep = (arr, p)
+        _check_srv(_lib.vgicp_server_submit(self._h, REQ[kind], arr, n, p.ctypes.data, p.shape[0],
+                                            ptr(r.H), ptr(r.b), ptr(r.e), ptr(r.inliers),
+                                            ptr(r.overlap), ctypes.byref(t)), self)
+        r.ticket = t.value
+        return r
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check_srv(_lib.vgicp_server_stats(self._h, *[ctypes.byref(x) for x in v]), self)
+        return {"batches": v[0].value, "requests": v[1].value,
+                "max_requests_per_batch": v[2].value, "max_inflight": v[3].value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.vgicp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

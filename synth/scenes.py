@@ -454,3 +454,38 @@ def make_scan_workload(cfg: int, n_frames: int, n_factors: int,
         resolution=resolution, sources=sources, targets=targets,
         poses=pose_rows(T_est), factors=np.array(factors, dtype=np.int32),
         meta=meta)
+
+
+def _scan_frame_subsampled(args):
+    """Worker: one frame's scan, k-NN covariances on the full scan, then a
+    random subsample of n_points kept in scan order (FP32)."""
+    scene, T, seed, k, n_points = args
+    rng = np.random.default_rng(seed)
+    pts, _ = raycast_scan(scene, T, rng)
+    cov = knn_covariances(pts, k)
+    if pts.shape[0] < n_points:
+        raise RuntimeError(f"frame has only {pts.shape[0]} returns (< {n_points})")
+    sel = np.sort(rng.choice(pts.shape[0], n_points, replace=False))
+    return _f32_cloud(pts[sel], cov[sel])
+
+
+def stream_scan_frames(cfg: int, n_frames: int, n_points: int = 20000, k: int = 20,
+                       workers: int | None = None, spacing: float = 1.0):
+    """Yield (index, estimated pose 4x4, xyz float32 (n,3), cov float32 (n,6))
+    for keyframes `spacing` metres apart along a corridor, generated in a
+    process pool and returned in order (memory stays bounded by the pool)."""
+    rng = rng_for(cfg)
+    scene = Corridor(rng, float(n_frames) * spacing, continuous=False)
+    T_gt = [scene.sensor_pose(f * spacing) for f in range(n_frames)]
+    T_est = [T @ random_perturbation(rng) for T in T_gt]
+    seeds = rng.integers(0, 2**63 - 1, size=n_frames)
+    jobs = [(scene, T_gt[f], int(seeds[f]), k, n_points) for f in range(n_frames)]
+    w = workers or default_workers()
+    if w <= 1:
+        for f, job in enumerate(jobs):
+            xyz, cov = _scan_frame_subsampled(job)
+            yield f, T_est[f], xyz, cov
+        return
+    with ProcessPoolExecutor(max_workers=w) as ex:
+        for f, (xyz, cov) in enumerate(ex.map(_scan_frame_subsampled, jobs, chunksize=4)):
+            yield f, T_est[f], xyz, cov

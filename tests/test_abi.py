@@ -92,3 +92,27 @@ def test_library_shares_the_hip_runtime_of_torch():
     with open(f"/proc/{os.getpid()}/maps") as fh:
         libs = {line.split()[-1] for line in fh if "libamdhip64" in line}
     assert len(libs) == 1, libs
+
+
+def test_server_rejects_bad_config_and_null_handles():
+    lib = vg.lib()
+    h = ctypes.c_void_p()
+    opts = vg.COpts(0, 0, 0, 0, 0.0, 0)
+    bad = [
+        vg.CServerConfig(0, 0, 1000, 16, 2, 0, 0, opts),      # max_batch_factors
+        vg.CServerConfig(0, 16, 0, 16, 2, 0, 0, opts),        # max_batch_points
+        vg.CServerConfig(0, 16, 1000, 16, 0, 0, 0, opts),     # inflight
+        vg.CServerConfig(0, 16, 1000, 16, 9, 0, 0, opts),     # inflight
+        vg.CServerConfig(-1, 16, 1000, 16, 2, 0, 0, opts),    # budget
+        vg.CServerConfig(0, 16, 1000, 16, 2, 100, 0, opts),   # tile_points
+        vg.CServerConfig(0, 16, 1000, 16, 2, 0, 0, vg.COpts(7, 0, 0, 0, 0.0, 0)),
+    ]
+    for cfg in bad:
+        assert lib.vgicp_server_create(0, ctypes.byref(cfg), ctypes.byref(h)) == vg.EINVAL
+    assert lib.vgicp_server_create(0, None, ctypes.byref(h)) == vg.EINVAL
+    assert lib.vgicp_server_destroy(None) == vg.OK
+    assert lib.vgicp_server_memory(None, None, None) == vg.EINVAL
+    assert lib.vgicp_server_poll(None, 1, None) == vg.EINVAL
+    assert lib.vgicp_server_wait(None, 1, None) == vg.EINVAL
+    assert lib.vgicp_server_remove_frame(None, 0) == vg.EINVAL
+    assert lib.vgicp_server_stats(None, None, None, None, None) == vg.EINVAL
