@@ -232,6 +232,29 @@ int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses
                           const vgicp_opts *opts, double *e, int64_t *inliers);
 
 /* --------------------------------------------------------------------------
+ * Assembly of the linearized system (Sec. III-D: the optimizer collects the
+ * per-factor results into one linear system).  With one 6-vector per pose in
+ * (omega, rho) order, every factor (i, j) adds H_ii to block (i, i), H_jj to
+ * (j, j), H_ij to (i, j), H_ij^T to (j, i), b_i to pose i and b_j to pose j
+ * (a factor with i == j adds all four blocks to (i, i)).  Sums run in factor
+ * order in FP64, so the result is deterministic.
+ * ------------------------------------------------------------------------ */
+
+/* Number of distinct unordered pose pairs {i, j}, i != j, of the factor set
+ * and, if `pairs` is not NULL, the pairs as host int32 [n_pairs][2] with
+ * pairs[k][0] < pairs[k][1], in increasing lexicographic order.  Errors: EINVAL. */
+int vgicp_factorset_pairs(vgicp_factorset fs, int64_t *n_pairs, int32_t *pairs);
+
+/* Assemble from per-factor H (device float64 [n_factors][12][12]) and b
+ * (device float64 [n_factors][12]), as written by vgicp_linearize_factors:
+ * Hdiag device float64 [n_poses][6][6], bvec device float64 [n_poses][6], and
+ * Hoff device float64 [n_pairs][6][6] (may be NULL) holding block (p, q) of
+ * pair k = (p, q) (block (q, p) is its transpose).  Poses no factor touches
+ * get zeros.  Errors: EINVAL, EHIP. */
+int vgicp_assemble_system(vgicp_ctx ctx, vgicp_factorset fs, const double *H, const double *b,
+                          double *Hdiag, double *bvec, double *Hoff);
+
+/* --------------------------------------------------------------------------
  * Overlap (Sec. III-B, Eqs. (7)-(8)): for each factor row (i, j), hits = number
  * of source points falling in a voxel of the target map under T_j^-1 T_i and
  * overlap = hits / N (0 when N = 0).

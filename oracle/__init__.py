@@ -18,4 +18,6 @@ from .vgicp_oracle import (  # noqa: F401
     linearize_workload,
     overlap_workload,
     build_maps,
+    assemble_system,
+    system_blocks,
 )

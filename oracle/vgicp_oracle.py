@@ -15,6 +15,8 @@ GPU-accelerated GICP Matching Cost Factors", IEEE RA-L 2021.
   linearize_factor  Sec. III-A, Eqs. (2)-(6): error, Hessian factor, b
   evaluate_factor   Sec. III-A, Eq. (3): the matching cost alone
   overlap_factor    Sec. III-B, Eqs. (7)-(8): voxel overlap rate
+  assemble_system   Sec. III-D: the factors' Hessians summed into the
+                    global linear system over all poses
 
 Readings where the paper is silent (each one is also a line of the design
 notes):
@@ -352,3 +354,36 @@ def overlap_workload(sources, maps, poses, factors):
     for f, (s, tg, pi, pj) in enumerate(factors):
         hits[f], ov[f] = overlap_factor(sources[s][0], maps[tg], poses[pi], poses[pj])
     return hits, ov
+
+
+# --------------------------------------------------------------------------
+# assembly of the global linear system (Sec. III-D)
+# --------------------------------------------------------------------------
+
+def assemble_system(H, b, factors, n_poses: int):
+    """Global Gauss-Newton system over all poses, 6 unknowns (omega, rho) per
+    pose.  Factor f with poses (i, j) maps the global perturbation to its own
+    12-vector through the selection S_f = [E_i; E_j] (E_p picks pose p's six
+    unknowns), so it adds S_f^T H_f S_f to the global matrix and S_f^T b_f to
+    the global vector.  Returns the dense (6P, 6P) matrix and (6P,) vector."""
+    factors = np.asarray(factors).reshape(-1, 4)
+    P6 = 6 * int(n_poses)
+    Hg = np.zeros((P6, P6))
+    bg = np.zeros(P6)
+    for f, (_, _, pi, pj) in enumerate(factors):
+        S = np.zeros((12, P6))
+        S[0:6, 6 * pi:6 * pi + 6] += np.eye(6)
+        S[6:12, 6 * pj:6 * pj + 6] += np.eye(6)
+        Hg += S.T @ np.asarray(H[f], np.float64) @ S
+        bg += S.T @ np.asarray(b[f], np.float64)
+    return Hg, bg
+
+
+def system_blocks(Hg, bg, n_poses: int, pairs):
+    """Diagonal 6x6 blocks, per-pose b and the (p, q) blocks of the listed
+    pose pairs, read out of the dense system."""
+    P = int(n_poses)
+    diag = np.stack([Hg[6 * p:6 * p + 6, 6 * p:6 * p + 6] for p in range(P)]) if P else np.zeros((0, 6, 6))
+    bvec = bg.reshape(P, 6)
+    off = np.stack([Hg[6 * p:6 * p + 6, 6 * q:6 * q + 6] for (p, q) in pairs]) if len(pairs) else np.zeros((0, 6, 6))
+    return diag, bvec, off

@@ -886,6 +886,53 @@ k_reduce(const FactorDesc *__restrict__ factors, int64_t factor_base,
   }
 }
 
+// ---------------------------------------------------------------- assembly
+// One 64-lane block per pose: lanes 0..35 own an entry of the 6x6 diagonal
+// block, lanes 36..41 an entry of b.  Contributions are added in CSR order
+// (factor order), so the sums are deterministic.  An entry is factor * 4 +
+// side (0: the pose is the factor's pose i, 1: pose j) + 2 when the factor's
+// two poses coincide; such a factor's pose-i entry also adds H_ij + H_ij^T.
+__global__ void __launch_bounds__(64)
+k_assemble_diag(const int64_t *__restrict__ off, const int64_t *__restrict__ ent,
+                const double *__restrict__ H, const double *__restrict__ b,
+                double *__restrict__ Hdiag, double *__restrict__ bvec) {
+  const int p = blockIdx.x, lane = threadIdx.x;
+  if (lane >= 42) return;
+  double acc = 0.0;
+  for (int64_t k = off[p]; k < off[p + 1]; ++k) {
+    const int64_t f = ent[k] >> 2;
+    const int o = 6 * (ent[k] & 1);
+    if (lane < 36) {
+      const int r = lane / 6, c = lane % 6;
+      acc += H[f * 144 + (o + r) * 12 + (o + c)];
+      if (ent[k] & 2) acc += H[f * 144 + r * 12 + (6 + c)] + H[f * 144 + (6 + r) * 12 + c];
+    } else {
+      acc += b[f * 12 + o + (lane - 36)];
+    }
+  }
+  if (lane < 36)
+    Hdiag[int64_t(p) * 36 + lane] = acc;
+  else
+    bvec[int64_t(p) * 6 + (lane - 36)] = acc;
+}
+
+// One 64-lane block per unordered pose pair (p, q), p < q: block (p, q) is the
+// sum of H_ij over factors (i, j) = (p, q) and of H_ij^T over (i, j) = (q, p).
+__global__ void __launch_bounds__(64)
+k_assemble_pairs(const int64_t *__restrict__ off, const int64_t *__restrict__ ent,
+                 const double *__restrict__ H, double *__restrict__ Hoff) {
+  const int q = blockIdx.x, lane = threadIdx.x;
+  if (lane >= 36) return;
+  const int r = lane / 6, c = lane % 6;
+  double acc = 0.0;
+  for (int64_t k = off[q]; k < off[q + 1]; ++k) {
+    const int64_t f = ent[k] >> 1;
+    const bool flip = ent[k] & 1;
+    acc += flip ? H[f * 144 + (6 + r) * 12 + c] : H[f * 144 + r * 12 + (6 + c)];
+  }
+  Hoff[int64_t(q) * 36 + lane] = acc;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned xcd_grid(int64_t tiles) { return unsigned(((tiles + 7) / 8) * 8); }
 
@@ -944,6 +991,22 @@ hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
   k_overlap<<<xcd_grid(te - tb), kBlock, 0, st>>>(fs->d_factors, fs->d_tiles, tb, te,
                                                    fs->tile_points, poses, fs->d_partials);
   return hipGetLastError();
+}
+
+hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const double *b,
+                           double *Hdiag, double *bvec, double *Hoff, hipStream_t st) {
+  if (fs->n_poses > 0) {
+    k_assemble_diag<<<unsigned(fs->n_poses), 64, 0, st>>>(fs->d_pose_off, fs->d_pose_ent, H, b,
+                                                         Hdiag, bvec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (Hoff && fs->n_pairs > 0) {
+    k_assemble_pairs<<<unsigned(fs->n_pairs), 64, 0, st>>>(fs->d_pair_off, fs->d_pair_ent, H,
+                                                           Hoff);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,

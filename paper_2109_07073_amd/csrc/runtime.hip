@@ -22,6 +22,8 @@ hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
                          int mode, double *H, double *b, double *e, int64_t *inl,
                          double *overlap, hipStream_t st);
+hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const double *b,
+                           double *Hdiag, double *bvec, double *Hoff, hipStream_t st);
 }  // namespace vgicp
 
 using namespace vgicp;
@@ -349,6 +351,42 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   }
   fs->n_tiles = int64_t(tiles.size());
 
+  // CSR of system-assembly contributions (factor order within each pose/pair)
+  std::vector<int64_t> pose_off(size_t(n_poses) + 1, 0), pose_ent;
+  {
+    std::vector<std::vector<int64_t>> per(static_cast<size_t>(n_poses));
+    for (int64_t f = 0; f < n_factors; ++f) {
+      const bool self = factors[f].pose_i == factors[f].pose_j;
+      per[size_t(factors[f].pose_i)].push_back(4 * f + (self ? 2 : 0));
+      per[size_t(factors[f].pose_j)].push_back(4 * f + 1);
+    }
+    for (int32_t p = 0; p < n_poses; ++p) {
+      pose_off[size_t(p) + 1] = pose_off[size_t(p)] + int64_t(per[size_t(p)].size());
+      pose_ent.insert(pose_ent.end(), per[size_t(p)].begin(), per[size_t(p)].end());
+    }
+  }
+  std::vector<int64_t> pair_off(1, 0), pair_ent;
+  {
+    std::vector<std::pair<std::pair<int32_t, int32_t>, int64_t>> keyed;
+    for (int64_t f = 0; f < n_factors; ++f) {
+      const int32_t i = factors[f].pose_i, j = factors[f].pose_j;
+      if (i == j) continue;
+      keyed.push_back({{std::min(i, j), std::max(i, j)}, 2 * f + (i > j ? 1 : 0)});
+    }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const auto &x, const auto &y) { return x.first < y.first; });
+    for (size_t k = 0; k < keyed.size(); ++k) {
+      if (k > 0 && keyed[k].first != keyed[k - 1].first) pair_off.push_back(int64_t(k));
+      if (k == 0 || keyed[k].first != keyed[k - 1].first) {
+        fs->h_pairs.push_back(keyed[k].first.first);
+        fs->h_pairs.push_back(keyed[k].first.second);
+      }
+      pair_ent.push_back(keyed[k].second);
+    }
+    if (!keyed.empty()) pair_off.push_back(int64_t(keyed.size()));
+    fs->n_pairs = int64_t(fs->h_pairs.size() / 2);
+  }
+
   hipError_t e = hipSuccess;
   const size_t fbytes = std::max<size_t>(1, fs->h_factors.size()) * sizeof(FactorDesc);
   const size_t tbytes = std::max<size_t>(1, tiles.size()) * sizeof(Tile);
@@ -362,6 +400,17 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpyAsync(fs->d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
                        hipMemcpyHostToDevice, ctx->stream);
+  auto upload = [&](int64_t **d, const std::vector<int64_t> &h) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(d, std::max<size_t>(1, h.size()) * sizeof(int64_t));
+    if (e == hipSuccess && !h.empty())
+      e = hipMemcpyAsync(*d, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                         ctx->stream);
+  };
+  upload(&fs->d_pose_off, pose_off);
+  upload(&fs->d_pose_ent, pose_ent);
+  upload(&fs->d_pair_off, pair_off);
+  upload(&fs->d_pair_ent, pair_ent);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     vgicp_factorset_destroy(fs);
@@ -390,6 +439,8 @@ int vgicp_factorset_destroy(vgicp_factorset fs) {
   if (fs->d_factors) (void)hipFree(fs->d_factors);
   if (fs->d_tiles) (void)hipFree(fs->d_tiles);
   if (fs->d_partials) (void)hipFree(fs->d_partials);
+  for (int64_t *p : {fs->d_pose_off, fs->d_pose_ent, fs->d_pair_off, fs->d_pair_ent})
+    if (p) (void)hipFree(p);
   delete fs;
   return VGICP_OK;
 }
@@ -560,6 +611,36 @@ int vgicp_overlap(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, int64_
     t.done();
   }
   if (err != hipSuccess) return hip_fail(ctx, who, err);
+  return VGICP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int vgicp_factorset_pairs(vgicp_factorset fs, int64_t *n_pairs, int32_t *pairs) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_pairs: fs is NULL");
+  if (n_pairs) *n_pairs = fs->n_pairs;
+  if (pairs && fs->n_pairs > 0)
+    std::memcpy(pairs, fs->h_pairs.data(), fs->h_pairs.size() * sizeof(int32_t));
+  return VGICP_OK;
+}
+
+int vgicp_assemble_system(vgicp_ctx ctx, vgicp_factorset fs, const double *H, const double *b,
+                          double *Hdiag, double *bvec, double *Hoff) {
+  const char *who = "vgicp_assemble_system";
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  if (fs->n_factors > 0 && (!H || !b))
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": H or b is NULL");
+  if (fs->n_poses > 0 && (!Hdiag || !bvec))
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": Hdiag or bvec is NULL");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  hipError_t e = launch_assemble(fs, H, b, Hdiag, bvec, Hoff, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
   return VGICP_OK;
 }
 

@@ -143,4 +143,13 @@ struct vgicp_factorset_s {
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
   std::vector<vgicp::FactorDesc> h_factors;
   std::vector<GraphEntry> graphs;
+  // System assembly: contributions to each pose (CSR over poses, entries are
+  // factor * 4 + side (0 = as pose i, 1 = as pose j) + 2 for a factor whose
+  // two poses coincide, on its pose-i entry) and to each
+  // unordered pose pair (CSR over pairs, entries factor * 2 + flip, flip 1
+  // when the factor's (i, j) is the pair's (q, p)).
+  std::vector<int32_t> h_pairs;   // [n_pairs][2]
+  int64_t n_pairs = 0;
+  int64_t *d_pose_off = nullptr, *d_pose_ent = nullptr;
+  int64_t *d_pair_off = nullptr, *d_pair_ent = nullptr;
 };

@@ -78,6 +78,8 @@ _PROTOS = {
                                               _i64, _i32, _i32, _P(_vp)]),
     "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "vgicp_factorset_destroy": (ctypes.c_int, [_vp]),
+    "vgicp_factorset_pairs": (ctypes.c_int, [_vp, _P(_i64), _vp]),
+    "vgicp_assemble_system": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vgicp_validate_factors": (ctypes.c_int, [_i32, _i32, _i32, _P(CFactor), _i64]),
     "vgicp_linearize_factors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp]),
     "vgicp_evaluate_errors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp]),
@@ -336,6 +338,12 @@ class FactorSet:
         self.n_factors, self.n_tiles, self.total_points = a.value, b.value, c.value
         self.source_sizes = np.array([int(self._sources[s][0].shape[1]) for s in self.factors[:, 0]],
                                      dtype=np.int64)
+        n = ctypes.c_int64()
+        _check(_lib.vgicp_factorset_pairs(h, ctypes.byref(n), None))
+        self.pairs = np.zeros((n.value, 2), dtype=np.int32)
+        if n.value:
+            _check(_lib.vgicp_factorset_pairs(h, ctypes.byref(n),
+                                              self.pairs.ctypes.data_as(ctypes.c_void_p)))
 
     @property
     def handle(self):
@@ -433,6 +441,34 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
                "overlap": torch.empty((F,), dtype=torch.float64, device=dev)}
     _check(_lib.vgicp_overlap(ctx.handle, fs.handle, poses.data_ptr(), out["hits"].data_ptr(),
                               out["overlap"].data_ptr()), ctx.handle)
+    return out
+
+
+def assemble_system(ctx: Context, fs: FactorSet, H, b, out=None, with_offdiag: bool = True):
+    """Global system blocks from per-factor H (F,12,12) and b (F,12) device
+    float64 tensors: Hdiag (P,6,6), bvec (P,6) and, when asked, Hoff (K,6,6)
+    for the pose pairs fs.pairs (K,2) (Sec. III-D)."""
+    torch = _torch()
+    dev = f"cuda:{ctx.device}"
+    F, P, K = fs.n_factors, fs.n_poses, fs.pairs.shape[0]
+    _dev_tensor(H, torch.float64, (F, 12, 12), "H")
+    _dev_tensor(b, torch.float64, (F, 12), "b")
+    if out is None:
+        out = {"Hdiag": torch.empty((P, 6, 6), dtype=torch.float64, device=dev),
+               "bvec": torch.empty((P, 6), dtype=torch.float64, device=dev)}
+        if with_offdiag:
+            out["Hoff"] = torch.empty((K, 6, 6), dtype=torch.float64, device=dev)
+    _dev_tensor(out["Hdiag"], torch.float64, (P, 6, 6), "Hdiag")
+    _dev_tensor(out["bvec"], torch.float64, (P, 6), "bvec")
+    hoff = out.get("Hoff")
+    if hoff is not None:
+        _dev_tensor(hoff, torch.float64, (K, 6, 6), "Hoff")
+    _check(_lib.vgicp_assemble_system(ctx.handle, fs.handle, H.data_ptr() if F else None,
+                                      b.data_ptr() if F else None,
+                                      out["Hdiag"].data_ptr() if P else None,
+                                      out["bvec"].data_ptr() if P else None,
+                                      hoff.data_ptr() if (hoff is not None and K) else None),
+           ctx.handle)
     return out
 
 

@@ -168,3 +168,69 @@ def rel_err(a, b):
     b = np.asarray(b, np.float64)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+def small_pose_graph(seed=5, n_poses=4):
+    """Four nearby poses and room clouds, with factors that exercise every
+    case of the assembly: distinct pairs, a pair repeated, the same pair
+    reversed, and a factor whose two poses coincide."""
+    from synth import make_tiny_workload, pose_rows
+    from synth.scenes import random_perturbation, rng_for
+    w = make_tiny_workload(seed=seed, n_src=300, n_tgt=500, resolution=0.5, n_factors=3)
+    rng = rng_for(300, seed)
+    T = [np.eye(4)] + [random_perturbation(rng, 0.15, 3.0) for _ in range(n_poses - 1)]
+    w.poses = pose_rows(T)
+    w.factors = np.array([[0, 1, 0, 1], [1, 2, 1, 2], [2, 0, 3, 0], [0, 2, 1, 0],
+                          [1, 0, 0, 1], [2, 1, 2, 2], [1, 2, 3, 1]], dtype=np.int32)
+    return w
+
+
+def fd_global_system(w, h=1e-6):
+    """Global H, b over all poses from finite differences of each factor's
+    frozen residual in the 6P-vector of pose perturbations (each factor sees
+    its own two poses' slices; a factor on one pose sees that slice twice)."""
+    P = w.poses.shape[0]
+    maps = oracle.build_maps(w.targets, w.resolution)
+    Hg = np.zeros((6 * P, 6 * P))
+    bg = np.zeros(6 * P)
+    for (s, tg, pi, pj) in w.factors:
+        xyz, cov = w.sources[s]
+        out = oracle.linearize_factor(xyz, cov, maps[tg], w.poses[pi], w.poses[pj])
+        hit = out["corr"] >= 0
+        Ti, Tj = hom(w.poses[pi]), hom(w.poses[pj])
+        R = (np.linalg.inv(Tj) @ Ti)[:3, :3]
+        mu = np.asarray(xyz, np.float64)[hit]
+        m = maps[tg].mean[out["corr"][hit]].astype(np.float64)
+        cs = np.asarray(cov, np.float64)[hit]
+        vc = maps[tg].cov[out["corr"][hit]].astype(np.float64)
+        Om = np.stack([np.linalg.inv(unpack6(vc[k]) + R @ unpack6(cs[k]) @ R.T)
+                       for k in range(mu.shape[0])])
+
+        def resid(x):
+            return frozen_residuals(np.concatenate([x[6 * pi:6 * pi + 6], x[6 * pj:6 * pj + 6]]),
+                                    Ti, Tj, mu, m)
+        J = np.zeros((mu.shape[0], 3, 6 * P))
+        for a in range(6 * P):
+            d = np.zeros(6 * P)
+            d[a] = h
+            J[:, :, a] = (resid(d) - resid(-d)) / (2 * h)
+        r0 = resid(np.zeros(6 * P))
+        Hg += np.einsum("nai,nab,nbj->ij", J, Om, J)
+        bg += np.einsum("nai,nab,nb->i", J, Om, r0)
+    return Hg, bg
+
+
+def global_null_space(poses):
+    """Columns Ad(T_p^-1) eta stacked over all poses, for the six unit eta:
+    a common left motion of every pose leaves every relative pose unchanged."""
+    cols = []
+    for p in poses:
+        Ti = np.linalg.inv(hom(p))
+        R, t = Ti[:3, :3], Ti[:3, 3]
+        S = np.array([[0, -t[2], t[1]], [t[2], 0, -t[0]], [-t[1], t[0], 0]])
+        A = np.zeros((6, 6))
+        A[:3, :3] = R
+        A[3:, :3] = S @ R
+        A[3:, 3:] = R
+        cols.append(A)
+    return np.vstack(cols)

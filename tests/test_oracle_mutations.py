@@ -143,3 +143,53 @@ def test_planted_mistake_is_caught(monkeypatch, name, fn):
     if name in ("relative_pose", "voxelize"):
         monkeypatch.setattr(oracle, name, fn)
     assert not _pins_hold()
+
+
+# ----------------------------------------------------------------- assembly
+
+def _assembly_pins_hold() -> bool:
+    from tests.oracle_pins import fd_global_system, global_null_space, small_pose_graph
+    w = small_pose_graph(seed=6)
+    maps = oracle.build_maps(w.targets, w.resolution)
+    ref = oracle.linearize_workload(w.sources, maps, w.poses, w.factors)
+    Hg, bg = oracle.assemble_system(ref["H"], ref["b"], w.factors, w.poses.shape[0])
+    Hfd, bfd = fd_global_system(w)
+    N = global_null_space(w.poses)
+    return (rel_err(Hg, Hfd) < 1e-7 and rel_err(bg, bfd) < 1e-7
+            and np.linalg.norm(Hg @ N) <= 1e-10 * np.linalg.norm(Hg) * np.linalg.norm(N))
+
+
+def _asm_poses_swapped(H, b, factors, P):
+    f = np.asarray(factors).copy()
+    f[:, [2, 3]] = f[:, [3, 2]]
+    return _orig_asm(H, b, f, P)
+
+
+def _asm_cross_transposed(H, b, factors, P):
+    H = np.array(H, copy=True)
+    for k in range(H.shape[0]):
+        H[k, :6, 6:] = H[k, :6, 6:].T.copy()
+        H[k, 6:, :6] = H[k, 6:, :6].T.copy()
+    return _orig_asm(H, b, factors, P)
+
+
+def _asm_bj_sign(H, b, factors, P):
+    b = np.array(b, copy=True)
+    b[:, 6:] *= -1
+    return _orig_asm(H, b, factors, P)
+
+
+_orig_asm = vo.assemble_system
+
+ASM_MUTANTS = [_asm_poses_swapped, _asm_cross_transposed, _asm_bj_sign]
+
+
+def test_unmodified_assembly_passes_its_pins():
+    assert _assembly_pins_hold()
+
+
+@pytest.mark.parametrize("fn", ASM_MUTANTS, ids=[f.__name__ for f in ASM_MUTANTS])
+def test_planted_assembly_mistake_is_caught(monkeypatch, fn):
+    monkeypatch.setattr(vo, "assemble_system", fn)
+    monkeypatch.setattr(oracle, "assemble_system", fn)
+    assert not _assembly_pins_hold()

@@ -286,3 +286,32 @@ def test_workload_driver_matches_per_factor():
         one = oracle.linearize_factor(*w.sources[s], maps[t], w.poses[pi], w.poses[pj])
         assert np.array_equal(res["H"][f], one["H"]) and res["inliers"][f] == one["inliers"]
     assert res["inliers"][2] == 0
+
+
+# ----------------------------------------------------------------- assembly
+
+def test_assembled_system_matches_global_finite_differences():
+    from tests.oracle_pins import fd_global_system, global_null_space, small_pose_graph
+    w = small_pose_graph()
+    maps = oracle.build_maps(w.targets, w.resolution)
+    ref = oracle.linearize_workload(w.sources, maps, w.poses, w.factors)
+    assert np.all(ref["inliers"] > 30)
+    P = w.poses.shape[0]
+    Hg, bg = oracle.assemble_system(ref["H"], ref["b"], w.factors, P)
+    Hfd, bfd = fd_global_system(w)
+    assert rel_err(Hg, Hfd) < 1e-7
+    assert rel_err(bg, bfd) < 1e-7
+    # gauge: a common motion of all poses is free
+    N = global_null_space(w.poses)
+    assert np.linalg.norm(Hg @ N) <= 1e-10 * np.linalg.norm(Hg) * np.linalg.norm(N)
+    assert np.abs(bg @ N).max() <= 1e-10 * np.linalg.norm(bg) * np.linalg.norm(N)
+    # the factor on one pose (rows 5) adds nothing: its relative pose is fixed
+    Hs, bs = oracle.assemble_system(ref["H"][5:6], ref["b"][5:6], w.factors[5:6], P)
+    assert np.linalg.norm(ref["H"][5]) > 0
+    assert np.abs(Hs).max() <= 1e-12 * np.linalg.norm(ref["H"][5])
+    assert np.abs(bs).max() <= 1e-12 * np.linalg.norm(ref["b"][5]) + 1e-300
+    # block read-out
+    pairs = [(0, 1), (0, 3), (1, 2), (1, 3)]
+    diag, bvec, off = oracle.system_blocks(Hg, bg, P, pairs)
+    assert np.array_equal(off[0], Hg[0:6, 6:12]) and np.array_equal(diag[2], Hg[12:18, 12:18])
+    assert np.array_equal(bvec[3], bg[18:24])
