@@ -15,4 +15,6 @@ from .scenes import (  # noqa: F401
     make_tiny_workload,
     pose_rows,
     rng_for,
+    stream_scan_frames,
+    drive_positions,
 )

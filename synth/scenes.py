@@ -469,23 +469,58 @@ def _scan_frame_subsampled(args):
     return _f32_cloud(pts[sel], cov[sel])
 
 
+def drive_positions(seed: int, n_frames: int, dt: float = 0.1, v_max: float = 12.0):
+    """Arc-length positions of a 10 Hz sensor on a vehicle that cruises at
+    2-12 m/s and stops now and then (stops last 1-4 s), seeded."""
+    rng = rng_for(400, seed)
+    s, v, out = 0.0, 0.0, []
+    target, stop_left = rng.uniform(2.0, v_max), 0
+    for _ in range(n_frames):
+        if stop_left > 0:
+            stop_left -= 1
+            v = 0.0
+        else:
+            if rng.random() < 0.01:
+                stop_left = int(rng.integers(10, 41))
+            if rng.random() < 0.05:
+                target = rng.uniform(2.0, v_max)
+            v += float(np.clip(target - v, -3.0 * dt, 2.0 * dt))
+        s += v * dt
+        out.append(s)
+    return np.array(out)
+
+
 def stream_scan_frames(cfg: int, n_frames: int, n_points: int = 20000, k: int = 20,
-                       workers: int | None = None, spacing: float = 1.0):
+                       workers: int | None = None, spacing: float = 1.0,
+                       positions=None, with_truth: bool = False,
+                       perturb=(0.1, 2.0)):
     """Yield (index, estimated pose 4x4, xyz float32 (n,3), cov float32 (n,6))
-    for keyframes `spacing` metres apart along a corridor, generated in a
-    process pool and returned in order (memory stays bounded by the pool)."""
+    for keyframes `spacing` metres apart along a corridor (or at the given
+    arc-length `positions`), generated in a process pool and returned in
+    order (memory stays bounded by the pool).  Each estimate is the truth
+    composed with a random (translation m, rotation deg) = `perturb` motion.
+    With `with_truth` the ground truth pose follows the estimate:
+    (index, T_est, T_gt, xyz, cov)."""
     rng = rng_for(cfg)
-    scene = Corridor(rng, float(n_frames) * spacing, continuous=False)
-    T_gt = [scene.sensor_pose(f * spacing) for f in range(n_frames)]
-    T_est = [T @ random_perturbation(rng) for T in T_gt]
+    if positions is None:
+        positions = np.arange(n_frames) * float(spacing)
+    positions = np.asarray(positions, dtype=np.float64)
+    assert positions.shape == (n_frames,)
+    scene = Corridor(rng, float(positions.max(initial=0.0)) + 1.0, continuous=False)
+    T_gt = [scene.sensor_pose(float(s)) for s in positions]
+    T_est = [T @ random_perturbation(rng, *perturb) for T in T_gt]
     seeds = rng.integers(0, 2**63 - 1, size=n_frames)
+    # a sensor at rest sees the same returns again
+    for f in range(1, n_frames):
+        if positions[f] == positions[f - 1]:
+            seeds[f] = seeds[f - 1]
     jobs = [(scene, T_gt[f], int(seeds[f]), k, n_points) for f in range(n_frames)]
     w = workers or default_workers()
     if w <= 1:
         for f, job in enumerate(jobs):
             xyz, cov = _scan_frame_subsampled(job)
-            yield f, T_est[f], xyz, cov
+            yield (f, T_est[f], T_gt[f], xyz, cov) if with_truth else (f, T_est[f], xyz, cov)
         return
     with ProcessPoolExecutor(max_workers=w) as ex:
         for f, (xyz, cov) in enumerate(ex.map(_scan_frame_subsampled, jobs, chunksize=4)):
-            yield f, T_est[f], xyz, cov
+            yield (f, T_est[f], T_gt[f], xyz, cov) if with_truth else (f, T_est[f], xyz, cov)

@@ -125,3 +125,19 @@ def test_empty_factor_set(vg, ctx):
     assert not out["Hdiag"].any() and not out["bvec"].any()
     with pytest.raises(ValueError):
         vg.assemble_system(ctx, g.fs, H[:, :6], b)
+
+
+def test_fully_connected_local_graph(vg, ctx):
+    """The local-mapping shape: every pair of 8 consecutive frames of a drive."""
+    from synth import Workload, drive_positions, pose_rows, stream_scan_frames
+    N = 8
+    pos = drive_positions(6, 160)[120:120 + N]
+    fr = list(stream_scan_frames(2, N, positions=pos, perturb=(0.02, 0.2), workers=8))
+    clouds = [(x, c) for (_, _, x, c) in fr]
+    w = Workload(name="local8", resolution=0.5, sources=clouds, targets=clouds,
+                 poses=pose_rows([T for (_, T, _, _) in fr]),
+                 factors=np.array([(a, b, a, b) for a in range(N) for b in range(a)], np.int32),
+                 meta={})
+    _, ref = oracle_results(w, with_corr=False)
+    assert np.all(ref["inliers"] > 1000)
+    _check(vg, ctx, w, ref)
