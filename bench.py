@@ -70,38 +70,69 @@ def distinct_voxels(fs_sizes, corr_t):
     return torch.bincount((u >> 32), minlength=F).cpu().numpy()
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
-    """The FP64 oracle on a bounded sample of the workload's factors,
-    single-threaded; returns (corr/s, cores, sample text, factor ids, outputs)."""
+_CPU_W = None     # the workload, inherited by forked oracle workers
+
+
+def _oracle_worker(args):
+    """Linearize factors order[k::stride] with the oracle until the budget runs out."""
     import oracle
+    k, stride, order, budget_s = args
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        threadpool_limits(1)
     except Exception:       # pragma: no cover
-        limiter = None
-    rng = np.random.default_rng(7)
-    order = rng.permutation(w.n_factors)
-    maps = {}
-    done, inl, pts = [], 0, 0
-    outs = []
+        pass
+    w = _CPU_W
+    maps, outs = {}, []
     t0 = time.perf_counter()
-    for f in order:
+    for f in order[k::stride]:
         s, tg, pi, pj = w.factors[f]
         if tg not in maps:
             maps[tg] = oracle.voxelize(*w.targets[tg], w.resolution)[0]
-        out = oracle.linearize_factor(*w.sources[s], maps[tg], w.poses[pi], w.poses[pj])
-        inl += out["inliers"]
-        pts += w.sources[s][0].shape[0]
-        done.append(int(f))
-        outs.append(out)
+        o = oracle.linearize_factor(*w.sources[s], maps[tg], w.poses[pi], w.poses[pj])
+        outs.append((int(f), {"H": o["H"], "b": o["b"], "e": o["e"], "inliers": o["inliers"]},
+                     int(w.sources[s][0].shape[0])))
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    sample = (f"{len(done)} of {w.n_factors} factors ({pts} source points, {inl} correspondences) "
-              f"linearized by the FP64 numpy oracle, voxel maps included, single thread")
-    return inl / dt, 1, sample, done, outs
+    return outs, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s: float = 12.0, workers: int = 1):
+    """The FP64 oracle on a bounded sample of the workload's factors, over
+    `workers` forked processes of one thread each (factors dealt round-robin
+    from a seeded permutation; each process stops after `budget_s`).  Must run
+    before the process touches the GPU.  Returns (corr/s, processes, sample
+    text, factor ids, outputs)."""
+    import multiprocessing as mp
+    global _CPU_W
+    _CPU_W = w
+    order = np.random.default_rng(7).permutation(w.n_factors)
+    jobs = [(k, workers, order, budget_s) for k in range(workers)]
+    t0 = time.perf_counter()
+    if workers == 1:
+        res = [_oracle_worker(jobs[0])]
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    ids, outs, inl, pts = [], [], 0, 0
+    for chunk, _ in res:
+        for f, o, n in chunk:
+            ids.append(f)
+            outs.append(o)
+            inl += int(o["inliers"])
+            pts += n
+    sample = (f"{len(ids)} of {w.n_factors} factors ({pts} source points, {inl} correspondences) "
+              f"linearized by the FP64 numpy oracle, voxel maps included, {workers} processes "
+              f"of 1 thread, {wall:.1f} s wall")
+    return inl / wall, workers, sample, ids, outs
+
+
+def _primed(gen):
+    """Start a generator (and the worker pool behind it) now; yields the same items."""
+    import itertools
+    first = next(gen)
+    return itertools.chain([first], gen)
 
 
 def run_serving(args):
@@ -125,6 +156,7 @@ def run_serving(args):
     resolution = 0.5
     rng = rng_for(5, 1)
     arrivals = np.cumsum(rng.exponential(0.1, size=n))
+    frames = _primed(stream_scan_frames(5, n, workers=None))   # forks before the GPU is used
     srv = vg.Server(memory_budget_bytes=int(args.budget_gib * 2**30), max_batch_factors=16384,
                     max_batch_points=1 << 28, max_batch_poses=65536, inflight=2)
     poses = np.zeros((0, 12))
@@ -159,7 +191,7 @@ def run_serving(args):
         Q[ids, 9:] = t + np.einsum("nij,nj->ni", R, dt)
         return Q
 
-    for f, T, xyz, cov in stream_scan_frames(5, n, workers=None):
+    for f, T, xyz, cov in frames:
         while True:
             try:
                 fid = srv.add_frame(xyz, cov, resolution)
@@ -292,6 +324,8 @@ def run_local(args):
     n = args.frames
     r, th_max, th_min, n_max, max_iters = 0.5, 0.95, 0.10, 15, 10
     positions = drive_positions(6, n)
+    frames = _primed(stream_scan_frames(2, n, positions=positions, with_truth=True,
+                                        perturb=(0.02, 0.2)))      # forks before the GPU is used
     ctx = vg.Context(0)
     sub = []                      # current submap: dicts of frame data
     stats = {"frames": 0, "skipped": 0, "submaps": 0, "factors": 0, "lm_iterations": 0,
@@ -370,8 +404,7 @@ def run_local(args):
         stats["factors"] += int(factors.shape[0])
 
     t_start = time.perf_counter()
-    for f, T_est, T_gt, xyz, cov in stream_scan_frames(2, n, positions=positions, with_truth=True,
-                                                         perturb=(0.02, 0.2)):
+    for f, T_est, T_gt, xyz, cov in frames:
         stats["frames"] += 1
         t0 = time.perf_counter()
         dev = vg.cloud_to_device(xyz, cov)
@@ -442,6 +475,8 @@ def main():
     ap.add_argument("--accum", default="f32", choices=["f32", "f32_comp", "f64"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="oracle processes for the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--keyframes", type=int, default=2000, help="serving: keyframes streamed")
     ap.add_argument("--frames", type=int, default=600, help="local: frames streamed (10 Hz)")
@@ -454,10 +489,8 @@ def main():
                                    "sharding is a design note only", "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import torch
-    from paper_2109_07073_amd import vgicp as vg
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # Everything that forks worker processes (input generation, the CPU
+    # baseline, the frame streams' pools) starts before the GPU is touched.
     if args.workload == "serving":
         run_serving(args)
         return
@@ -468,6 +501,15 @@ def main():
     w = build_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.n_factors} factors, {w.source_points()} source points, "
         f"generated in {time.perf_counter() - t_gen:.1f} s")
+    cpu_run = None
+    if not args.no_cpu_baseline:
+        cpu_run = cpu_baseline(w, workers=max(1, min(args.cpu_workers, os.cpu_count() or 1)))
+        log(f"[bench] cpu baseline: {cpu_run[2]}")
+
+    import torch
+    from paper_2109_07073_amd import vgicp as vg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
@@ -574,8 +616,8 @@ def main():
     # ---- CPU oracle baseline and a parity spot check on the same factors
     cpu = None
     spot = None
-    if not args.no_cpu_baseline:
-        rate, cores, sample, ids, outs = cpu_baseline(w)
+    if cpu_run is not None:
+        rate, cores, sample, ids, outs = cpu_run
         cpu = {"value": rate, "unit": "correspondences/s", "cores": cores, "kind": "oracle",
                "sample": sample}
         Hg, bg, eg = out["H"].cpu().numpy(), out["b"].cpu().numpy(), out["e"].cpu().numpy()

@@ -132,7 +132,7 @@ def test_fully_connected_local_graph(vg, ctx):
     from synth import Workload, drive_positions, pose_rows, stream_scan_frames
     N = 8
     pos = drive_positions(6, 160)[120:120 + N]
-    fr = list(stream_scan_frames(2, N, positions=pos, perturb=(0.02, 0.2), workers=8))
+    fr = list(stream_scan_frames(2, N, positions=pos, perturb=(0.02, 0.2), workers=1))
     clouds = [(x, c) for (_, _, x, c) in fr]
     w = Workload(name="local8", resolution=0.5, sources=clouds, targets=clouds,
                  poses=pose_rows([T for (_, T, _, _) in fr]),
