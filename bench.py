@@ -652,7 +652,7 @@ def main():
             "resolution_m": w.resolution,
             "accumulation": args.accum,
             "schedule": "batched, HIP graph replay",
-            "tile_points": int(args.tile or 4096),
+            "tile_points": int(fs.tile_points),
             "seed": w.meta.get("seed"),
         },
         "round_latency_ms": {

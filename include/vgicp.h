@@ -185,8 +185,9 @@ int vgicp_map_free(vgicp_map map);
 /* sources: host array of n_sources cloud descriptors (device data, caller
  * owned, must outlive the factor set); maps: host array of n_maps handles;
  * factors: host array of n_factors rows; n_poses: length of the pose arrays
- * later calls pass; tile_points: source points per workgroup tile (0 picks
- * the default 4096; otherwise a multiple of 256 in [256, 1<<20]).
+ * later calls pass; tile_points: source points per workgroup tile, a multiple
+ * of 256 in [256, 1<<20], or 0 for automatic: 4096, halved (down to 1024)
+ * while the factor set would have fewer than 3072 tiles.
  * Outputs of later calls are indexed in the order of `factors`.  Per-point
  * outputs (corr) are laid out factor after factor, n_src points each.
  * Errors: EINVAL (any index out of range, NULL pointers with nonzero counts,
@@ -196,9 +197,10 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
                            int64_t n_factors, int32_t n_poses, int32_t tile_points,
                            vgicp_factorset *out);
 
-/* Factor-set facts; any output may be NULL.  Errors: EINVAL. */
+/* Factor-set facts (tile_points: the tile size in use); any output may be
+ * NULL.  Errors: EINVAL. */
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
-                         int64_t *total_points);
+                         int64_t *total_points, int32_t *tile_points);
 
 /* Free a factor set and its captured graphs (NULL accepted). */
 int vgicp_factorset_destroy(vgicp_factorset fs);

@@ -53,6 +53,8 @@ int use_device(vgicp_ctx ctx) {
 }
 
 constexpr int kDefaultTile = 4096;
+constexpr int kMinAutoTile = 1024;     // 4 lookup passes of a 256-thread block
+constexpr int64_t kMinAutoTiles = 3072;  // 4 tiles per resident block slot (256 CUs x 3)
 
 // Brackets one kernel launch with events when timing is on.
 struct TimedLaunch {
@@ -290,8 +292,7 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   if (n_maps > 0 && !maps) return fail(ctx, VGICP_EINVAL, "vgicp_factorset_create: maps is NULL");
   if (vgicp_validate_factors(n_sources, n_maps, n_poses, factors, n_factors) != VGICP_OK)
     return fail(ctx, VGICP_EINVAL, g_thread_error);
-  if (tile_points == 0) tile_points = kDefaultTile;
-  if (tile_points < 256 || tile_points > (1 << 20) || tile_points % 256 != 0)
+  if (tile_points != 0 && (tile_points < 256 || tile_points > (1 << 20) || tile_points % 256 != 0))
     return fail(ctx, VGICP_EINVAL,
                 "vgicp_factorset_create: tile_points must be a multiple of 256 in [256, 2^20]");
   for (int32_t s = 0; s < n_sources; ++s) {
@@ -304,6 +305,18 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     if (!maps[m] || maps[m]->device != ctx->device)
       return fail(ctx, VGICP_EINVAL,
                   "vgicp_factorset_create: map " + std::to_string(m) + " is NULL or foreign");
+  if (tile_points == 0) {
+    // Automatic: the default tile, halved while the grid would not give every
+    // resident block slot several tiles (small factor sets such as a local
+    // submap), down to the smallest tile one lookup chunk of a block covers.
+    tile_points = kDefaultTile;
+    auto count_tiles = [&](int64_t tp) {
+      int64_t t = 0;
+      for (int64_t f = 0; f < n_factors; ++f) t += (sources[factors[f].src].n + tp - 1) / tp;
+      return t;
+    };
+    while (tile_points > kMinAutoTile && count_tiles(tile_points) < kMinAutoTiles) tile_points /= 2;
+  }
   int rc = use_device(ctx);
   if (rc) return rc;
 
@@ -421,8 +434,9 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
 }
 
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
-                         int64_t *total_points) {
+                         int64_t *total_points, int32_t *tile_points) {
   if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_info: fs is NULL");
+  if (tile_points) *tile_points = fs->tile_points;
   if (n_factors) *n_factors = fs->n_factors;
   if (n_tiles) *n_tiles = fs->n_tiles;
   if (total_points) *total_points = fs->total_points;

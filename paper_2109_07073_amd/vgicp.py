@@ -76,7 +76,7 @@ _PROTOS = {
     "vgicp_map_free": (ctypes.c_int, [_vp]),
     "vgicp_factorset_create": (ctypes.c_int, [_vp, _P(CCloud), _i32, _P(_vp), _i32, _P(CFactor),
                                               _i64, _i32, _i32, _P(_vp)]),
-    "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
+    "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)]),
     "vgicp_factorset_destroy": (ctypes.c_int, [_vp]),
     "vgicp_factorset_pairs": (ctypes.c_int, [_vp, _P(_i64), _vp]),
     "vgicp_assemble_system": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -333,9 +333,11 @@ class FactorSet:
                                            arr, nf, self.n_poses, int(tile_points), ctypes.byref(h)),
                ctx.handle)
         self._h = h
-        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _check(_lib.vgicp_factorset_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib.vgicp_factorset_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                         ctypes.byref(d)))
         self.n_factors, self.n_tiles, self.total_points = a.value, b.value, c.value
+        self.tile_points = d.value
         self.source_sizes = np.array([int(self._sources[s][0].shape[1]) for s in self.factors[:, 0]],
                                      dtype=np.int64)
         n = ctypes.c_int64()

@@ -62,7 +62,7 @@ def test_null_handles_are_rejected_without_a_device():
     assert lib.vgicp_map_info(None, None, None, None, None) == vg.EINVAL
     assert lib.vgicp_map_export(None, None, None, None, None, None) == vg.EINVAL
     assert lib.vgicp_factorset_create(None, None, 0, None, 0, None, 0, 0, 0, ctypes.byref(h)) == vg.EINVAL
-    assert lib.vgicp_factorset_info(None, None, None, None) == vg.EINVAL
+    assert lib.vgicp_factorset_info(None, None, None, None, None) == vg.EINVAL
     assert lib.vgicp_linearize_factors(None, None, None, None, None, None, None, None, None) == vg.EINVAL
     assert lib.vgicp_evaluate_errors(None, None, None, None, None, None) == vg.EINVAL
     assert lib.vgicp_overlap(None, None, None, None, None) == vg.EINVAL
