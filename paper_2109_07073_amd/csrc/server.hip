@@ -126,6 +126,7 @@ struct vgicp_server_s {
   std::mutex ingest_mu;  // one voxelization at a time (the ingest scratch is shared)
   std::string last_error;
   std::mutex err_mu;
+  int64_t callbacks_outstanding = 0;  // completion callbacks enqueued and not yet run
   // stats
   int64_t n_batches = 0, n_completed = 0, max_req_per_batch = 0, max_inflight = 0;
 };
@@ -187,14 +188,18 @@ struct DoneArgs {
   size_t slot;
 };
 
+// Runs on the HIP runtime's callback thread.  Everything it does to the
+// server happens under the lock, and the server is destroyed only once no
+// callback is outstanding, so it never touches a freed server.
 void on_batch_done(void *p) {
   DoneArgs *a = static_cast<DoneArgs *>(p);
-  {
-    std::lock_guard<std::mutex> g(a->srv->mu);
-    a->srv->slots[a->slot].finished = true;
-  }
-  a->srv->cv.notify_all();
+  vgicp_server srv = a->srv;
+  const size_t slot = a->slot;
   delete a;
+  std::lock_guard<std::mutex> g(srv->mu);
+  srv->slots[slot].finished = true;
+  srv->callbacks_outstanding -= 1;
+  srv->cv.notify_all();
 }
 
 int64_t request_points(const vgicp_server_s *srv, const vgicp_factor &f) {
@@ -330,7 +335,11 @@ void launch_batch(vgicp_server srv, size_t si) {
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(s.h_inl, s.d_inl, size_t(nf) * sizeof(int64_t), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipLaunchHostFunc(st, on_batch_done, new DoneArgs{srv, si});
+  if (e == hipSuccess) {
+    srv->callbacks_outstanding += 1;
+    e = hipLaunchHostFunc(st, on_batch_done, new DoneArgs{srv, si});
+    if (e != hipSuccess) srv->callbacks_outstanding -= 1;
+  }
   if (e != hipSuccess) {
     s.err = e;
     s.finished = true;  // retired as failed by the worker
@@ -490,6 +499,10 @@ int vgicp_server_destroy(vgicp_server srv) {
   }
   srv->cv.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv.wait(lk, [&] { return srv->callbacks_outstanding == 0; });
+  }
   (void)hipSetDevice(srv->device);
   for (Slot &s : srv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);

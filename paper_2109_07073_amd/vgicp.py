@@ -498,7 +498,11 @@ class ServerRequest:
 
     def wait(self):
         lat = ctypes.c_double()
-        _check_srv(_lib.vgicp_server_wait(self.server._h, self.ticket, ctypes.byref(lat)), self.server)
+        try:
+            _check_srv(_lib.vgicp_server_wait(self.server._h, self.ticket, ctypes.byref(lat)),
+                       self.server)
+        finally:
+            self.server._inflight.pop(self.ticket, None)
         self.latency_ms = lat.value
         return self
 
@@ -527,7 +531,9 @@ class Server:
         if code != OK:
             raise VgicpError(code, "vgicp_server_create failed")
         self._h = h
-        self._requests = []
+        # Submitted requests own the host arrays the worker writes into: keep
+        # them alive until they are waited for or the server is closed.
+        self._inflight = {}
 
     def add_frame(self, xyz, cov, resolution: float) -> int:
         x = np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(-1, 3).T)
@@ -556,6 +562,7 @@ class Server:
                                             ptr(r.H), ptr(r.b), ptr(r.e), ptr(r.inliers),
                                             ptr(r.overlap), ctypes.byref(t)), self)
         r.ticket = t.value
+        self._inflight[r.ticket] = r
         return r
 
     def stats(self):
@@ -565,9 +572,17 @@ class Server:
                 "max_requests_per_batch": v[2].value, "max_inflight": v[3].value}
 
     def close(self):
+        """Finish every submitted request, then free the server."""
         if getattr(self, "_h", None):
             _lib.vgicp_server_destroy(self._h)
             self._h = None
+            self._inflight.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -446,7 +446,8 @@ def make_scan_workload(cfg: int, n_frames: int, n_factors: int,
         sources = targets
         ill_sources = ill_targets
     meta = {"seed": [SEED_BASE, cfg], "k": k, "n_frames": n_frames,
-            "valid_returns_mean": float(np.mean([p[0].shape[0] for p in frames]))}
+            "valid_returns_mean": float(np.mean([p[0].shape[0] for p in frames])),
+            "poses_gt": pose_rows(T_gt)}
     if ill_eps:
         meta["ill"] = {"sources": ill_sources, "targets": ill_targets, "eps": ill_eps}
     return Workload(

@@ -36,102 +36,118 @@ def _frames(srv, w):
 
 def test_alone_mix_split_and_factorset_agree(vg, scans):
     import torch
-    srv = vg.Server(max_batch_factors=7, inflight=2)
-    ids = _frames(srv, scans)
-    fac = scans.factors.copy()
-    fac[:, 0] = [ids[s] for s in fac[:, 0]]
-    fac[:, 1] = [ids[t] for t in fac[:, 1]]
-    A, B, C = fac[:15], fac[15:30], fac[30:]
-    alone = srv.submit("linearize", A, scans.poses).wait()
-    # the same request in a mix (and split over several 7-factor batches)
-    reqs = [srv.submit("linearize", X, scans.poses) for X in (B, A, C, A)]
-    for r in reqs:
-        r.wait()
+    with vg.Server(max_batch_factors=7, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        A, B, C = fac[:15], fac[15:30], fac[30:]
+        alone = srv.submit("linearize", A, scans.poses).wait()
+        # the same request in a mix (and split over several 7-factor batches)
+        reqs = [srv.submit("linearize", X, scans.poses) for X in (B, A, C, A)]
+        for r in reqs:
+            r.wait()
+        st = srv.stats()
     for mixed in (reqs[1], reqs[3]):
         for k in ("H", "b", "e", "inliers"):
             assert np.array_equal(getattr(mixed, k), getattr(alone, k)), k
-    # the factor-set path computes the same bits
+    # the factor-set path computes the same bits with the server's tile size
     ctx = vg.Context(0)
     dev = [vg.cloud_to_device(x, c) for (x, c) in scans.targets]
     maps = [vg.voxelize(ctx, x, c, scans.resolution) for (x, c) in dev]
-    fs = vg.FactorSet(ctx, dev, maps, scans.factors[:15], scans.poses.shape[0])
+    fs = vg.FactorSet(ctx, dev, maps, scans.factors[:15], scans.poses.shape[0], tile_points=4096)
     out = vg.linearize_factors(ctx, fs, torch.from_numpy(scans.poses).to("cuda"))
     ctx.synchronize()
     for k in ("H", "b", "e", "inliers"):
         assert np.array_equal(out[k].cpu().numpy(), getattr(alone, k)), k
-    st = srv.stats()
-    assert st["max_requests_per_batch"] >= 2 and st["batches"] >= 6
     print("server stats", st, "latency ms", [round(r.latency_ms, 3) for r in reqs])
-    srv.close()
+    assert st["max_requests_per_batch"] >= 2 and st["batches"] >= 6
 
 
 def test_evaluate_and_overlap_requests(vg, scans):
-    import torch
-    srv = vg.Server(inflight=3)
-    ids = _frames(srv, scans)
-    fac = scans.factors.copy()
-    fac[:, 0] = [ids[s] for s in fac[:, 0]]
-    fac[:, 1] = [ids[t] for t in fac[:, 1]]
-    lin = srv.submit("linearize", fac, scans.poses)
-    ev = srv.submit("evaluate", fac, scans.poses)
-    ov = srv.submit("overlap", fac, scans.poses)
-    for r in (lin, ev, ov):
-        r.wait()
+    with vg.Server(inflight=3) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        lin = srv.submit("linearize", fac, scans.poses)
+        ev = srv.submit("evaluate", fac, scans.poses)
+        ov = srv.submit("overlap", fac, scans.poses)
+        for r in (lin, ev, ov):
+            r.wait()
     assert np.array_equal(ev.e, lin.e) and np.array_equal(ev.inliers, lin.inliers)
     assert np.array_equal(ov.inliers, lin.inliers)
     n = np.array([scans.sources[s][0].shape[0] for s in scans.factors[:, 0]])
     assert np.array_equal(ov.overlap, ov.inliers / n)
-    srv.close()
 
 
 def test_memory_budget_admission(vg, scans):
-    srv = vg.Server(memory_budget_bytes=1)
-    with pytest.raises(vg.VgicpError) as ex:
-        srv.add_frame(*scans.targets[0], scans.resolution)
-    assert ex.value.code == vg.EFULL
-    srv.close()
-    probe = vg.Server()
-    fid = probe.add_frame(*scans.targets[0], scans.resolution)
-    one = probe.memory()[0]
-    probe.close()
-    srv = vg.Server(memory_budget_bytes=int(one * 2.5))
-    a = srv.add_frame(*scans.targets[0], scans.resolution)
-    b = srv.add_frame(*scans.targets[1], scans.resolution)
-    with pytest.raises(vg.VgicpError) as ex:
-        srv.add_frame(*scans.targets[2], scans.resolution)
-    assert ex.value.code == vg.EFULL
-    srv.remove_frame(a)
-    c = srv.add_frame(*scans.targets[2], scans.resolution)
-    assert srv.memory()[0] <= int(one * 2.5)
-    # unknown frames and out-of-range poses are refused at submit
-    with pytest.raises(vg.VgicpError):
-        srv.submit("linearize", [(a, b, 0, 1)], scans.poses)
-    with pytest.raises(vg.VgicpError):
-        srv.submit("linearize", [(b, c, 0, 10**6)], scans.poses)
-    r = srv.submit("overlap", [(b, c, 0, 1)], scans.poses).wait()
+    with vg.Server(memory_budget_bytes=1) as srv:
+        with pytest.raises(vg.VgicpError) as ex:
+            srv.add_frame(*scans.targets[0], scans.resolution)
+        assert ex.value.code == vg.EFULL
+        assert srv.memory()[0] == 0
+    # frame sizes differ (the hash capacity is a power of two): measure each
+    size = []
+    with vg.Server() as probe:
+        for k in range(3):
+            before = probe.memory()[0]
+            probe.add_frame(*scans.targets[k], scans.resolution)
+            size.append(probe.memory()[0] - before)
+    budget = sum(size) - 1           # any two frames fit, all three do not
+    with vg.Server(memory_budget_bytes=budget) as srv:
+        a = srv.add_frame(*scans.targets[0], scans.resolution)
+        b = srv.add_frame(*scans.targets[1], scans.resolution)
+        assert srv.memory()[0] == size[0] + size[1]
+        with pytest.raises(vg.VgicpError) as ex:
+            srv.add_frame(*scans.targets[2], scans.resolution)
+        assert ex.value.code == vg.EFULL
+        assert srv.memory()[0] == size[0] + size[1]
+        srv.remove_frame(a)
+        c = srv.add_frame(*scans.targets[2], scans.resolution)
+        assert srv.memory()[0] == size[1] + size[2] <= budget
+        # unknown frames and out-of-range poses are refused at submit
+        with pytest.raises(vg.VgicpError):
+            srv.submit("linearize", [(a, b, 0, 1)], scans.poses)
+        with pytest.raises(vg.VgicpError):
+            srv.submit("linearize", [(b, c, 0, 10**6)], scans.poses)
+        r = srv.submit("overlap", [(b, c, 0, 1)], scans.poses).wait()
     assert r.inliers[0] >= 0
-    srv.close()
 
 
 def test_threads_submit_concurrently(vg, scans):
-    srv = vg.Server(max_batch_factors=16, inflight=2)
-    ids = _frames(srv, scans)
-    fac = scans.factors.copy()
-    fac[:, 0] = [ids[s] for s in fac[:, 0]]
-    fac[:, 1] = [ids[t] for t in fac[:, 1]]
-    ref = srv.submit("linearize", fac, scans.poses).wait()
     results = {}
+    with vg.Server(max_batch_factors=16, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        ref = srv.submit("linearize", fac, scans.poses).wait()
 
-    def client(k):
-        rs = [srv.submit("linearize", fac[k::4], scans.poses) for _ in range(3)]
-        results[k] = [r.wait() for r in rs]
+        def client(k):
+            rs = [srv.submit("linearize", fac[k::4], scans.poses) for _ in range(3)]
+            results[k] = [r.wait() for r in rs]
 
-    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
+        th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    assert sorted(results) == [0, 1, 2, 3]
     for k, rs in results.items():
         for r in rs:
             assert np.array_equal(r.H, ref.H[k::4]) and np.array_equal(r.e, ref.e[k::4])
-    srv.close()
+
+
+def test_unwaited_requests_finish_before_close(vg, scans):
+    """Requests nobody waits for still complete into their arrays before the
+    server is freed; the binding keeps their arrays alive until then."""
+    with vg.Server(max_batch_factors=5, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        ref = srv.submit("linearize", fac, scans.poses).wait()
+        reqs = [srv.submit("linearize", fac, scans.poses) for _ in range(3)]
+    for r in reqs:
+        assert np.array_equal(r.H, ref.H) and np.array_equal(r.inliers, ref.inliers)
