@@ -17,6 +17,7 @@ input; inputs are resident in HBM before timing starts.
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -130,7 +131,6 @@ def cpu_baseline(w, budget_s: float = 12.0, workers: int = 1):
 
 def _primed(gen):
     """Start a generator (and the worker pool behind it) now; yields the same items."""
-    import itertools
     first = next(gen)
     return itertools.chain([first], gen)
 
@@ -324,8 +324,12 @@ def run_local(args):
     n = args.frames
     r, th_max, th_min, n_max, max_iters = 0.5, 0.95, 0.10, 15, 10
     positions = drive_positions(6, n)
-    frames = _primed(stream_scan_frames(2, n, positions=positions, with_truth=True,
-                                        perturb=(0.02, 0.2)))      # forks before the GPU is used
+    # generated up front (before the GPU is used), so that no generator
+    # process competes with the timed loop for the host's cores
+    t_gen = time.perf_counter()
+    frames = list(stream_scan_frames(2, n, positions=positions, with_truth=True,
+                                     perturb=(0.02, 0.2)))
+    log(f"[local] {n} frames generated in {time.perf_counter() - t_gen:.1f} s")
     ctx = vg.Context(0)
     sub = []                      # current submap: dicts of frame data
     stats = {"frames": 0, "skipped": 0, "submaps": 0, "factors": 0, "lm_iterations": 0,
@@ -402,6 +406,19 @@ def run_local(args):
         err_after.extend(a_t)
         stats["submaps"] += 1
         stats["factors"] += int(factors.shape[0])
+
+    # load every kernel once (first launches pay for code-object loading)
+    _, T0, _, x0, c0 = frames[0]
+    d0 = vg.cloud_to_device(x0, c0)
+    m0 = vg.voxelize(ctx, d0[0], d0[1], r)
+    fs0 = vg.FactorSet(ctx, [d0, d0], [m0, m0], [(0, 1, 0, 1)], 2)
+    P0 = torch.from_numpy(pose_rows([T0, T0])).to("cuda")
+    l0 = vg.linearize_factors(ctx, fs0, P0)
+    vg.assemble_system(ctx, fs0, l0["H"], l0["b"])
+    vg.evaluate_errors(ctx, fs0, P0)
+    vg.overlap(ctx, fs0, P0)
+    sync()
+    del fs0, m0, d0
 
     t_start = time.perf_counter()
     for f, T_est, T_gt, xyz, cov in frames:

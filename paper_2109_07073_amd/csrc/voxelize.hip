@@ -269,11 +269,18 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
     n_voxels = int64_t(ctx->host_pinned[1]);
   }
 
+  // Load factor at most 1/8: a lookup that misses (most points of a partial
+  // overlap) then almost always finds an empty home slot or one more probe.
+  // Slots are int32 indices, so the table stops at 2^31 slots (load <= 1/2).
   int64_t cap = 16;
   uint32_t log2cap = 4;
-  while (cap < 2 * n_voxels) {
+  while (cap < 8 * n_voxels && cap < (int64_t(1) << 31)) {
     cap <<= 1;
     ++log2cap;
+  }
+  if (cap < 2 * n_voxels) {
+    msg = "vgicp_voxelize: more than 2^30 voxels in one map";
+    return VGICP_EINVAL;
   }
   vgicp_map m = new (std::nothrow) vgicp_voxelmap_s();
   if (!m) {

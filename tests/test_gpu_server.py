@@ -104,11 +104,13 @@ def test_memory_budget_admission(vg, scans):
         assert ex.value.code == vg.EFULL
         assert srv.memory()[0] == size[0] + size[1]
         srv.remove_frame(a)
-        c = srv.add_frame(*scans.targets[2], scans.resolution)
+        with pytest.raises(vg.VgicpError):
+            srv.submit("linearize", [(a, b, 0, 1)], scans.poses)   # removed frame
+        c = srv.add_frame(*scans.targets[2], scans.resolution)     # may reuse a's id
         assert srv.memory()[0] == size[1] + size[2] <= budget
         # unknown frames and out-of-range poses are refused at submit
         with pytest.raises(vg.VgicpError):
-            srv.submit("linearize", [(a, b, 0, 1)], scans.poses)
+            srv.submit("linearize", [(10**6, b, 0, 1)], scans.poses)
         with pytest.raises(vg.VgicpError):
             srv.submit("linearize", [(b, c, 0, 10**6)], scans.poses)
         r = srv.submit("overlap", [(b, c, 0, 1)], scans.poses).wait()
