@@ -58,6 +58,31 @@ def build_workload(name: str):
                               n_factors=spec["n_factors"], src_range=spec["src_range"])
 
 
+def profiled_traffic(workload: str):
+    """HBM bytes per linearize launch measured by rocprofv3 (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy-kernel calibration) for this workload, from
+    profiles/k_linearize_<workload>.md, or None when there is no profile or
+    the kernel sources have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_linearize_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            key, _, val = line.strip().partition(": ")
+            if key in ("traffic_bytes_per_launch", "source_sha256_16"):
+                fields[key] = val.strip()
+    csrc = os.path.join(ROOT, "paper_2109_07073_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("linearize.hip", "voxelize.hip", "vgicp_internal.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def distinct_voxels(fs_sizes, corr_t):
     """U_f: distinct target voxels touched per factor, from the per-point
     correspondence output (device tensor)."""
@@ -607,6 +632,7 @@ def main():
     alg_bytes = float(36 * sizes.sum() + 44 * U.sum())          # per linearize launch
     strict_bytes = float(12 * sizes.sum() + 24 * n_corr + 44 * U.sum())
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = profiled_traffic(args.workload) if args.accum == "f32" and not args.tile else None
 
     # ---- plain per-factor launches on the same factors
     plain = None
@@ -685,7 +711,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
             "kernel": "k_linearize",
             "kernel_ms": round(k_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,

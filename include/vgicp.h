@@ -67,9 +67,10 @@ extern "C" {
 
 /* Residual e_k = mu'_k - T mu_k of the per-point terms.  The correspondence
  * decision always uses the FP32 transform; these modes only change how the
- * residual's rounding error is handled. */
-#define VGICP_RESID_FF 0  /* double-float transform (exact products by fma, two-sum): the
-                             residual is accurate to FP32 rounding of the residual itself */
+ * residual itself is evaluated. */
+#define VGICP_RESID_F64 0 /* T mu_k and the difference in FP64 from the FP32 point and voxel
+                             mean and the FP64 relative pose, then rounded to FP32: accurate
+                             to the rounding of the residual itself                       */
 #define VGICP_RESID_F32 1 /* plain FP32 transform: absolute error ~ |mu| * 2^-23        */
 
 /* How the factors of one call are launched. */
@@ -220,7 +221,7 @@ int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
  * (points that fell in a voxel of the target map), and optionally corr int32
  * [total_points] with the voxel ordinal of each source point or -1 (NULL to
  * skip).  A factor with no inlier returns H = 0, b = 0, e = 0.
- * opts may be NULL (FP32 accumulation, batched schedule, no graph, double-float residual).  Results
+ * opts may be NULL (FP32 accumulation, batched schedule, no graph, FP64 residual).  Results
  * are deterministic and do not depend on the schedule or on the other factors
  * of the set.  Errors: EINVAL, EHIP. */
 int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,

@@ -220,31 +220,18 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &err) 
   err = (a - (s - bp)) + (b - bp);
 }
 
-// Rounding error of the FP32 lookup transform against the exact relative
-// motion: (R mu + t) - q with q the FP32 transform of lookup_transform,
-// accurate to a few units in the last place of the error itself.  Products
-// are split exactly with fma, the fixed-order sums with two-sum, and the
-// FP32 rounding of R and t enters through their low parts.  q itself is the
-// high part of this double-float evaluation, so the correspondence decision
-// is unchanged.
-__device__ __forceinline__ void transform_error(const float R[9], const float Rlo[9],
-                                                const float t[3], const float tlo[3], float x,
-                                                float y, float z, float q[3], float qerr[3]) {
-#pragma clang fp contract(off)
+// Residual m - (R mu + t) in FP64 from the FP32 point and voxel mean and the
+// FP64 relative pose, rounded once to FP32.  FP64 fused multiply-adds issue at
+// the unpacked FP32 rate, so this costs about a fifth of an FP32 double-float
+// evaluation and is accurate to the rounding of the residual itself.
+__device__ __forceinline__ void residual64(const double R[9], const double t[3], float x,
+                                           float y, float z, const float m[3], float e[3]) {
+  const double dx = x, dy = y, dz = z;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const float p0 = R[3 * r] * x, p1 = R[3 * r + 1] * y, p2 = R[3 * r + 2] * z;
-    const float e0 = __builtin_fmaf(R[3 * r], x, -p0);
-    const float e1 = __builtin_fmaf(R[3 * r + 1], y, -p1);
-    const float e2 = __builtin_fmaf(R[3 * r + 2], z, -p2);
-    float s1, s2, s3, d1, d2, d3;
-    two_sum(p0, p1, s1, d1);
-    two_sum(s1, p2, s2, d2);
-    two_sum(s2, t[r], s3, d3);
-    const float lo = __builtin_fmaf(Rlo[3 * r], x, __builtin_fmaf(Rlo[3 * r + 1], y,
-                                                                  Rlo[3 * r + 2] * z));
-    q[r] = s3;
-    qerr[r] = ((e0 + e1) + (e2 + d1)) + ((d2 + d3) + (tlo[r] + lo));
+    const double q = __builtin_fma(R[3 * r + 2], dz,
+                                   __builtin_fma(R[3 * r + 1], dy, __builtin_fma(R[3 * r], dx, t[r])));
+    e[r] = float(double(m[r]) - q);
   }
 }
 
@@ -298,15 +285,21 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
 
 // ---------------------------------------------------------------- factor constants
 struct FactorConsts {
-  float R[9];    // fl32(R)
-  float t[3];    // fl32(t)
-  float Rlo[9];  // fl32(R - fl32(R))
-  float tlo[3];  // fl32(t - fl32(t))
-  double R64[9]; // R itself, for the FP64 fused covariance of ill-conditioned points
+  float R[9];     // fl32(R): lookup transform and per-point algebra
+  float t[3];     // fl32(t): lookup transform
+  double R64[9];  // R itself: FP64 residual and FP64 fused covariance
+  double t64[3];  // t itself: FP64 residual
 };
 
 __device__ __forceinline__ float uniform_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
 // ---------------------------------------------------------------- per point
@@ -350,29 +343,23 @@ __device__ __noinline__ bool fused_information_fp64(const double R[9], const flo
 }
 
 // Adds one correspondence.  k holds the FP32 relative rotation (and its FP64
-// value), (mx, my, mz) is the source point, c its covariance, q its FP32
-// transform and qerr that transform's rounding error, m / S the voxel mean
-// and covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
+// value), (mx, my, mz) is the source point, c its covariance, e its residual
+// m - T mu in the target frame, S the voxel covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
 // the cost are added; without it only the cost.  With KAPPA, points whose
 // FP32 fused covariance is not positive definite or has a condition estimate
 // trace^3 / (27 det) above `kappa` take the FP64 fused covariance.
 template <bool LIN, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConsts &k,
                                                    float kappa, float mx, float my, float mz,
-                                                   const float c[6], const float q[3],
-                                                   const float qerr[3], const float m[3],
+                                                   const float c[6], const float e[3],
                                                    const float S[6]) {
   // Contraction is off and every fused multiply-add is explicit, so the cost
   // comes out bit-identical in the linearization and the cost-only kernels.
 #pragma clang fp contract(off)
   const float *R = k.R;
 #define FMA __builtin_fmaf
-  // residual e_k = mu' - T mu (target frame), rotated into the source frame;
-  // m - q is exact when the two are within a factor of two, and qerr carries
-  // the transform's rounding error (zero for the plain FP32 residual)
-  const float e0 = (m[0] - q[0]) - qerr[0];
-  const float e1 = (m[1] - q[1]) - qerr[1];
-  const float e2 = (m[2] - q[2]) - qerr[2];
+  // residual e_k = mu' - T mu (target frame), rotated into the source frame
+  const float e0 = e[0], e1 = e[1], e2 = e[2];
   const float r0 = FMA(R[6], e2, FMA(R[3], e1, R[0] * e0));
   const float r1 = FMA(R[7], e2, FMA(R[4], e1, R[1] * e0));
   const float r2 = FMA(R[8], e2, FMA(R[5], e1, R[2] * e0));
@@ -413,7 +400,10 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
     o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
   } else {
     if (!pd32) return;  // not positive definite
-    const float inv = 1.0f / det;
+    // hardware reciprocal refined by one Newton step (within an ulp or so;
+    // det > 0 here and far above the FP32 subnormal range for these inputs)
+    const float r0i = __builtin_amdgcn_rcpf(det);
+    const float inv = FMA(FMA(-det, r0i, 1.0f), r0i, r0i);
     o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
     o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
   }
@@ -480,17 +470,12 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     k.R[i] = uniform_f(float(R[i]));
-    k.Rlo[i] = uniform_f(float(R[i] - double(k.R[i])));
-    const long long b = __double_as_longlong(R[i]);
-    const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
-    const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
-    k.R64[i] = __longlong_as_double((static_cast<long long>(hi) << 32) |
-                                    static_cast<long long>(static_cast<unsigned>(lo)));
+    k.R64[i] = uniform_d(R[i]);
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     k.t[i] = uniform_f(float(t[i]));
-    k.tlo[i] = uniform_f(float(t[i] - double(k.t[i])));
+    k.t64[i] = uniform_d(t[i]);
   }
   return k;
 }
@@ -549,23 +534,28 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <bool LIN, bool FF, bool CORR, bool KAPPA, typename SumsT>
+template <bool LIN, bool R64, bool CORR, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
                                            float kappa, int32_t *pcorr) {
   if constexpr (CORR) pcorr[B.idx] = B.ord;
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
-  float q[3], qerr[3] = {0.f, 0.f, 0.f};
-  if constexpr (FF) {
-    transform_error(k.R, k.Rlo, k.t, k.tlo, B.x, B.y, B.z, q, qerr);
+  float e[3];
+  if constexpr (R64) {
+    residual64(k.R64, k.t64, B.x, B.y, B.z, m, e);
   } else {
+#pragma clang fp contract(off)
+    float q[3];
     lookup_transform(k.R, k.t, B.x, B.y, B.z, q);
+    e[0] = m[0] - q[0];
+    e[1] = m[1] - q[1];
+    e[2] = m[2] - q[2];
   }
-  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, q, qerr, m, S);
+  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, e, S);
 }
 
 // Linearization (LIN) or cost evaluation (!LIN) of one tile per block.
-// FF: residual from the double-float transform (else plain FP32).
+// R64: residual in FP64 from the FP64 relative pose (else plain FP32).
 // CORR: also write each point's voxel ordinal (or -1).
 // KAPPA: ill-conditioned points take the FP64 fused covariance (see
 // add_correspondence).
@@ -579,7 +569,7 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //           and covariance gathers are in flight during the previous batch's
 //           math.
 // The last partial batch runs at the end of the tile.
-template <int ACC, bool LIN, bool FF, bool CORR, bool KAPPA>
+template <int ACC, bool LIN, bool R64, bool CORR, bool KAPPA>
 __global__ void __launch_bounds__(kBlock)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_points,
@@ -683,18 +673,18 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR, KAPPA>(acc, B, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
         head = ring_add(head, 64);
-        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
-        batch_math<LIN, FF, CORR, KAPPA>(acc, B, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       } else {
-        batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
       }
       count -= nb * 64;
     }
@@ -704,7 +694,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     const bool live = uint32_t(lane) < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, pc, n, payload);
-    if (live) batch_math<LIN, FF, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+    if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
   }
 
   acc.wave_reduce();
@@ -936,15 +926,15 @@ k_assemble_pairs(const int64_t *__restrict__ off, const int64_t *__restrict__ en
 // ---------------------------------------------------------------- launchers
 static inline unsigned xcd_grid(int64_t tiles) { return unsigned(((tiles + 7) / 8) * 8); }
 
-template <int ACC, bool LIN, bool FF, bool KAPPA>
+template <int ACC, bool LIN, bool R64, bool KAPPA>
 static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                              const double *poses, int32_t *corr, float kappa, hipStream_t st) {
   if (te <= tb) return hipSuccess;
   if (corr) {
-    k_linearize<ACC, LIN, FF, true, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+    k_linearize<ACC, LIN, R64, true, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
         fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr, kappa);
   } else {
-    k_linearize<ACC, LIN, FF, false, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
+    k_linearize<ACC, LIN, R64, false, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
         fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, nullptr,
         kappa);
   }
@@ -952,37 +942,37 @@ static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te
 }
 
 template <int ACC, bool KAPPA>
-static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool ff, int64_t tb,
+static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool r64, int64_t tb,
                              int64_t te, const double *poses, int32_t *corr, float kappa,
                              hipStream_t st) {
   if (lin) {
-    return ff ? launch_lin<ACC, true, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
+    return r64 ? launch_lin<ACC, true, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
               : launch_lin<ACC, true, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
   }
-  return ff ? launch_lin<ACC, false, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
+  return r64 ? launch_lin<ACC, false, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
             : launch_lin<ACC, false, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
 }
 
 template <bool KAPPA>
-static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool ff, int64_t tb,
+static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool r64, int64_t tb,
                            int64_t te, const double *poses, int32_t *corr, float kappa,
                            hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F64:
-      return launch_acc<VGICP_ACC_F64, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_F64, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
     case VGICP_ACC_F32_COMP:
-      return launch_acc<VGICP_ACC_F32_COMP, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_F32_COMP, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
     default:
-      return launch_acc<VGICP_ACC_F32, KAPPA>(fs, lin, ff, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_F32, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
   }
 }
 
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
                             bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
                             hipStream_t st) {
-  const bool ff = resid == VGICP_RESID_FF;
-  if (kappa > 0.f) return launch_k<true>(fs, accum, lin, ff, tb, te, poses, corr, kappa, st);
-  return launch_k<false>(fs, accum, lin, ff, tb, te, poses, corr, 0.f, st);
+  const bool r64 = resid == VGICP_RESID_F64;
+  if (kappa > 0.f) return launch_k<true>(fs, accum, lin, r64, tb, te, poses, corr, kappa, st);
+  return launch_k<false>(fs, accum, lin, r64, tb, te, poses, corr, 0.f, st);
 }
 
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,

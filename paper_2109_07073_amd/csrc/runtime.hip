@@ -479,13 +479,13 @@ int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const c
 }
 
 int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
-  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_FF, 0.0f, 0};
+  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_F64, 0.0f, 0};
   if (opts) *o = *opts;
   if (o->accum < VGICP_ACC_F32 || o->accum > VGICP_ACC_F64)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown accumulation");
   if (o->schedule != VGICP_SCHED_BATCHED && o->schedule != VGICP_SCHED_PER_FACTOR)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown schedule");
-  if (o->resid != VGICP_RESID_FF && o->resid != VGICP_RESID_F32)
+  if (o->resid != VGICP_RESID_F64 && o->resid != VGICP_RESID_F32)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown residual mode");
   if (!(o->fp64_kappa >= 0.0f) || !std::isfinite(o->fp64_kappa))
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": fp64_kappa must be finite and >= 0");

@@ -458,7 +458,7 @@ int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server
   if (tp < 256 || tp > (1 << 20) || tp % 256 != 0) return VGICP_EINVAL;
   const vgicp_opts &o = cfg->opts;
   if (o.accum < VGICP_ACC_F32 || o.accum > VGICP_ACC_F64 ||
-      (o.resid != VGICP_RESID_FF && o.resid != VGICP_RESID_F32) || !(o.fp64_kappa >= 0.0f) ||
+      (o.resid != VGICP_RESID_F64 && o.resid != VGICP_RESID_F32) || !(o.fp64_kappa >= 0.0f) ||
       !std::isfinite(o.fp64_kappa) || o.reserved != 0)
     return VGICP_EINVAL;
   int n = 0;

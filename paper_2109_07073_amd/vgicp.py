@@ -26,7 +26,7 @@ REQ = {"linearize": 0, "evaluate": 1, "overlap": 2}
 ACC = {"f32": 0, "f32_comp": 1, "f64": 2}
 KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
-RESID = {"ff": 0, "f32": 1}
+RESID = {"f64": 0, "f32": 1}
 
 
 class VgicpError(RuntimeError):
@@ -363,7 +363,7 @@ class FactorSet:
             pass
 
 
-def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "ff",
+def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "f64",
           fp64_kappa: float = 0.0) -> COpts:
     if accum not in ACC:
         raise ValueError(f"accum must be one of {sorted(ACC)}")
@@ -382,7 +382,7 @@ def _check_poses(fs: FactorSet, poses):
 
 def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                       schedule: str = "batched", use_graph: bool = False,
-                      with_corr: bool = False, out=None, resid: str = "ff",
+                      with_corr: bool = False, out=None, resid: str = "f64",
                       fp64_kappa: float = 0.0):
     """Hessian factors of every factor at `poses` (float64 (P, 12) device).
     Returns dict of device tensors H (F,12,12), b (F,12), e (F,), inliers (F,)
@@ -417,7 +417,7 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
 
 def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                     schedule: str = "batched", use_graph: bool = False, out=None,
-                    resid: str = "ff", fp64_kappa: float = 0.0):
+                    resid: str = "f64", fp64_kappa: float = 0.0):
     """Matching cost e (F,) and inliers (F,) without Jacobians."""
     torch = _torch()
     _check_poses(fs, poses)
@@ -522,7 +522,7 @@ class Server:
 
     def __init__(self, device=0, memory_budget_bytes=0, max_batch_factors=4096,
                  max_batch_points=1 << 27, max_batch_poses=65536, inflight=2, tile_points=0,
-                 accum="f32", resid="ff", fp64_kappa=0.0):
+                 accum="f32", resid="f64", fp64_kappa=0.0):
         cfg = CServerConfig(int(memory_budget_bytes), int(max_batch_factors), int(max_batch_points),
                             int(max_batch_poses), int(inflight), int(tile_points), 0,
                             _opts(accum, "batched", False, resid, fp64_kappa))

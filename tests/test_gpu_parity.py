@@ -167,11 +167,11 @@ def scans40_ref(scans40):
 
 
 @pytest.mark.parametrize("accum", ACCS)
-def test_scan_factors_40_double_float_residual(vg, ctx, scans40, scans40_ref, accum):
+def test_scan_factors_40_fp64_residual(vg, ctx, scans40, scans40_ref, accum):
     g = GpuWorkload(vg, ctx, scans40)
-    got = g.linearize(accum=accum, resid="ff")
+    got = g.linearize(accum=accum, resid="f64")
     worst = assert_linearize_parity(got, scans40_ref)
-    print(f"40 scan factors {accum}/ff: worst relative error {worst}")
+    print(f"40 scan factors {accum}/f64-residual: worst relative error {worst}")
 
 
 def test_plain_fp32_residual_is_the_looser_variant(vg, ctx, scans40, scans40_ref):
@@ -181,8 +181,8 @@ def test_plain_fp32_residual_is_the_looser_variant(vg, ctx, scans40, scans40_ref
     got = g.linearize(accum="f64", resid="f32")
     worst = assert_linearize_parity(got, scans40_ref, tol=1e-4)
     print(f"40 scan factors f64/f32-residual: worst relative error {worst}")
-    ff = g.linearize(accum="f64", resid="ff")
-    assert np.array_equal(ff["inliers"], got["inliers"])
+    r64 = g.linearize(accum="f64", resid="f64")
+    assert np.array_equal(r64["inliers"], got["inliers"])
 
 
 def test_schedules_graph_and_repeats_are_bitwise_identical(vg, ctx, ragged):

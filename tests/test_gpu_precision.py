@@ -14,7 +14,7 @@ U{5,000..40,000} points):
 
 The printed table is the study; the asserts pin what the design promises:
   * every variant keeps the integer outputs (inliers) bit-exact;
-  * with the double-float residual, both k-NN sets are within 1e-5 for every
+  * with the FP64 residual, both k-NN sets are within 1e-5 for every
     accumulation variant;
   * the FP64 fused covariance (kappa gate 1e4) keeps the ill-conditioned sets
     within 1e-5 and does not lose accuracy against the all-FP32 form.
@@ -78,9 +78,9 @@ def _errors(got, ref):
 
 
 VARIANTS = [
-    ("f32", "f32", 0.0), ("f32", "ff", 0.0), ("f32_comp", "ff", 0.0), ("f64", "ff", 0.0),
-    ("f32", "ff", 1e3), ("f32", "ff", 1e4), ("f32", "ff", 1e5),
-    ("f32_comp", "ff", 1e4), ("f64", "ff", 1e4), ("f64", "f32", 1e4),
+    ("f32", "f32", 0.0), ("f32", "f64", 0.0), ("f32_comp", "f64", 0.0), ("f64", "f64", 0.0),
+    ("f32", "f64", 1e3), ("f32", "f64", 1e4), ("f32", "f64", 1e5),
+    ("f32_comp", "f64", 1e4), ("f64", "f64", 1e4), ("f64", "f32", 1e4),
 ]
 
 
@@ -98,10 +98,10 @@ def test_precision_study(vg, ctx, sets):
               f"{err['e'][0]:.2e}  {err['H'][1]:.2e}  {err['b'][1]:.2e}")
     for name in ("regular", "regular_gt"):
         for accum in ("f32", "f32_comp", "f64"):
-            err = table[(name, accum, "ff", 0.0)]
+            err = table[(name, accum, "f64", 0.0)]
             assert max(err["H"][0], err["b"][0], err["e"][0]) <= 1e-5, (name, accum, err)
     for name in ("ill", "ill_gt"):
-        gated = table[(name, "f64", "ff", 1e4)]
-        plain = table[(name, "f64", "ff", 0.0)]
+        gated = table[(name, "f64", "f64", 1e4)]
+        plain = table[(name, "f64", "f64", 0.0)]
         assert max(gated["H"][0], gated["b"][0], gated["e"][0]) <= 1e-5, (name, gated)
         assert gated["H"][0] <= plain["H"][0], (name, plain, gated)
