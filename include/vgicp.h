@@ -162,7 +162,8 @@ int vgicp_ctx_destroy(vgicp_ctx ctx);
  * <= 0), ENONFINITE, ERANGE, ENOMEM, EHIP. */
 int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out);
 
-/* Map facts: number of voxels, hash capacity (slots), device bytes held and the
+/* Map facts: number of voxels, capacity of its brick table (records; voxels
+ * are indexed through bricks of 4 x 4 x 4), device bytes held and the
  * resolution.  Any output pointer may be NULL.  Errors: EINVAL. */
 int vgicp_map_info(vgicp_map map, int64_t *n_voxels, int64_t *capacity, int64_t *device_bytes,
                    double *resolution);
@@ -187,8 +188,9 @@ int vgicp_map_free(vgicp_map map);
  * owned, must outlive the factor set); maps: host array of n_maps handles;
  * factors: host array of n_factors rows; n_poses: length of the pose arrays
  * later calls pass; tile_points: source points per workgroup tile, a multiple
- * of 256 in [256, 1<<20], or 0 for automatic: 4096, halved (down to 1024)
- * while the factor set would have fewer than 3072 tiles.
+ * of 256 in [256, 1<<20], or 0 for automatic: the first of 4608, 3072, 2304,
+ * 1536 and 768 (whole lookup phases of a workgroup) that gives the factor set
+ * at least 3072 tiles, else 768.
  * Outputs of later calls are indexed in the order of `factors`.  Per-point
  * outputs (corr) are laid out factor after factor, n_src points each.
  * Errors: EINVAL (any index out of range, NULL pointers with nonzero counts,
@@ -294,7 +296,7 @@ typedef struct {
   int32_t max_batch_points;    /* source points per batch, >= 1                     */
   int32_t max_batch_poses;     /* poses per batch, >= 1                             */
   int32_t inflight;            /* batches on the device at once, 1..8                */
-  int32_t tile_points;         /* 0 = default (as vgicp_factorset_create)           */
+  int32_t tile_points;         /* 0 = 4608 (whole lookup phases of a workgroup)     */
   int32_t reserved;            /* must be 0                                         */
   vgicp_opts opts;             /* accumulation, residual, kappa of every batch
                                   (schedule and use_graph are ignored)              */

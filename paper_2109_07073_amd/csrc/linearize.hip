@@ -66,7 +66,6 @@ __device__ __forceinline__ void lookup_transform(const float R[9], const float t
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef const float __attribute__((address_space(1))) gfloat;
 typedef const f32x4 __attribute__((address_space(1))) gfloat4;
-typedef const uint64_t __attribute__((address_space(1))) gu64;
 
 __device__ __forceinline__ void load_xyz(const float *px, int64_t n, int64_t i, float p[3]) {
   gfloat *g = (gfloat *)px;
@@ -75,12 +74,17 @@ __device__ __forceinline__ void load_xyz(const float *px, int64_t n, int64_t i, 
   p[2] = __builtin_nontemporal_load(g + 2 * n + i);
 }
 
-// Packed key and home slot of the voxel holding q (ok = false when a key
-// would fall outside [-2^20, 2^20), which no voxel of any map has).
+typedef const uint32_t __attribute__((address_space(1))) gu32;
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef const u64x2 __attribute__((address_space(1))) gu64x2;
+
+// Brick key, home record and bit of the voxel holding q (ok = false when a
+// voxel key would fall outside [-2^20, 2^20), which no voxel of any map has).
 struct VoxelKey {
   bool ok;
-  uint64_t key;
-  uint32_t h;
+  uint64_t key;  // packed brick key
+  uint32_t h;    // home record
+  uint32_t bit;  // the voxel's bit in the brick's occupancy mask
 };
 
 __device__ __forceinline__ VoxelKey voxel_key(const float q[3], float s, uint32_t log2cap) {
@@ -88,32 +92,59 @@ __device__ __forceinline__ VoxelKey voxel_key(const float q[3], float s, uint32_
   VoxelKey r;
   r.ok = (vx >= -kKeyLimitF) & (vx < kKeyLimitF) & (vy >= -kKeyLimitF) & (vy < kKeyLimitF) &
          (vz >= -kKeyLimitF) & (vz < kKeyLimitF);
-  r.key = r.ok ? pack_key(int32_t(floorf(vx)), int32_t(floorf(vy)), int32_t(floorf(vz))) : 0;
+  const int32_t kx = r.ok ? int32_t(floorf(vx)) : 0;
+  const int32_t ky = r.ok ? int32_t(floorf(vy)) : 0;
+  const int32_t kz = r.ok ? int32_t(floorf(vz)) : 0;
+  r.key = pack_brick(kx, ky, kz);
+  r.bit = brick_bit(kx, ky, kz);
   r.h = hash_slot(r.key, log2cap);
   return r;
 }
 
-// Finish a linear probe whose home slot h held k0: the slot of `key` or -1
-// at the first empty slot.  At most `capacity` slots are visited.
-__device__ __forceinline__ int find_slot(const uint64_t *keys, uint32_t log2cap, uint64_t key,
-                                         uint32_t h, uint64_t k0) {
-  if (k0 == key) return int(h);
-  if (k0 == kEmptyKey) return -1;
-  // Rare: keep probing.  The full wait at the end leaves no load of this path
-  // in flight, so the common path's waits stay exact.
-  int r = -1;
-  const uint32_t mask = (1u << log2cap) - 1u;
-  for (uint32_t p = 0; p < mask; ++p) {
-    h = (h + 1u) & mask;
-    const uint64_t k = *(gu64 *)(keys + h);
-    if (k == key) {
-      r = int(h);
-      break;
-    }
-    if (k == kEmptyKey) break;
-  }
-  __builtin_amdgcn_s_waitcnt(0);
+// Issue the loads of a key's home record: key and mask (one 16-byte load)
+// and the payload base.
+struct RecordLoad {
+  u64x2 km;
+  uint32_t base;
+};
+
+__device__ __forceinline__ RecordLoad load_record(const BrickRecord *bricks, uint32_t h) {
+  RecordLoad r;
+  r.km = *(gu64x2 *)(bricks + h);
+  r.base = *(gu32 *)(&bricks[h].base);
   return r;
+}
+
+// Payload index of the voxel, or -1: the home record's brick, or the records
+// after it up to the first free one (linear probing), must hold the brick,
+// and its mask the voxel's bit.  At most `capacity` records are visited.
+__device__ __forceinline__ int find_voxel(const BrickRecord *bricks, uint32_t log2cap,
+                                          const VoxelKey &vk, const RecordLoad &home) {
+  uint64_t mask = home.km.y;
+  uint32_t base = home.base;
+  if (home.km.x != vk.key) {
+    if (home.km.x == kEmptyKey) return -1;
+    // Rare: keep probing.  The full wait at the end leaves no load of this
+    // path in flight, so the common path's waits stay exact.
+    bool found = false;
+    const uint32_t cm = (1u << log2cap) - 1u;
+    uint32_t h = vk.h;
+    for (uint32_t p = 0; p < cm; ++p) {
+      h = (h + 1u) & cm;
+      const u64x2 km = *(gu64x2 *)(bricks + h);
+      if (km.x == vk.key) {
+        mask = km.y;
+        base = *(gu32 *)(&bricks[h].base);
+        found = true;
+        break;
+      }
+      if (km.x == kEmptyKey) break;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (!found) return -1;
+  }
+  if (!((mask >> vk.bit) & 1ull)) return -1;
+  return int(base + uint32_t(__popcll(mask & ((1ull << vk.bit) - 1ull))));
 }
 
 // ---------------------------------------------------------------- sums
@@ -483,13 +514,14 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
 // Pending hits of one wave, a ring in LDS (structure of arrays).  A lookup
 // phase appends the lanes that found their voxel; the math then runs on full
 // batches of 64 hits, so misses cost no math lanes.
-constexpr int kChunk = 4;                    // lookup passes per phase
+constexpr int kChunk = kLookupPasses;  // lookup passes per phase of k_linearize (4 waves/SIMD)
+constexpr int kOvlChunk = 2;  // lookup passes per step of k_overlap (8 waves/SIMD)
 constexpr uint32_t kRing = 64 * kChunk + 64;  // >= 63 left over + 64 * kChunk appended
 
 struct HitQueue {
   float x[kRing], y[kRing], z[kRing];
   int32_t idx[kRing];   // point index in the source cloud
-  int32_t slot[kRing];  // slot of its voxel in the target map
+  int32_t pidx[kRing];  // payload index of its voxel in the target map
 };
 
 __device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
@@ -508,7 +540,7 @@ struct Batch {
 };
 
 // Reads the entry of each lane and issues its 9 global loads (no branches:
-// dead lanes of a partial batch read entry `head`, point 0 and slot 0).  Only
+// dead lanes of a partial batch read entry `head`, point 0 and payload 0).  Only
 // words that are used are loaded: a dead destination register could be
 // reused while its load is in flight, which forces an early wait.
 template <bool CORR>
@@ -518,12 +550,12 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   B.y = Q.y[e];
   B.z = Q.z[e];
   const int32_t idx = Q.idx[e];
-  const int32_t slot = Q.slot[e];
+  const int32_t pidx = Q.pidx[e];
   B.idx = live ? idx : 0;
   gfloat *gc = (gfloat *)pc;
 #pragma unroll
   for (int a = 0; a < 6; ++a) B.c[a] = __builtin_nontemporal_load(gc + a * n + B.idx);
-  const Payload *pl = payload + (live ? slot : 0);
+  const Payload *pl = payload + (live ? pidx : 0);
   gfloat4 *gp = (gfloat4 *)pl;
   B.w0 = gp[0];
   B.w1 = gp[1];
@@ -589,7 +621,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const int64_t n = fd.n;
   const float *__restrict__ px = fd.xyz;
   const float *__restrict__ pc = fd.cov;
-  const uint64_t *__restrict__ keys = fd.keys;
+  const BrickRecord *__restrict__ bricks = fd.bricks;
   const Payload *__restrict__ payload = fd.payload;
   const int64_t begin = td.start;
   const int64_t end = min(begin + int64_t(tile_points), n);
@@ -612,11 +644,12 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       load_xyz(px, n, min(base + p * kBlock + lane, end - 1), cur[p]);
   }
   while (base < end) {
-    // ---- lookup phase: the keys of all kChunk passes are in flight at once,
-    // then the next chunk's coordinates; keys are then resolved in order, so
-    // each wait leaves the later keys and the whole prefetch in flight.
+    // ---- lookup phase: the brick records of all kChunk passes are in flight
+    // at once, then the next chunk's coordinates; records are then resolved
+    // in order, so each wait leaves the later records and the whole prefetch
+    // in flight.
     VoxelKey vk[kChunk];
-    uint64_t k0[kChunk];
+    RecordLoad rec[kChunk];
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
       float q[3];
@@ -624,7 +657,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       vk[p] = voxel_key(q, fd.scale, fd.log2cap);
     }
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) k0[p] = *(gu64 *)(keys + vk[p].h);
+    for (int p = 0; p < kChunk; ++p) rec[p] = load_record(bricks, vk[p].h);
     __builtin_amdgcn_sched_barrier(0);
     float nxt[kChunk][3];
 #pragma unroll
@@ -635,7 +668,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     for (int p = 0; p < kChunk; ++p) {
       const int64_t i = base + p * kBlock + lane;
       const bool valid = i < end;
-      const int hs = find_slot(keys, fd.log2cap, vk[p].key, vk[p].h, k0[p]);
+      const int hs = find_voxel(bricks, fd.log2cap, vk[p], rec[p]);
       const int h = (valid && vk[p].ok) ? hs : -1;
       if constexpr (CORR) {
         if (valid && h < 0) pcorr[i] = -1;
@@ -649,7 +682,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
         Q.y[e] = cur[p][1];
         Q.z[e] = cur[p][2];
         Q.idx[e] = int32_t(i);
-        Q.slot[e] = h;
+        Q.pidx[e] = h;
       }
       const uint32_t got = uint32_t(__popcll(mask));
       count += got;
@@ -714,7 +747,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   }
 }
 
-// Overlap hit counts of one tile per block (Eq. (7)): keys only.
+// Overlap hit counts of one tile per block (Eq. (7)): brick records only.
 __global__ void __launch_bounds__(kBlock)
 k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
           int64_t tile_base, int64_t tile_end, int32_t tile_points,
@@ -731,39 +764,39 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   const int64_t end = min(begin + int64_t(tile_points), n);
   int hits = 0;
   const float *__restrict__ pk = px;
-  float cur[kChunk][3];
+  float cur[kOvlChunk][3];
   int64_t base = begin + int64_t(threadIdx.x & ~63);
   const int lane = threadIdx.x & 63;
   if (base < end) {
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p)
+    for (int p = 0; p < kOvlChunk; ++p)
       load_xyz(pk, n, min(base + p * kBlock + lane, end - 1), cur[p]);
   }
-  for (; base < end; base += kChunk * kBlock) {
-    VoxelKey vk[kChunk];
-    uint64_t k0[kChunk];
+  for (; base < end; base += kOvlChunk * kBlock) {
+    VoxelKey vk[kOvlChunk];
+    RecordLoad rec[kOvlChunk];
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) {
+    for (int p = 0; p < kOvlChunk; ++p) {
       float q[3];
       lookup_transform(k.R, k.t, cur[p][0], cur[p][1], cur[p][2], q);
       vk[p] = voxel_key(q, fd.scale, fd.log2cap);
     }
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) k0[p] = *(gu64 *)(fd.keys + vk[p].h);
+    for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_record(fd.bricks, vk[p].h);
     __builtin_amdgcn_sched_barrier(0);
-    float nxt[kChunk][3];
+    float nxt[kOvlChunk][3];
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p)
-      load_xyz(pk, n, min(base + (kChunk + p) * kBlock + lane, end - 1), nxt[p]);
+    for (int p = 0; p < kOvlChunk; ++p)
+      load_xyz(pk, n, min(base + (kOvlChunk + p) * kBlock + lane, end - 1), nxt[p]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) {
+    for (int p = 0; p < kOvlChunk; ++p) {
       const bool valid = base + p * kBlock + lane < end;
-      const int hs = find_slot(fd.keys, fd.log2cap, vk[p].key, vk[p].h, k0[p]);
+      const int hs = find_voxel(fd.bricks, fd.log2cap, vk[p], rec[p]);
       hits += (valid && vk[p].ok && hs >= 0) ? 1 : 0;
     }
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p)
+    for (int p = 0; p < kOvlChunk; ++p)
 #pragma unroll
       for (int a = 0; a < 3; ++a) cur[p][a] = nxt[p][a];
   }

@@ -52,9 +52,7 @@ int use_device(vgicp_ctx ctx) {
   return VGICP_OK;
 }
 
-constexpr int kDefaultTile = 4096;
-constexpr int kMinAutoTile = 1024;     // 4 lookup passes of a 256-thread block
-constexpr int64_t kMinAutoTiles = 3072;  // 4 tiles per resident block slot (256 CUs x 3)
+constexpr int64_t kMinAutoTiles = 3072;  // several tiles per resident block slot
 
 // Brackets one kernel launch with events when timing is on.
 struct TimedLaunch {
@@ -228,7 +226,7 @@ int vgicp_map_info(vgicp_map map, int64_t *n_voxels, int64_t *capacity, int64_t 
   if (n_voxels) *n_voxels = map->n_voxels;
   if (capacity) *capacity = map->capacity;
   if (device_bytes)
-    *device_bytes = map->capacity * int64_t(sizeof(uint64_t) + sizeof(Payload));
+    *device_bytes = map->device_bytes();
   if (resolution) *resolution = map->resolution;
   return VGICP_OK;
 }
@@ -306,16 +304,19 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
       return fail(ctx, VGICP_EINVAL,
                   "vgicp_factorset_create: map " + std::to_string(m) + " is NULL or foreign");
   if (tile_points == 0) {
-    // Automatic: the default tile, halved while the grid would not give every
-    // resident block slot several tiles (small factor sets such as a local
-    // submap), down to the smallest tile one lookup chunk of a block covers.
-    tile_points = kDefaultTile;
+    // Automatic: the default tile, made smaller (in steps of whole lookup
+    // phases) while the grid would not give every resident block slot several
+    // tiles (small factor sets such as a local submap).
     auto count_tiles = [&](int64_t tp) {
       int64_t t = 0;
       for (int64_t f = 0; f < n_factors; ++f) t += (sources[factors[f].src].n + tp - 1) / tp;
       return t;
     };
-    while (tile_points > kMinAutoTile && count_tiles(tile_points) < kMinAutoTiles) tile_points /= 2;
+    tile_points = kDefaultTile;
+    for (int q : {6, 4, 3, 2, 1}) {
+      tile_points = q * kTileQuantum;
+      if (count_tiles(tile_points) >= kMinAutoTiles) break;
+    }
   }
   int rc = use_device(ctx);
   if (rc) return rc;
@@ -344,7 +345,7 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     const vgicp_voxelmap_s *m = maps[x.tgt];
     d.xyz = c.xyz;
     d.cov = c.cov;
-    d.keys = m->keys;
+    d.bricks = m->bricks;
     d.payload = m->payload;
     d.n = c.n;
     d.corr_offset = corr_off;

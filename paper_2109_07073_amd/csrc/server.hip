@@ -42,7 +42,6 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr int kDefaultTile = 4096;
 
 struct Frame {
   bool live = false;
@@ -243,7 +242,7 @@ void launch_batch(vgicp_server srv, size_t si) {
       const Frame &tgt = srv->frames[size_t(x.tgt)];
       d.xyz = src.cloud;
       d.cov = src.cloud + 3 * src.n;
-      d.keys = tgt.map->keys;
+      d.bricks = tgt.map->bricks;
       d.payload = tgt.map->payload;
       d.n = src.n;
       d.pose_i = int32_t(pose_base + x.pose_i);
@@ -564,8 +563,7 @@ int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_
     (void)hipFree(fr.cloud);
     return srv_fail(srv, rc, msg);
   }
-  fr.bytes = int64_t(cloud_bytes) +
-             fr.map->capacity * int64_t(sizeof(uint64_t) + sizeof(Payload));
+  fr.bytes = int64_t(cloud_bytes) + fr.map->device_bytes();
   fr.live = true;
   std::unique_lock<std::mutex> g(srv->mu);
   if (srv->cfg.memory_budget_bytes > 0 && srv->used_bytes + fr.bytes > srv->cfg.memory_budget_bytes) {

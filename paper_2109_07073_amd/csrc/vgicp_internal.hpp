@@ -36,28 +36,70 @@ __host__ __device__ inline uint32_t hash_slot(uint64_t key, uint32_t log2cap) {
   return uint32_t((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// A voxel map is an open-addressed table in two arrays indexed by slot:
-//   keys[cap]     packed voxel keys (kEmptyKey for empty slots), probed by
-//                 every lookup; 16 keys share a 128-byte line, so the lines a
-//                 factor's misses touch are few;
-//   payload[cap]  the voxel's statistics, read only when the key matched.
-// A payload is 64 bytes so that it never straddles a 128-byte line.
+// ---------------------------------------------------------------- bricks
+// Voxels are grouped in bricks of 4 x 4 x 4.  A brick key packs floor(k / 4)
+// per axis as three biased 19-bit fields (57 bits); voxel (kx, ky, kz) is bit
+// (kx & 3) << 4 | (ky & 3) << 2 | (kz & 3) of its brick's 64-bit occupancy
+// mask.  Consecutive points of a scan mostly fall in the same or neighbouring
+// bricks, so their lookups share brick records (and cache lines) instead of
+// scattering over a voxel-keyed table.
+constexpr int kBrickBits = 19;
+constexpr int32_t kBrickBias = 1 << 18;  // floor(k / 4) lies in [-2^18, 2^18)
+
+__host__ __device__ inline uint64_t pack_brick(int32_t kx, int32_t ky, int32_t kz) {
+  return (uint64_t(uint32_t((kx >> 2) + kBrickBias)) << (2 * kBrickBits)) |
+         (uint64_t(uint32_t((ky >> 2) + kBrickBias)) << kBrickBits) |
+         uint64_t(uint32_t((kz >> 2) + kBrickBias));
+}
+
+__host__ __device__ inline uint32_t brick_bit(int32_t kx, int32_t ky, int32_t kz) {
+  return (uint32_t(kx & 3) << 4) | (uint32_t(ky & 3) << 2) | uint32_t(kz & 3);
+}
+
+// A voxel map is an open-addressed table of brick records (linear probing,
+// load factor at most 1/8) plus a dense payload array:
+//   bricks[cap]  32-byte records {brick key (kEmptyKey when free), occupancy
+//                mask, payload index of the brick's first voxel}; a lookup
+//                reads key and mask with one 16-byte load and the base with
+//                a second load from the same record;
+//   payload[V]   the voxels' statistics, brick after brick and by mask bit
+//                within a brick, so voxel b of a brick sits at
+//                base + popcount(mask & (2^b - 1)).
+struct alignas(32) BrickRecord {
+  uint64_t key;
+  uint64_t mask;
+  uint32_t base;
+  uint32_t pad[3];
+};
+static_assert(sizeof(BrickRecord) == 32, "brick record layout");
+
+// A payload is 64 bytes so that it never straddles a 128-byte line.  The
+// packed voxel key is kept for the map export.
 struct alignas(64) Payload {
   float mean[3];
   float cov[6];  // xx xy xz yy yz zz
   int32_t ordinal;
   int32_t count;
-  int32_t pad[5];
+  int32_t pad0;
+  uint64_t key;
+  int32_t pad1[2];
 };
 static_assert(sizeof(Payload) == 64, "payload layout");
 
 // ---------------------------------------------------------------- factors
+// Tiles.  A 256-thread block of k_linearize looks up kLookupPasses rows of
+// 256 points per phase, so tiles that are multiples of kTileQuantum points
+// leave no phase partly empty.
+constexpr int kLookupPasses = 3;
+constexpr int kTileQuantum = 256 * kLookupPasses;
+constexpr int kDefaultTile = 6 * kTileQuantum;  // 4608 points
+
 // Per-factor device descriptor (read with uniform loads by every tile).
 struct FactorDesc {
   const float *xyz;        // [3][n]
   const float *cov;        // [6][n]
-  const uint64_t *keys;    // target map: slot keys
-  const Payload *payload;  // target map: slot payloads
+  const BrickRecord *bricks;  // target map: brick table
+  const Payload *payload;     // target map: dense voxel payloads
   int64_t n;          // source points
   int64_t corr_offset;
   int32_t pose_i;
@@ -113,9 +155,14 @@ struct vgicp_voxelmap_s {
   uint32_t log2cap = 0;
   float scale = 0.f;
   double resolution = 0.0;
-  void *buffer = nullptr;             // one allocation: keys, then payloads
-  uint64_t *keys = nullptr;
+  int64_t n_bricks = 0;
+  void *buffer = nullptr;             // one allocation: brick table, then payloads
+  vgicp::BrickRecord *bricks = nullptr;
   vgicp::Payload *payload = nullptr;
+  int64_t device_bytes() const {
+    return capacity * int64_t(sizeof(vgicp::BrickRecord)) +
+           n_voxels * int64_t(sizeof(vgicp::Payload));
+  }
 };
 
 struct GraphEntry {

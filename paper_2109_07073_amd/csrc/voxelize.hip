@@ -1,14 +1,16 @@
 // Voxel-map construction on gfx950 (Sec. III-A, VGICP voxel data association).
 //
-// A cloud becomes an open-addressed hash table keyed by the packed voxel key
-// (a key array and a payload array indexed by slot).  Each payload carries
-// the voxel mean and the mean of the point covariances (the VGICP aggregation
-// of point distributions), both accumulated in FP64 in point order and
-// rounded once to FP32.
+// Each voxel carries the mean of its points and the mean of their
+// covariances (the VGICP aggregation of point distributions), accumulated in
+// FP64 in point order and rounded once to FP32.  Voxels are stored densely,
+// brick after brick (bricks of 4 x 4 x 4 voxels), and found through an
+// open-addressed table of brick records holding each brick's occupancy mask.
 //
-// Steps: keys -> radix sort of (key, point index) -> segment heads -> scan
-// -> segment starts -> [one host sync to size the table] -> FP64 segment sums
-// and hash insertion.  This runs once per cloud, off the per-iteration path.
+// Steps: keys -> radix sort of (key, point index) -> segment heads -> scan ->
+// segment starts -> [host sync: voxel count] -> per voxel its brick-major
+// sort key -> radix sort of (brick key and bit, voxel ordinal) -> brick heads
+// -> scan -> brick starts -> [host sync: brick count] -> brick table insertion
+// and FP64 voxel sums.  This runs once per cloud, off the per-iteration path.
 
 #include <cstring>
 
@@ -62,20 +64,78 @@ k_segment_starts(const uint32_t *__restrict__ head, const uint32_t *__restrict__
   if (i == n - 1) seg[ord1[i]] = uint32_t(n);
 }
 
-__global__ void __launch_bounds__(256) k_fill_empty(uint64_t *__restrict__ keys, int64_t cap) {
+__global__ void __launch_bounds__(256)
+k_fill_empty(BrickRecord *__restrict__ bricks, int64_t cap) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < cap) keys[i] = kEmptyKey;
+  if (i < cap) {
+    BrickRecord r;
+    r.key = kEmptyKey;
+    r.mask = 0;
+    r.base = 0;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    bricks[i] = r;
+  }
 }
 
-// One thread per voxel: sequential FP64 sums over the voxel's points in point
-// order, one FP64 division, one rounding to FP32, then linear-probing insert.
+// Per voxel (in lexicographic order): its packed key and its brick-major sort
+// key (brick key above the 6-bit position in the brick).
 __global__ void __launch_bounds__(256)
-k_build_slots(const float *__restrict__ xyz, const float *__restrict__ cov, int64_t n,
-              const uint64_t *__restrict__ sorted_keys, const uint32_t *__restrict__ sorted_idx,
-              const uint32_t *__restrict__ seg, int64_t n_voxels, uint64_t *__restrict__ keys,
-              Payload *__restrict__ payload, uint32_t log2cap) {
+k_brick_sortkeys(const uint64_t *__restrict__ sorted_keys, const uint32_t *__restrict__ seg,
+                 int64_t n_voxels, uint64_t *__restrict__ vkey, uint64_t *__restrict__ bsort,
+                 uint32_t *__restrict__ vord) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n_voxels) return;
+  const uint64_t key = sorted_keys[seg[v]];
+  const int32_t kx = key_field(key, 0), ky = key_field(key, 1), kz = key_field(key, 2);
+  vkey[v] = key;
+  bsort[v] = (pack_brick(kx, ky, kz) << 6) | uint64_t(brick_bit(kx, ky, kz));
+  vord[v] = uint32_t(v);
+}
+
+__global__ void __launch_bounds__(256)
+k_brick_heads(const uint64_t *__restrict__ bsort, int64_t n_voxels, uint32_t *__restrict__ head) {
+  const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (d >= n_voxels) return;
+  head[d] = (d == 0 || (bsort[d] >> 6) != (bsort[d - 1] >> 6)) ? 1u : 0u;
+}
+
+// One thread per brick: its occupancy mask from its voxels' bits, then
+// linear-probing insertion of the record.
+__global__ void __launch_bounds__(256)
+k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ bstart,
+               int64_t n_bricks, int64_t n_voxels, BrickRecord *__restrict__ bricks,
+               uint32_t log2cap) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= n_bricks) return;
+  const uint32_t d0 = bstart[b];
+  const uint32_t d1 = (b + 1 < n_bricks) ? bstart[b + 1] : uint32_t(n_voxels);
+  uint64_t mask = 0;
+  for (uint32_t d = d0; d < d1; ++d) mask |= 1ull << (bsort[d] & 63u);
+  const uint64_t key = bsort[d0] >> 6;
+  const uint32_t cmask = (1u << log2cap) - 1u;
+  uint32_t h = hash_slot(key, log2cap);
+  for (uint32_t probe = 0; probe <= cmask; ++probe) {
+    const unsigned long long prev =
+        atomicCAS(reinterpret_cast<unsigned long long *>(&bricks[h].key),
+                  (unsigned long long)kEmptyKey, (unsigned long long)key);
+    if (prev == kEmptyKey) break;
+    h = (h + 1u) & cmask;
+  }
+  bricks[h].mask = mask;
+  bricks[h].base = d0;
+}
+
+// One thread per voxel, by dense (brick-major) position d: sequential FP64
+// sums over the voxel's points in point order, one FP64 division, one
+// rounding to FP32.
+__global__ void __launch_bounds__(256)
+k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, int64_t n,
+                const uint32_t *__restrict__ sorted_idx, const uint32_t *__restrict__ seg,
+                const uint32_t *__restrict__ vord, const uint64_t *__restrict__ vkey,
+                int64_t n_voxels, Payload *__restrict__ payload) {
+  const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (d >= n_voxels) return;
+  const uint32_t v = vord[d];
   const uint32_t b = seg[v], e = seg[v + 1];
   double sm[3] = {0.0, 0.0, 0.0};
   double sc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -87,16 +147,6 @@ k_build_slots(const float *__restrict__ xyz, const float *__restrict__ cov, int6
     for (int a = 0; a < 6; ++a) sc[a] += double(cov[a * n + p]);
   }
   const double cnt = double(e - b);
-  const uint64_t key = sorted_keys[b];
-  const uint32_t mask = (1u << log2cap) - 1u;
-  uint32_t h = hash_slot(key, log2cap);
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
-    const unsigned long long prev =
-        atomicCAS(reinterpret_cast<unsigned long long *>(&keys[h]),
-                  (unsigned long long)kEmptyKey, (unsigned long long)key);
-    if (prev == kEmptyKey) break;
-    h = (h + 1u) & mask;
-  }
   Payload pl;
 #pragma unroll
   for (int a = 0; a < 3; ++a) pl.mean[a] = float(sm[a] / cnt);
@@ -104,24 +154,22 @@ k_build_slots(const float *__restrict__ xyz, const float *__restrict__ cov, int6
   for (int a = 0; a < 6; ++a) pl.cov[a] = float(sc[a] / cnt);
   pl.ordinal = int32_t(v);
   pl.count = int32_t(e - b);
-#pragma unroll
-  for (int a = 0; a < 5; ++a) pl.pad[a] = 0;
-  payload[h] = pl;
+  pl.pad0 = 0;
+  pl.key = vkey[v];
+  pl.pad1[0] = pl.pad1[1] = 0;
+  payload[d] = pl;
 }
 
 __global__ void __launch_bounds__(256)
-k_export(const uint64_t *__restrict__ keys_tab, const Payload *__restrict__ payload, int64_t cap,
-         int32_t *__restrict__ keys, float *__restrict__ mean, float *__restrict__ cov,
-         int32_t *__restrict__ count) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= cap) return;
-  const uint64_t key = keys_tab[i];
-  if (key == kEmptyKey) return;
-  const Payload s = payload[i];
+k_export(const Payload *__restrict__ payload, int64_t n_voxels, int32_t *__restrict__ keys,
+         float *__restrict__ mean, float *__restrict__ cov, int32_t *__restrict__ count) {
+  const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (d >= n_voxels) return;
+  const Payload s = payload[d];
   const int64_t o = s.ordinal;
   if (keys) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(key, a);
+    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(s.key, a);
   }
   if (mean) {
 #pragma unroll
@@ -141,9 +189,12 @@ static inline unsigned grid_for(int64_t n, int block = 256) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Scratch layout for n points; returns total bytes (rocPRIM temp included).
+// After the point sort, keys_in, idx_in, head, ord1 and spare are reused for
+// the per-voxel arrays (V <= n): vkey, vord_in, bhead, bord1, vord_out;
+// bsort_in/out hold the brick-major sort keys and bstart the brick starts.
 struct VoxScratch {
-  uint64_t *keys_in, *keys_out;
-  uint32_t *idx_in, *idx_out, *head, *ord1, *seg;
+  uint64_t *keys_in, *keys_out, *bsort_in, *bsort_out;
+  uint32_t *idx_in, *idx_out, *head, *ord1, *spare, *seg, *bstart;
   void *temp;
   size_t temp_bytes;
 };
@@ -159,7 +210,7 @@ static hipError_t plan_scratch(int64_t n, hipStream_t stream, size_t *total, siz
                                 rocprim::plus<uint32_t>(), stream);
   if (err != hipSuccess) return err;
   const size_t nn = size_t(n);
-  *total = 2 * align256(8 * nn) + 5 * align256(4 * nn) + align256(4 * (nn + 1)) +
+  *total = 4 * align256(8 * nn) + 5 * align256(4 * nn) + 2 * align256(4 * (nn + 1)) +
            align256(std::max(sb, cb));
   *sort_bytes = sb;
   *scan_bytes = cb;
@@ -174,6 +225,10 @@ static VoxScratch carve(void *base, int64_t n, size_t temp_bytes) {
   p += align256(8 * nn);
   s.keys_out = reinterpret_cast<uint64_t *>(p);
   p += align256(8 * nn);
+  s.bsort_in = reinterpret_cast<uint64_t *>(p);
+  p += align256(8 * nn);
+  s.bsort_out = reinterpret_cast<uint64_t *>(p);
+  p += align256(8 * nn);
   s.idx_in = reinterpret_cast<uint32_t *>(p);
   p += align256(4 * nn);
   s.idx_out = reinterpret_cast<uint32_t *>(p);
@@ -182,8 +237,11 @@ static VoxScratch carve(void *base, int64_t n, size_t temp_bytes) {
   p += align256(4 * nn);
   s.ord1 = reinterpret_cast<uint32_t *>(p);
   p += align256(4 * nn);
-  p += align256(4 * nn);  // spare
+  s.spare = reinterpret_cast<uint32_t *>(p);
+  p += align256(4 * nn);
   s.seg = reinterpret_cast<uint32_t *>(p);
+  p += align256(4 * (nn + 1));
+  s.bstart = reinterpret_cast<uint32_t *>(p);
   p += align256(4 * (nn + 1));
   s.temp = p;
   s.temp_bytes = temp_bytes;
@@ -269,17 +327,69 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
     n_voxels = int64_t(ctx->host_pinned[1]);
   }
 
-  // Load factor at most 1/8: a lookup that misses (most points of a partial
-  // overlap) then almost always finds an empty home slot or one more probe.
-  // Slots are int32 indices, so the table stops at 2^31 slots (load <= 1/2).
+  // Brick order: sort the voxels by (brick key, position in the brick).
+  int64_t n_bricks = 0;
+  uint64_t *vkey = sc.keys_in;
+  uint32_t *vord_in = sc.idx_in, *bhead = sc.head, *bord1 = sc.ord1, *vord_out = sc.spare;
+  if (n_voxels > 0) {
+    size_t need_sort = 0, need_scan = 0;
+    HIP_TRY(rocprim::radix_sort_pairs(nullptr, need_sort, (uint64_t *)nullptr,
+                                      (uint64_t *)nullptr, (uint32_t *)nullptr,
+                                      (uint32_t *)nullptr, size_t(n_voxels), 0, 63, st));
+    HIP_TRY(rocprim::inclusive_scan(nullptr, need_scan, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                    size_t(n_voxels), rocprim::plus<uint32_t>(), st));
+    // rocPRIM's temporary storage for V <= n elements normally fits in the
+    // storage planned for n; if it does not, this phase gets its own.
+    void *temp = sc.temp;
+    size_t temp_bytes = sc.temp_bytes;
+    void *own_temp = nullptr;
+    if (need_sort > temp_bytes || need_scan > temp_bytes) {
+      temp_bytes = std::max(need_sort, need_scan);
+      HIP_TRY(hipMalloc(&own_temp, temp_bytes));
+      temp = own_temp;
+    }
+    const int64_t V = n_voxels;
+    k_brick_sortkeys<<<grid_for(V), 256, 0, st>>>(sc.keys_out, sc.seg, V, vkey, sc.bsort_in,
+                                                   vord_in);
+    HIP_TRY(hipGetLastError());
+    size_t tb = temp_bytes;
+    hipError_t pe = rocprim::radix_sort_pairs(temp, tb, sc.bsort_in, sc.bsort_out, vord_in,
+                                              vord_out, size_t(V), 0, 63, st);
+    if (pe == hipSuccess) {
+      k_brick_heads<<<grid_for(V), 256, 0, st>>>(sc.bsort_out, V, bhead);
+      pe = hipGetLastError();
+    }
+    tb = temp_bytes;
+    if (pe == hipSuccess)
+      pe = rocprim::inclusive_scan(temp, tb, bhead, bord1, size_t(V), rocprim::plus<uint32_t>(),
+                                   st);
+    if (pe == hipSuccess) {
+      k_segment_starts<<<grid_for(V), 256, 0, st>>>(bhead, bord1, V, sc.bstart);
+      pe = hipGetLastError();
+    }
+    if (pe == hipSuccess)
+      pe = hipMemcpyAsync(ctx->host_pinned + 1, bord1 + (V - 1), sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, st);
+    if (pe == hipSuccess) pe = hipStreamSynchronize(st);
+    if (own_temp) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(own_temp);
+    }
+    HIP_TRY(pe);
+    n_bricks = int64_t(ctx->host_pinned[1]);
+  }
+
+  // Load factor at most 1/8: a lookup in an empty brick (most misses of a
+  // partial overlap) almost always stops at an empty home record or one
+  // probe later.  Slots are 32-bit indices, so the table stops at 2^31.
   int64_t cap = 16;
   uint32_t log2cap = 4;
-  while (cap < 8 * n_voxels && cap < (int64_t(1) << 31)) {
+  while (cap < 8 * n_bricks && cap < (int64_t(1) << 31)) {
     cap <<= 1;
     ++log2cap;
   }
-  if (cap < 2 * n_voxels) {
-    msg = "vgicp_voxelize: more than 2^30 voxels in one map";
+  if (cap < 2 * n_bricks) {
+    msg = "vgicp_voxelize: more than 2^30 bricks in one map";
     return VGICP_EINVAL;
   }
   vgicp_map m = new (std::nothrow) vgicp_voxelmap_s();
@@ -289,26 +399,29 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
   }
   m->device = ctx->device;
   m->n_voxels = n_voxels;
+  m->n_bricks = n_bricks;
   m->capacity = cap;
   m->log2cap = log2cap;
   m->scale = s;
   m->resolution = resolution;
-  const size_t key_bytes = (size_t(cap) * sizeof(uint64_t) + 255) & ~size_t(255);
-  hipError_t e = hipMalloc(&m->buffer, key_bytes + size_t(cap) * sizeof(Payload));
+  const size_t brick_bytes = align256(size_t(cap) * sizeof(BrickRecord));
+  hipError_t e = hipMalloc(&m->buffer, brick_bytes + size_t(n_voxels) * sizeof(Payload));
   if (e == hipSuccess) {
-    m->keys = static_cast<uint64_t *>(m->buffer);
-    m->payload = reinterpret_cast<Payload *>(static_cast<char *>(m->buffer) + key_bytes);
+    m->bricks = static_cast<BrickRecord *>(m->buffer);
+    m->payload = reinterpret_cast<Payload *>(static_cast<char *>(m->buffer) + brick_bytes);
   }
   if (e != hipSuccess) {
     delete m;
-    msg = std::string("vgicp_voxelize: hipMalloc of the hash table: ") + hipGetErrorString(e);
+    msg = std::string("vgicp_voxelize: hipMalloc of the voxel map: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP;
   }
-  k_fill_empty<<<grid_for(cap), 256, 0, st>>>(m->keys, cap);
+  k_fill_empty<<<grid_for(cap), 256, 0, st>>>(m->bricks, cap);
   if (n_voxels > 0) {
-    k_build_slots<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.keys_out,
-                                                       sc.idx_out, sc.seg, n_voxels, m->keys,
-                                                       m->payload, log2cap);
+    k_build_bricks<<<grid_for(n_bricks), 256, 0, st>>>(sc.bsort_out, sc.bstart, n_bricks,
+                                                       n_voxels, m->bricks, log2cap);
+    k_build_payload<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.idx_out,
+                                                        sc.seg, vord_out, vkey, n_voxels,
+                                                        m->payload);
   }
   e = hipGetLastError();
   if (e != hipSuccess) {
@@ -324,8 +437,8 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg) {
   if (m->n_voxels == 0) return VGICP_OK;
-  k_export<<<grid_for(m->capacity), 256, 0, ctx->stream>>>(m->keys, m->payload, m->capacity, keys,
-                                                           mean, cov, count);
+  k_export<<<grid_for(m->n_voxels), 256, 0, ctx->stream>>>(m->payload, m->n_voxels, keys, mean,
+                                                           cov, count);
   HIP_TRY(hipGetLastError());
   return VGICP_OK;
 }

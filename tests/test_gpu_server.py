@@ -55,7 +55,7 @@ def test_alone_mix_split_and_factorset_agree(vg, scans):
     ctx = vg.Context(0)
     dev = [vg.cloud_to_device(x, c) for (x, c) in scans.targets]
     maps = [vg.voxelize(ctx, x, c, scans.resolution) for (x, c) in dev]
-    fs = vg.FactorSet(ctx, dev, maps, scans.factors[:15], scans.poses.shape[0], tile_points=4096)
+    fs = vg.FactorSet(ctx, dev, maps, scans.factors[:15], scans.poses.shape[0], tile_points=4608)
     out = vg.linearize_factors(ctx, fs, torch.from_numpy(scans.poses).to("cuda"))
     ctx.synchronize()
     for k in ("H", "b", "e", "inliers"):
@@ -87,7 +87,7 @@ def test_memory_budget_admission(vg, scans):
             srv.add_frame(*scans.targets[0], scans.resolution)
         assert ex.value.code == vg.EFULL
         assert srv.memory()[0] == 0
-    # frame sizes differ (the hash capacity is a power of two): measure each
+    # frame sizes differ (the brick table size is a power of two): measure each
     size = []
     with vg.Server() as probe:
         for k in range(3):
