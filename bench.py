@@ -511,8 +511,9 @@ def run_local(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed rounds first (the GPU clocks ramp up over the first few)")
     ap.add_argument("--workload", default="batched4500", choices=sorted(WORKLOADS))
     ap.add_argument("--accum", default="f32", choices=["f32", "f32_comp", "f64"])
     ap.add_argument("--tile", type=int, default=0)

@@ -9,9 +9,9 @@ every accumulation variant."""
 import numpy as np
 import pytest
 
-from synth import make_scan_workload, make_single_factor, make_tiny_workload, pose_rows
+from synth import Workload, make_scan_workload, make_single_factor, make_tiny_workload, pose_rows
 from tests.gpu_helpers import (TOL, GpuWorkload, assert_linearize_parity,
-                               oracle_results)
+                               oracle_results, rel_fro)
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -272,6 +272,47 @@ def test_self_overlap_is_one_and_far_is_zero(vg, ctx, scans):
     ctx.synchronize()
     assert out["hits"].tolist() == [xyz.shape[0], 0]
     assert out["overlap"].tolist() == [1.0, 0.0]
+
+
+def test_transforms_beyond_the_key_range_miss(vg, ctx, cfg1):
+    """Source points carried near and past the edge of the key range
+    (|key| >= 2^20 voxels) miss like the oracle's, partly in range and partly
+    out; nothing is added for them."""
+    from tests.oracle_pins import hom, rows
+    w = cfg1
+    poses = [w.poses[0], w.poses[1]]
+    for shift in (1048560.0, 1048600.0, -1048590.0, 3.0e7):
+        Ti = hom(w.poses[0])
+        Ti[:3, 3] += [shift * w.resolution, 0.0, 0.0]
+        poses.append(rows(Ti))
+    poses = np.stack(poses)
+    factors = np.array([[0, 0, k, 1] for k in range(len(poses)) if k != 1], np.int32)
+    wf = Workload(name="edge", resolution=w.resolution, sources=w.sources, targets=w.targets,
+                  poses=poses, factors=factors, meta={})
+    _, ref = oracle_results(wf, with_corr=True)
+    g = GpuWorkload(vg, ctx, wf)
+    got = g.linearize(with_corr=True)
+    assert_linearize_parity(got, ref)
+    assert np.array_equal(got["corr"], np.concatenate(ref["corr"]))
+    assert ref["inliers"][0] > 0 and np.all(ref["inliers"][1:] == 0)
+    ov = g.overlap()
+    assert np.array_equal(ov["hits"], ref["inliers"])
+
+
+def test_automatic_tile_size(vg, ctx, cfg1, ragged):
+    """Small factor sets get the smallest whole-phase tile (768 points); an
+    explicit tile is kept; results do not depend on it beyond rounding."""
+    g = GpuWorkload(vg, ctx, ragged)
+    assert g.fs.tile_points == 768
+    fs = vg.FactorSet(ctx, g.src, g.maps, ragged.factors, ragged.poses.shape[0], 4608)
+    assert fs.tile_points == 4608
+    a = g.linearize()
+    b = vg.linearize_factors(ctx, fs, g.poses)
+    ctx.synchronize()
+    assert np.array_equal(a["inliers"], b["inliers"].cpu().numpy())
+    for f in range(ragged.factors.shape[0]):
+        if a["inliers"][f]:
+            assert rel_fro(b["H"][f].cpu().numpy(), a["H"][f]) < TOL
 
 
 def test_empty_factor_set_is_a_no_op(vg, ctx, cfg1):
