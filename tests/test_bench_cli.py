@@ -1,0 +1,27 @@
+"""bench.py command line (CPU only): one GPU only, and the JSON contract of the
+refusal line."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_profiled_traffic_follows_the_sources():
+    """The roofline traffic figure is reported only for a profiled workload
+    whose kernel sources still hash to the profiled ones."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.profiled_traffic("batched4500")
+    assert t is None or t > 3.0e9
+    assert bench.profiled_traffic("no_such_workload") is None
