@@ -58,11 +58,11 @@ def build_workload(name: str):
                               n_factors=spec["n_factors"], src_range=spec["src_range"])
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(workload: str, tile_points: int | None = None):
     """HBM bytes per linearize launch measured by rocprofv3 (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) for this workload, from
-    profiles/k_linearize_<workload>.md, or None when there is no profile or
-    the kernel sources have changed since it was taken."""
+    profiles/k_linearize_<workload>.md, or None when there is no profile, the
+    kernel sources have changed since it was taken, or the tile size differs."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_linearize_{workload}.md")
     if not os.path.exists(path):
@@ -71,7 +71,7 @@ def profiled_traffic(workload: str):
     with open(path) as fh:
         for line in fh:
             key, _, val = line.strip().partition(": ")
-            if key in ("traffic_bytes_per_launch", "source_sha256_16"):
+            if key in ("traffic_bytes_per_launch", "source_sha256_16", "tile_points"):
                 fields[key] = val.strip()
     csrc = os.path.join(ROOT, "paper_2109_07073_amd", "csrc")
     h = hashlib.sha256()
@@ -79,6 +79,8 @@ def profiled_traffic(workload: str):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    if tile_points is not None and fields.get("tile_points") != str(tile_points):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -544,6 +546,9 @@ def main():
     w = build_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.n_factors} factors, {w.source_points()} source points, "
         f"generated in {time.perf_counter() - t_gen:.1f} s")
+    # two 50,000-point scans 1 m apart for the single-pair overlap latency
+    from synth import stream_scan_frames
+    pair = [(x, c, T) for (_, T, x, c) in stream_scan_frames(2, 2, n_points=50000, workers=1)]
     cpu_run = None
     if not args.no_cpu_baseline:
         cpu_run = cpu_baseline(w, workers=max(1, min(args.cpu_workers, os.cpu_count() or 1)))
@@ -570,6 +575,11 @@ def main():
     map_bytes = int(sum(m.device_bytes for m in maps))
     fs = vg.FactorSet(ctx, src, maps, w.factors, w.poses.shape[0], args.tile)
     poses = torch.from_numpy(np.ascontiguousarray(w.poses)).to("cuda")
+    tuned = None
+    if not args.tile:      # measure the candidate tile sizes and keep the fastest
+        best, best_ms = vg.tune_tiles(ctx, fs, poses, accum=args.accum)
+        tuned = {"tile_points": best, "round_ms": round(best_ms, 4)}
+        log(f"[bench] tile autotuned: {best} points ({best_ms:.3f} ms per round)")
     F = fs.n_factors
     log(f"[bench] {len(maps)} voxel maps ({n_vox} voxels, {map_bytes / 2**20:.1f} MiB) in "
         f"{t_vox * 1e3:.1f} ms; {fs.n_tiles} tiles")
@@ -583,6 +593,29 @@ def main():
         vg.overlap(ctx, fs, poses, out=ov)
     ctx.synchronize()
     t_ov = (time.perf_counter() - t0) / ov_reps
+
+    # ---- one overlap check between two 50,000-point scans (factor creation)
+    pair_dev = [vg.cloud_to_device(x, c) for (x, c, _) in pair]
+    pair_maps = [vg.voxelize(ctx, x, c, w.resolution) for (x, c) in pair_dev]
+    pair_fs = vg.FactorSet(ctx, pair_dev, pair_maps, [(1, 0, 1, 0)], 2)
+    from synth import pose_rows
+    pair_poses = torch.from_numpy(pose_rows([T for (_, _, T) in pair])).to("cuda")
+    pov = vg.overlap(ctx, pair_fs, pair_poses)
+    for _ in range(20):
+        vg.overlap(ctx, pair_fs, pair_poses, out=pov)
+    torch.cuda.synchronize()
+    pair_dev_ms, pair_host_ms = [], []
+    for _ in range(100):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        h0 = time.perf_counter()
+        a.record(stream)
+        vg.overlap(ctx, pair_fs, pair_poses, out=pov)
+        b.record(stream)
+        stream.synchronize()
+        pair_host_ms.append((time.perf_counter() - h0) * 1e3)
+        pair_dev_ms.append(a.elapsed_time(b))
+    pair_overlap = float(pov["overlap"].cpu()[0])
 
     # ---- outputs, correspondences, distinct voxels
     out = vg.linearize_factors(ctx, fs, poses, accum=args.accum, with_corr=True)
@@ -633,7 +666,7 @@ def main():
     alg_bytes = float(36 * sizes.sum() + 44 * U.sum())          # per linearize launch
     strict_bytes = float(12 * sizes.sum() + 24 * n_corr + 44 * U.sum())
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    traffic = profiled_traffic(args.workload) if args.accum == "f32" and not args.tile else None
+    traffic = profiled_traffic(args.workload, fs.tile_points) if args.accum == "f32" else None
 
     # ---- plain per-factor launches on the same factors
     plain = None
@@ -695,7 +728,7 @@ def main():
             "correspondences_per_round": n_corr,
             "resolution_m": w.resolution,
             "accumulation": args.accum,
-            "schedule": "batched, HIP graph replay",
+            "schedule": "batched, HIP graph replay" + (", autotuned tile" if tuned else ""),
             "tile_points": int(fs.tile_points),
             "seed": w.meta.get("seed"),
         },
@@ -725,6 +758,9 @@ def main():
             "voxelize_all_maps_ms": round(t_vox * 1e3, 3),
             "maps": len(maps),
             "overlap_all_pairs_ms": round(t_ov * 1e3, 4),
+            "overlap_one_pair_50k_ms": {"device_p50": float(np.percentile(pair_dev_ms, 50)),
+                                        "host_visible_p50": float(np.percentile(pair_host_ms, 50)),
+                                        "overlap": round(pair_overlap, 4)},
             "evaluate_round_ms": round(ev_ms, 4),
             "distinct_voxels_touched": int(U.sum()),
         },

@@ -205,6 +205,22 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
                          int64_t *total_points, int32_t *tile_points);
 
+/* Tile-size autotuning (the batched schedule of Sec. III-D's one-launch
+ * linearization round): after 10 warm-up rounds, time a linearization round
+ * of this factor set at these poses for each candidate tile size (twice, in
+ * forward and reverse order, keeping each candidate's best) (host int32 array of multiples of
+ * 256 in [256, 2^20]; NULL = 4608, 3072, 2304, 1536, 768, whole lookup phases
+ * of a workgroup) and keep the fastest.  H, b, e, inliers are device buffers
+ * as for vgicp_linearize_factors, overwritten by the trial rounds.  The
+ * factor set's tiles change (results change only by FP32 summation order) and
+ * its captured graphs are dropped.  best_tile and best_ms (mean device time
+ * of a round) may be NULL.  Synchronizes ctx's stream.
+ * Errors: EINVAL, EHIP. */
+int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                         const vgicp_opts *opts, double *H, double *b, double *e,
+                         int64_t *inliers, const int32_t *candidates, int32_t n_candidates,
+                         int32_t *best_tile, double *best_ms);
+
 /* Free a factor set and its captured graphs (NULL accepted). */
 int vgicp_factorset_destroy(vgicp_factorset fs);
 

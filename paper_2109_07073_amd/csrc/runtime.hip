@@ -364,6 +364,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
   }
   fs->n_tiles = int64_t(tiles.size());
+  fs->tiles_capacity = std::max<int64_t>(1, fs->n_tiles);
+  fs->tile_order = order;
 
   // CSR of system-assembly contributions (factor order within each pose/pair)
   std::vector<int64_t> pose_off(size_t(n_poses) + 1, 0), pose_ent;
@@ -433,6 +435,57 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   *out = fs;
   return VGICP_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Rebuild the tile table for `tp` points per tile (factors keep their tile
+// order), growing the device tables when needed.  Captured graphs refer to the
+// old table and grid, so they are dropped.  Synchronizes ctx's stream.
+int set_tiles(vgicp_ctx ctx, vgicp_factorset fs, int32_t tp, const char *who) {
+  std::vector<Tile> tiles;
+  for (int64_t f : fs->tile_order) {
+    FactorDesc &d = fs->h_factors[size_t(f)];
+    d.tile_begin = int32_t(tiles.size());
+    for (int64_t s = 0; s < d.n; s += tp) tiles.push_back(Tile{int32_t(f), int32_t(s)});
+    d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  for (auto &g : fs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  fs->graphs.clear();
+  const int64_t nt = int64_t(tiles.size());
+  if (e == hipSuccess && nt > fs->tiles_capacity) {
+    (void)hipFree(fs->d_tiles);
+    (void)hipFree(fs->d_partials);
+    fs->d_tiles = nullptr;
+    fs->d_partials = nullptr;
+    fs->tiles_capacity = 0;
+    e = hipMalloc(&fs->d_tiles, size_t(nt) * sizeof(Tile));
+    if (e == hipSuccess)
+      e = hipMalloc(&fs->d_partials, size_t(nt) * kPartialStride * sizeof(double));
+    if (e == hipSuccess) fs->tiles_capacity = nt;
+  }
+  if (e == hipSuccess && fs->n_factors > 0)
+    e = hipMemcpyAsync(fs->d_factors, fs->h_factors.data(),
+                       fs->h_factors.size() * sizeof(FactorDesc), hipMemcpyHostToDevice,
+                       ctx->stream);
+  if (e == hipSuccess && nt > 0)
+    e = hipMemcpyAsync(fs->d_tiles, tiles.data(), size_t(nt) * sizeof(Tile),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  fs->n_tiles = nt;
+  fs->tile_points = tp;
+  return VGICP_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
                          int64_t *total_points, int32_t *tile_points) {
@@ -656,6 +709,85 @@ int vgicp_assemble_system(vgicp_ctx ctx, vgicp_factorset fs, const double *H, co
   if (rc) return rc;
   hipError_t e = launch_assemble(fs, H, b, Hdiag, bvec, Hoff, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, who, e);
+  return VGICP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                         const vgicp_opts *opts, double *H, double *b, double *e,
+                         int64_t *inliers, const int32_t *candidates, int32_t n_candidates,
+                         int32_t *best_tile, double *best_ms) {
+  const char *who = "vgicp_factorset_tune";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  vgicp_opts o;
+  rc = read_opts(ctx, opts, &o, who);
+  if (rc) return rc;
+  if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": an output pointer is NULL");
+  static const int32_t kDefaultCandidates[] = {6 * kTileQuantum, 4 * kTileQuantum,
+                                               3 * kTileQuantum, 2 * kTileQuantum,
+                                               kTileQuantum};
+  if (!candidates) {
+    candidates = kDefaultCandidates;
+    n_candidates = int32_t(sizeof(kDefaultCandidates) / sizeof(kDefaultCandidates[0]));
+  }
+  if (n_candidates < 1)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": no candidate tile sizes");
+  for (int32_t k = 0; k < n_candidates; ++k)
+    if (candidates[k] < 256 || candidates[k] > (1 << 20) || candidates[k] % 256 != 0)
+      return fail(ctx, VGICP_EINVAL,
+                  std::string(who) + ": tile sizes must be multiples of 256 in [256, 2^20]");
+  o.schedule = VGICP_SCHED_BATCHED;
+  o.use_graph = 0;
+  // The first rounds after idle run at lower clocks: warm up first, then time
+  // every candidate twice (forward and reverse order) and keep its best.
+  for (int r = 0; r < 10 && rc == VGICP_OK; ++r)
+    rc = run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, nullptr, who);
+  if (rc != VGICP_OK) return rc;
+  const int kWarm = 2, kTimed = 5;
+  std::vector<double> cand_ms(size_t(n_candidates), 1e300);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t he = hipEventCreate(&t0);
+  if (he == hipSuccess) he = hipEventCreate(&t1);
+  if (he != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(ctx, who, he);
+  }
+  for (int32_t step = 0; step < 2 * n_candidates && rc == VGICP_OK; ++step) {
+    const int32_t k = step < n_candidates ? step : 2 * n_candidates - 1 - step;
+    rc = set_tiles(ctx, fs, candidates[k], who);
+    for (int r = 0; r < kWarm + kTimed && rc == VGICP_OK; ++r) {
+      if (r == kWarm && (he = hipEventRecord(t0, ctx->stream)) != hipSuccess)
+        rc = hip_fail(ctx, who, he);
+      if (rc == VGICP_OK)
+        rc = run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, nullptr, who);
+    }
+    float ms = 0.f;
+    if (rc == VGICP_OK && (he = hipEventRecord(t1, ctx->stream)) != hipSuccess)
+      rc = hip_fail(ctx, who, he);
+    if (rc == VGICP_OK && (he = hipEventSynchronize(t1)) != hipSuccess) rc = hip_fail(ctx, who, he);
+    if (rc == VGICP_OK && (he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+      rc = hip_fail(ctx, who, he);
+    if (rc == VGICP_OK) cand_ms[size_t(k)] = std::min(cand_ms[size_t(k)], double(ms) / kTimed);
+  }
+  int32_t best = candidates[0];
+  double best_t = cand_ms[0];
+  for (int32_t k = 1; k < n_candidates; ++k)
+    if (cand_ms[size_t(k)] < best_t) {
+      best = candidates[k];
+      best_t = cand_ms[size_t(k)];
+    }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc != VGICP_OK) return rc;
+  rc = set_tiles(ctx, fs, best, who);
+  if (rc != VGICP_OK) return rc;
+  if (best_tile) *best_tile = best;
+  if (best_ms) *best_ms = best_t;
   return VGICP_OK;
 }
 

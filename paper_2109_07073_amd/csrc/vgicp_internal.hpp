@@ -189,6 +189,8 @@ struct vgicp_factorset_s {
   vgicp::Tile *d_tiles = nullptr;          // device
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
   std::vector<vgicp::FactorDesc> h_factors;
+  std::vector<int64_t> tile_order;  // factors in tile order (grouped by target map)
+  int64_t tiles_capacity = 0;       // tiles d_tiles and d_partials have room for
   std::vector<GraphEntry> graphs;
   // System assembly: contributions to each pose (CSR over poses, entries are
   // factor * 4 + side (0 = as pose i, 1 = as pose j) + 2 for a factor whose

@@ -79,6 +79,8 @@ _PROTOS = {
     "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)]),
     "vgicp_factorset_destroy": (ctypes.c_int, [_vp]),
     "vgicp_factorset_pairs": (ctypes.c_int, [_vp, _P(_i64), _vp]),
+    "vgicp_factorset_tune": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp,
+                                            _i32, _P(_i32), _P(_dbl)]),
     "vgicp_assemble_system": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vgicp_validate_factors": (ctypes.c_int, [_i32, _i32, _i32, _P(CFactor), _i64]),
     "vgicp_linearize_factors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp]),
@@ -444,6 +446,35 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
     _check(_lib.vgicp_overlap(ctx.handle, fs.handle, poses.data_ptr(), out["hits"].data_ptr(),
                               out["overlap"].data_ptr()), ctx.handle)
     return out
+
+
+def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str = "f32",
+               resid: str = "f64", fp64_kappa: float = 0.0):
+    """Time a linearization round per candidate tile size and keep the fastest
+    (vgicp_factorset_tune).  Returns (tile_points, ms per round)."""
+    torch = _torch()
+    _check_poses(fs, poses)
+    dev = f"cuda:{ctx.device}"
+    F = fs.n_factors
+    H = torch.empty((max(F, 1), 12, 12), dtype=torch.float64, device=dev)
+    b = torch.empty((max(F, 1), 12), dtype=torch.float64, device=dev)
+    e = torch.empty((max(F, 1),), dtype=torch.float64, device=dev)
+    inl = torch.empty((max(F, 1),), dtype=torch.int64, device=dev)
+    o = _opts(accum, "batched", False, resid, fp64_kappa)
+    cand = None
+    n = 0
+    if candidates is not None:
+        c = np.ascontiguousarray(np.asarray(candidates, dtype=np.int32).reshape(-1))
+        cand, n = c.ctypes.data_as(ctypes.c_void_p), c.size
+    best, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.vgicp_factorset_tune(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
+                                     H.data_ptr(), b.data_ptr(), e.data_ptr(), inl.data_ptr(),
+                                     cand, n, ctypes.byref(best), ctypes.byref(ms)), ctx.handle)
+    a, nt, c3, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.vgicp_factorset_info(fs.handle, ctypes.byref(a), ctypes.byref(nt),
+                                     ctypes.byref(c3), ctypes.byref(d)))
+    fs.n_tiles, fs.tile_points = nt.value, d.value
+    return best.value, ms.value
 
 
 def assemble_system(ctx: Context, fs: FactorSet, H, b, out=None, with_offdiag: bool = True):

@@ -24,4 +24,5 @@ def test_profiled_traffic_follows_the_sources():
     import bench
     t = bench.profiled_traffic("batched4500")
     assert t is None or t > 3.0e9
+    assert bench.profiled_traffic("batched4500", 1536) is None
     assert bench.profiled_traffic("no_such_workload") is None

@@ -315,6 +315,32 @@ def test_automatic_tile_size(vg, ctx, cfg1, ragged):
             assert rel_fro(b["H"][f].cpu().numpy(), a["H"][f]) < TOL
 
 
+def test_tile_autotuning_keeps_parity(vg, ctx, scans, ragged):
+    """Tuning picks one of the candidates, rebuilds the tiles, drops captured
+    graphs, and the factors still match the oracle (and the graph replay the
+    direct launch) afterwards."""
+    import torch
+    _, ref = oracle_results(ragged, with_corr=False)
+    g = GpuWorkload(vg, ctx, ragged)
+    stream = torch.cuda.Stream()
+    sctx = vg.Context(0, stream=stream)
+    fs = vg.FactorSet(sctx, g.src, g.maps, ragged.factors, ragged.poses.shape[0])
+    with torch.cuda.stream(stream):
+        poses = g.poses.clone()
+        before = vg.linearize_factors(sctx, fs, poses, use_graph=True)
+        best, ms = vg.tune_tiles(sctx, fs, poses, candidates=[1536, 768, 2304])
+        assert best in (1536, 768, 2304) and fs.tile_points == best and ms > 0
+        direct = vg.linearize_factors(sctx, fs, poses)
+        graph = vg.linearize_factors(sctx, fs, poses, use_graph=True, out=before)
+    stream.synchronize()
+    got = {k: v.cpu().numpy() for k, v in direct.items()}
+    assert_linearize_parity(got, ref)
+    for k in ("H", "b", "e", "inliers"):
+        assert torch.equal(graph[k], direct[k]), k
+    with pytest.raises(vg.VgicpError):
+        vg.tune_tiles(sctx, fs, poses, candidates=[100])
+
+
 def test_empty_factor_set_is_a_no_op(vg, ctx, cfg1):
     import torch
     g = GpuWorkload(vg, ctx, cfg1)
