@@ -241,7 +241,10 @@ int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
  * skip).  A factor with no inlier returns H = 0, b = 0, e = 0.
  * opts may be NULL (FP32 accumulation, batched schedule, no graph, FP64 residual).  Results
  * are deterministic and do not depend on the schedule or on the other factors
- * of the set.  Errors: EINVAL, EHIP. */
+ * of the set.  Device inputs are not scanned: a source point whose transform
+ * is not finite or falls outside the key range is a miss, and a hit whose
+ * fused covariance is not positive definite (including non-finite) adds
+ * nothing but counts as an inlier.  Errors: EINVAL, EHIP. */
 int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                             const vgicp_opts *opts, double *H, double *b, double *e,
                             int64_t *inliers, int32_t *corr);

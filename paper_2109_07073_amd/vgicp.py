@@ -146,12 +146,23 @@ def validate_factors(n_sources: int, n_maps: int, n_poses: int, factors) -> None
     _check(_lib.vgicp_validate_factors(n_sources, n_maps, n_poses, arr, n))
 
 
+class _FactorRows:
+    """(n, 4) int32 rows viewed as a vgicp_factor array (same layout: four
+    int32 fields); keeps the buffer alive while the pointer is in use."""
+
+    def __init__(self, factors):
+        f = np.asarray(factors, dtype=np.int32).reshape(-1, 4)
+        self.rows = np.ascontiguousarray(f if f.shape[0] else np.zeros((1, 4), np.int32))
+        self.n = int(f.shape[0])
+        self._as_parameter_ = self.rows.ctypes.data_as(ctypes.POINTER(CFactor))
+
+
+assert ctypes.sizeof(CFactor) == 16
+
+
 def _factor_array(factors):
-    f = np.ascontiguousarray(np.asarray(factors, dtype=np.int32).reshape(-1, 4))
-    arr = (CFactor * max(1, f.shape[0]))()
-    for k, row in enumerate(f):
-        arr[k] = CFactor(*[int(v) for v in row])
-    return arr, int(f.shape[0])
+    rows = _FactorRows(factors)
+    return rows, rows.n
 
 
 # ---------------------------------------------------------------- torch glue

@@ -299,6 +299,30 @@ def test_transforms_beyond_the_key_range_miss(vg, ctx, cfg1):
     assert np.array_equal(ov["hits"], ref["inliers"])
 
 
+def test_non_finite_source_points_miss(vg, ctx, cfg1):
+    """Source points with NaN or infinite coordinates are misses (corr -1,
+    nothing added), like finite points carried far outside the key range:
+    the oracle gets such far points in their place."""
+    xyz, cov = cfg1.sources[0]
+    bad = np.arange(0, xyz.shape[0], 17)
+    vals = np.array([np.nan, np.inf, -np.inf], np.float32)
+    xyz_bad = xyz.copy()
+    for j, i in enumerate(bad):
+        xyz_bad[i, j % 3] = vals[j % 3]
+    xyz_far = xyz.copy()
+    xyz_far[bad] = np.float32(1.0e7)
+    w_bad = Workload(name="nan", resolution=cfg1.resolution, sources=[(xyz_bad, cov)],
+                     targets=cfg1.targets, poses=cfg1.poses, factors=cfg1.factors, meta={})
+    w_far = Workload(name="far", resolution=cfg1.resolution, sources=[(xyz_far, cov)],
+                     targets=cfg1.targets, poses=cfg1.poses, factors=cfg1.factors, meta={})
+    _, ref = oracle_results(w_far, with_corr=True)
+    got = GpuWorkload(vg, ctx, w_bad).linearize(with_corr=True)
+    assert np.all(got["corr"][bad] == -1)
+    assert np.array_equal(got["corr"], ref["corr"][0])
+    assert_linearize_parity(got, ref)
+    assert np.all(np.isfinite(got["H"])) and np.all(np.isfinite(got["b"]))
+
+
 def test_automatic_tile_size(vg, ctx, cfg1, ragged):
     """Small factor sets get the smallest whole-phase tile (768 points); an
     explicit tile is kept; results do not depend on it beyond rounding."""
