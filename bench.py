@@ -124,12 +124,13 @@ def _oracle_worker(args):
     return outs, time.perf_counter() - t0
 
 
-def cpu_baseline(w, budget_s: float = 12.0, workers: int = 1):
+def cpu_baseline(w, cpu_seconds: float = 24.0, workers: int = 1):
     """The FP64 oracle on a bounded sample of the workload's factors, over
     `workers` forked processes of one thread each (factors dealt round-robin
-    from a seeded permutation; each process stops after `budget_s`).  Must run
-    before the process touches the GPU.  Returns (corr/s, processes, sample
-    text, factor ids, outputs)."""
+    from a seeded permutation; each process stops once it has used its share
+    of `cpu_seconds`).  Must run before the process touches the GPU.  Returns
+    (corr/s, processes, sample text, factor ids, outputs)."""
+    budget_s = cpu_seconds / max(1, workers)
     import multiprocessing as mp
     global _CPU_W
     _CPU_W = w
@@ -151,7 +152,7 @@ def cpu_baseline(w, budget_s: float = 12.0, workers: int = 1):
             pts += n
     sample = (f"{len(ids)} of {w.n_factors} factors ({pts} source points, {inl} correspondences) "
               f"linearized by the FP64 numpy oracle, voxel maps included, {workers} processes "
-              f"of 1 thread, {wall:.1f} s wall")
+              f"of 1 thread, {wall:.1f} s wall, about {cpu_seconds:.0f} s of CPU work")
     return inl / wall, workers, sample, ids, outs
 
 
