@@ -22,10 +22,12 @@
  *     ctx for failures that had no valid context).  On failure no output is
  *     specified and no handle is created.
  *   - Arguments are validated on the host before anything is enqueued.
- *   - Clouds are frame-local.  A cloud of n points is two SoA arrays:
- *       xyz: float32 [3][n]  (x[0..n), then y[0..n), then z[0..n))
- *       cov: float32 [6][n]  (planes xx, xy, xz, yy, yz, zz of the symmetric
- *                              3x3 point covariance)
+ *   - Clouds are frame-local.  A cloud of n points is two arrays:
+ *       xyz: float32 [3][n]  (x[0..n), then y[0..n), then z[0..n)): every
+ *                              lookup streams all of it
+ *       cov: float32 [n][6]  (per point xx, xy, xz, yy, yz, zz of the
+ *                              symmetric 3x3 covariance; 8-byte aligned): only
+ *                              points that fall in a voxel read theirs
  *     The caller owns them and keeps them alive while any factor set that
  *     references them is used.
  *   - A pose is 12 float64 values: R (3x3, row-major) then t; it maps sensor
@@ -83,7 +85,7 @@ typedef struct vgicp_factorset_s *vgicp_factorset;
 
 typedef struct {
   const float *xyz; /* device, [3][n] */
-  const float *cov; /* device, [6][n] */
+  const float *cov; /* device, [n][6], 8-byte aligned */
   int64_t n;        /* number of points, >= 0 */
 } vgicp_cloud;
 
@@ -332,7 +334,7 @@ int vgicp_server_destroy(vgicp_server srv);
 /* Message of the last failure on srv. */
 const char *vgicp_server_last_error(vgicp_server srv);
 
-/* Register a keyframe: host SoA arrays h_xyz [3][n] and h_cov [6][n] are copied
+/* Register a keyframe: host arrays h_xyz [3][n] and h_cov [n][6] are copied
  * to server-owned device memory and voxelized at `resolution`.  Returns its id.
  * Errors: EINVAL, ENONFINITE, ERANGE, EFULL (the frame would exceed the memory
  * budget; nothing is kept), ENOMEM, EHIP. */

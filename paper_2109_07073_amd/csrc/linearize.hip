@@ -64,6 +64,8 @@ __device__ __forceinline__ void lookup_transform(const float R[9], const float t
 // Global-address-space views: loads through them compile to global_load_*
 // (flat loads would also tie up the LDS counter).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef const f32x2 __attribute__((address_space(1))) gfloat2;
 typedef const float __attribute__((address_space(1))) gfloat;
 typedef const f32x4 __attribute__((address_space(1))) gfloat4;
 
@@ -552,9 +554,14 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   const int32_t idx = Q.idx[e];
   const int32_t pidx = Q.pidx[e];
   B.idx = live ? idx : 0;
-  gfloat *gc = (gfloat *)pc;
+  // the point's covariance: 24 contiguous bytes, three 8-byte loads
+  gfloat2 *gc = (gfloat2 *)pc + 3 * int64_t(B.idx);
 #pragma unroll
-  for (int a = 0; a < 6; ++a) B.c[a] = __builtin_nontemporal_load(gc + a * n + B.idx);
+  for (int a = 0; a < 3; ++a) {
+    const f32x2 v = __builtin_nontemporal_load(gc + a);
+    B.c[2 * a] = v.x;
+    B.c[2 * a + 1] = v.y;
+  }
   const Payload *pl = payload + (live ? pidx : 0);
   gfloat4 *gp = (gfloat4 *)pl;
   B.w0 = gp[0];

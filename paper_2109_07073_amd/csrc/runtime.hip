@@ -207,6 +207,8 @@ int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, v
     return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: more than 2^31-1 points");
   if (cloud->n > 0 && (!cloud->xyz || !cloud->cov))
     return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: NULL point arrays with n > 0");
+  if (cloud->n > 0 && (reinterpret_cast<uintptr_t>(cloud->cov) & 7u))
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: cov is not 8-byte aligned");
   if (!std::isfinite(resolution) || !(resolution > 0.0))
     return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: resolution must be finite and > 0");
   const float s = float(1.0 / resolution);
@@ -295,7 +297,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
                 "vgicp_factorset_create: tile_points must be a multiple of 256 in [256, 2^20]");
   for (int32_t s = 0; s < n_sources; ++s) {
     const vgicp_cloud &c = sources[s];
-    if (c.n < 0 || c.n > INT32_MAX || (c.n > 0 && (!c.xyz || !c.cov)))
+    if (c.n < 0 || c.n > INT32_MAX || (c.n > 0 && (!c.xyz || !c.cov)) ||
+        (c.n > 0 && (reinterpret_cast<uintptr_t>(c.cov) & 7u)))
       return fail(ctx, VGICP_EINVAL,
                   "vgicp_factorset_create: source " + std::to_string(s) + " is invalid");
   }

@@ -45,7 +45,8 @@ namespace {
 
 struct Frame {
   bool live = false;
-  float *cloud = nullptr;  // device: xyz [3][n] then cov [6][n]
+  float *cloud = nullptr;  // device: xyz [3][n], then cov [n][6] at cov_offset floats
+  int64_t cov_offset = 0;  // 3n rounded up to a multiple of 4 floats (16 bytes)
   int64_t n = 0;
   vgicp_map map = nullptr;
   int64_t bytes = 0;
@@ -241,7 +242,7 @@ void launch_batch(vgicp_server srv, size_t si) {
       const Frame &src = srv->frames[size_t(x.src)];
       const Frame &tgt = srv->frames[size_t(x.tgt)];
       d.xyz = src.cloud;
-      d.cov = src.cloud + 3 * src.n;
+      d.cov = src.cloud + src.cov_offset;
       d.bricks = tgt.map->bricks;
       d.payload = tgt.map->payload;
       d.n = src.n;
@@ -537,18 +538,21 @@ int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_
     return srv_fail(srv, VGICP_EHIP, "vgicp_server_add_frame: hipSetDevice");
   Frame fr;
   fr.n = n;
-  const size_t cloud_bytes = size_t(9) * size_t(std::max<int64_t>(n, 1)) * sizeof(float);
+  fr.cov_offset = (3 * n + 3) & ~int64_t(3);
+  const size_t cloud_bytes =
+      size_t(std::max<int64_t>(fr.cov_offset + 6 * n, 1)) * sizeof(float);
   hipError_t e = hipMalloc(&fr.cloud, cloud_bytes);
   if (e == hipSuccess && n > 0)
     e = hipMemcpy(fr.cloud, h_xyz, size_t(3 * n) * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess && n > 0)
-    e = hipMemcpy(fr.cloud + 3 * n, h_cov, size_t(6 * n) * sizeof(float), hipMemcpyHostToDevice);
+    e = hipMemcpy(fr.cloud + fr.cov_offset, h_cov, size_t(6 * n) * sizeof(float),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (fr.cloud) (void)hipFree(fr.cloud);
     return srv_fail(srv, e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP,
                     std::string("vgicp_server_add_frame: ") + hipGetErrorString(e));
   }
-  vgicp_cloud c{fr.cloud, fr.cloud + 3 * n, n};
+  vgicp_cloud c{fr.cloud, fr.cloud + fr.cov_offset, n};
   std::string msg;
   int rc;
   {

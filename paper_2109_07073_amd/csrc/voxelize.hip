@@ -144,7 +144,7 @@ k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, in
 #pragma unroll
     for (int a = 0; a < 3; ++a) sm[a] += double(xyz[a * n + p]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) sc[a] += double(cov[a * n + p]);
+    for (int a = 0; a < 6; ++a) sc[a] += double(cov[6 * int64_t(p) + a]);
   }
   const double cnt = double(e - b);
   Payload pl;

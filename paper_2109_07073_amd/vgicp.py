@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of voxelization, linearization, cost
 evaluation and overlap runs in the library's HIP kernels.  Device memory and
-streams come from PyTorch-ROCm tensors; clouds are passed as SoA tensors
-xyz float32 (3, n) and cov float32 (6, n) on the GPU.
+streams come from PyTorch-ROCm tensors; clouds are passed as tensors
+xyz float32 (3, n) (coordinate planes) and cov float32 (n, 6) (per point
+xx, xy, xz, yy, yz, zz) on the GPU.
 
 The library must be built (python -m paper_2109_07073_amd.build); importing
 this module without it raises ImportError.  There is no CPU fallback.
@@ -193,28 +194,34 @@ def _dev_tensor(t, dtype, shape=None, name="tensor"):
 
 
 def cloud_to_device(xyz, cov, device="cuda"):
-    """(n,3)/(n,6) float32 host arrays -> SoA device tensors (3,n), (6,n)."""
+    """(n,3)/(n,6) float32 host arrays -> device tensors xyz (3,n), cov (n,6)."""
     torch = _torch()
     x = torch.from_numpy(np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(-1, 3).T))
-    c = torch.from_numpy(np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6).T))
+    c = torch.from_numpy(np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6)))
     return x.to(device).contiguous(), c.to(device).contiguous()
+
+
+def _pad16(k: int) -> int:
+    return (k + 15) & ~15
 
 
 def clouds_to_device(clouds, device="cuda"):
     """Upload many (xyz (n,3), cov (n,6)) host clouds into one device buffer and
-    return SoA views (3,n)/(6,n) per cloud, plus the buffer."""
+    return views xyz (3,n) / cov (n,6) per cloud (each array starts on a
+    64-byte boundary), plus the buffer."""
     torch = _torch()
     sizes = [int(np.asarray(x).reshape(-1, 3).shape[0]) for x, _ in clouds]
-    total = int(sum(sizes))
-    host = np.empty(9 * total, dtype=np.float32)
+    total = int(sum(_pad16(3 * n) + _pad16(6 * n) for n in sizes))
+    host = np.zeros(max(total, 1), dtype=np.float32)
     views, off = [], 0
     for (x, c), n in zip(clouds, sizes):
+        oc = off + _pad16(3 * n)
         host[off:off + 3 * n] = np.asarray(x, np.float32).reshape(-1, 3).T.reshape(-1)
-        host[off + 3 * n:off + 9 * n] = np.asarray(c, np.float32).reshape(-1, 6).T.reshape(-1)
-        views.append((off, n))
-        off += 9 * n
+        host[oc:oc + 6 * n] = np.asarray(c, np.float32).reshape(-1)
+        views.append((off, oc, n))
+        off = oc + _pad16(6 * n)
     buf = torch.from_numpy(host).to(device)
-    out = [(buf[o:o + 3 * n].view(3, n), buf[o + 3 * n:o + 9 * n].view(6, n)) for o, n in views]
+    out = [(buf[o:o + 3 * n].view(3, n), buf[oc:oc + 6 * n].view(n, 6)) for o, oc, n in views]
     return out, buf
 
 
@@ -306,11 +313,11 @@ class VoxelMap:
 
 
 def voxelize(ctx: Context, xyz, cov, resolution: float) -> VoxelMap:
-    """Voxel map of a device cloud (xyz (3,n), cov (6,n) float32 tensors)."""
+    """Voxel map of a device cloud (xyz (3,n), cov (n,6) float32 tensors)."""
     torch = _torch()
     n = int(xyz.shape[1]) if xyz.dim() == 2 else -1
     _dev_tensor(xyz, torch.float32, (3, n), "xyz")
-    _dev_tensor(cov, torch.float32, (6, n), "cov")
+    _dev_tensor(cov, torch.float32, (n, 6), "cov")
     c = CCloud(xyz.data_ptr() if n else None, cov.data_ptr() if n else None, n)
     h = ctypes.c_void_p()
     _check(_lib.vgicp_voxelize(ctx.handle, ctypes.byref(c), float(resolution), ctypes.byref(h)),
@@ -321,7 +328,7 @@ def voxelize(ctx: Context, xyz, cov, resolution: float) -> VoxelMap:
 class FactorSet:
     """Factor list bound to its source clouds and target maps.
 
-    sources: list of (xyz (3,n), cov (6,n)) device tensors (kept alive here);
+    sources: list of (xyz (3,n), cov (n,6)) device tensors (kept alive here);
     maps: list of VoxelMap; factors: (F, 4) rows (src, tgt, pose_i, pose_j)."""
 
     def __init__(self, ctx: Context, sources, maps, factors, n_poses: int, tile_points: int = 0):
@@ -333,7 +340,7 @@ class FactorSet:
         for k, (x, c) in enumerate(self._sources):
             n = int(x.shape[1])
             _dev_tensor(x, torch.float32, (3, n), f"sources[{k}].xyz")
-            _dev_tensor(c, torch.float32, (6, n), f"sources[{k}].cov")
+            _dev_tensor(c, torch.float32, (n, 6), f"sources[{k}].cov")
             cl[k] = CCloud(x.data_ptr() if n else None, c.data_ptr() if n else None, n)
         mp = (ctypes.c_void_p * max(1, len(self._maps)))()
         for k, m in enumerate(self._maps):
@@ -579,7 +586,7 @@ class Server:
 
     def add_frame(self, xyz, cov, resolution: float) -> int:
         x = np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(-1, 3).T)
-        c = np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6).T)
+        c = np.ascontiguousarray(np.asarray(cov, np.float32).reshape(-1, 6))
         fid = ctypes.c_int32()
         _check_srv(_lib.vgicp_server_add_frame(self._h, x.ctypes.data, c.ctypes.data, x.shape[1],
                                                float(resolution), ctypes.byref(fid)), self)

@@ -103,7 +103,7 @@ def test_voxelize_scan_frames_bitexact(vg, ctx, scans):
 def test_voxelize_empty_and_single_point(vg, ctx):
     import torch
     z3 = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
-    z6 = torch.zeros((6, 0), dtype=torch.float32, device="cuda")
+    z6 = torch.zeros((0, 6), dtype=torch.float32, device="cuda")
     m = vg.voxelize(ctx, z3, z6, 0.5)
     assert m.n_voxels == 0
     xyz = np.array([[0.25, -0.75, 3.5]], np.float32)
@@ -129,6 +129,18 @@ def test_voxelize_rejects_nonfinite_and_out_of_range(vg, ctx):
     assert ex.value.code == vg.ERANGE
     with pytest.raises(vg.VgicpError) as ex:
         vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.0)
+    assert ex.value.code == vg.EINVAL
+    # covariances must be 8-byte aligned (they are read 8 bytes at a time)
+    import torch
+    dx, dc = vg.cloud_to_device(xyz, cov)
+    buf = torch.zeros(6 * 300 + 1, dtype=torch.float32, device="cuda")
+    shifted = buf[1:].view(300, 6)
+    shifted.copy_(dc)
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.voxelize(ctx, dx, shifted, 0.5)
+    assert ex.value.code == vg.EINVAL
+    with pytest.raises(vg.VgicpError) as ex:
+        vg.FactorSet(ctx, [(dx, shifted)], [vg.voxelize(ctx, dx, dc, 0.5)], [(0, 0, 0, 0)], 1)
     assert ex.value.code == vg.EINVAL
     # the context stays usable
     m = vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.5)
