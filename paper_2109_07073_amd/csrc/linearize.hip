@@ -97,9 +97,11 @@ __device__ __forceinline__ VoxelKey voxel_key(const float q[3], float s, uint32_
   const int32_t kx = r.ok ? int32_t(floorf(vx)) : 0;
   const int32_t ky = r.ok ? int32_t(floorf(vy)) : 0;
   const int32_t kz = r.ok ? int32_t(floorf(vz)) : 0;
-  r.key = pack_brick(kx, ky, kz);
+  const uint32_t fx = uint32_t((kx >> 2) + kBrickBias), fy = uint32_t((ky >> 2) + kBrickBias);
+  const uint32_t fz = uint32_t((kz >> 2) + kBrickBias);
+  r.key = (uint64_t(fx) << (2 * kBrickBits)) | (uint64_t(fy) << kBrickBits) | uint64_t(fz);
   r.bit = brick_bit(kx, ky, kz);
-  r.h = hash_slot(r.key, log2cap);
+  r.h = brick_slot(fx, fy, fz, log2cap);
   return r;
 }
 

@@ -113,7 +113,7 @@ k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ 
   for (uint32_t d = d0; d < d1; ++d) mask |= 1ull << (bsort[d] & 63u);
   const uint64_t key = bsort[d0] >> 6;
   const uint32_t cmask = (1u << log2cap) - 1u;
-  uint32_t h = hash_slot(key, log2cap);
+  uint32_t h = brick_slot_of_key(key, log2cap);
   for (uint32_t probe = 0; probe <= cmask; ++probe) {
     const unsigned long long prev =
         atomicCAS(reinterpret_cast<unsigned long long *>(&bricks[h].key),
