@@ -68,7 +68,8 @@ extern "C" {
 #define VGICP_ACC_F64 2      /* FP64 from the first per-point term                  */
 
 /* Residual e_k = mu'_k - T mu_k of the per-point terms.  The correspondence
- * decision always uses the FP32 transform; these modes only change how the
+ * decision always uses the FP32 lookup coordinates (fused multiply-adds with the
+ * rotation and translation scaled by fl32(1/r)); these modes only change how the
  * residual itself is evaluated. */
 #define VGICP_RESID_F64 0 /* T mu_k and the difference in FP64 from the FP32 point and voxel
                              mean and the FP64 relative pose, then rounded to FP32: accurate
@@ -86,7 +87,7 @@ typedef struct vgicp_factorset_s *vgicp_factorset;
 typedef struct {
   const float *xyz; /* device, [3][n] */
   const float *cov; /* device, [n][6], 8-byte aligned */
-  int64_t n;        /* number of points, >= 0 */
+  int64_t n;        /* number of points, 0 <= n <= 2^26 */
 } vgicp_cloud;
 
 /* One matching-cost factor (Eq. (1)): indices into the source-cloud list, the
@@ -160,8 +161,9 @@ int vgicp_ctx_destroy(vgicp_ctx ctx);
  * metres.  Synchronizes the stream once.  The map is library-owned device
  * memory; free it with vgicp_map_free.  The cloud is not referenced after the
  * call returns.
- * Errors: EINVAL (NULL pointers with n > 0, n < 0, resolution not finite or
- * <= 0), ENONFINITE, ERANGE, ENOMEM, EHIP. */
+ * Errors: EINVAL (NULL pointers with n > 0, n outside [0, 2^26], resolution
+ * not finite or <= 0, more than 2^24 occupied 4 x 4 x 4 bricks), ENONFINITE,
+ * ERANGE, ENOMEM, EHIP. */
 int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out);
 
 /* Map facts: number of voxels, capacity of its brick table (records; voxels
@@ -196,7 +198,7 @@ int vgicp_map_free(vgicp_map map);
  * Outputs of later calls are indexed in the order of `factors`.  Per-point
  * outputs (corr) are laid out factor after factor, n_src points each.
  * Errors: EINVAL (any index out of range, NULL pointers with nonzero counts,
- * bad tile_points), ENOMEM, EHIP. */
+ * bad tile_points, a source of more than 2^26 points), ENOMEM, EHIP. */
 int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_sources,
                            const vgicp_map *maps, int32_t n_maps, const vgicp_factor *factors,
                            int64_t n_factors, int32_t n_poses, int32_t tile_points,
@@ -336,7 +338,8 @@ const char *vgicp_server_last_error(vgicp_server srv);
 
 /* Register a keyframe: host arrays h_xyz [3][n] and h_cov [n][6] are copied
  * to server-owned device memory and voxelized at `resolution`.  Returns its id.
- * Errors: EINVAL, ENONFINITE, ERANGE, EFULL (the frame would exceed the memory
+ * Errors: EINVAL (n outside [0, 2^26], NULL arrays, bad resolution), ENONFINITE,
+ * ERANGE, EFULL (the frame would exceed the memory
  * budget; nothing is kept), ENOMEM, EHIP. */
 int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_cov, int64_t n,
                            double resolution, int32_t *frame_id);

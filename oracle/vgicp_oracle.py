@@ -12,6 +12,7 @@ GPU-accelerated GICP Matching Cost Factors", IEEE RA-L 2021.
                     aggregated point covariances per voxel)
   relative_pose     Sec. III-A, Eq. (3): relative pose between the pair
   lookup            Sec. III-A, Eq. (3): corresponding voxel of each point
+  fma32             exact FP32 fused multiply-add (rounding to odd)
   linearize_factor  Sec. III-A, Eqs. (2)-(6): error, Hessian factor, b
   evaluate_factor   Sec. III-A, Eq. (3): the matching cost alone
   overlap_factor    Sec. III-B, Eqs. (7)-(8): voxel overlap rate
@@ -28,9 +29,10 @@ notes):
     keys lie in [-2^20, 2^20); the voxel mean is fl32 of the FP64 mean of
     the points and the voxel covariance fl32 of the FP64 mean of the point
     covariances;
-  * the lookup transform that decides the correspondence is evaluated in
-    FP32 with a fixed operation order (no fused multiply-add) from the
-    FP32-rounded relative pose; the residual and weights are then FP64;
+  * the correspondence of a point is decided in FP32: its coordinates in
+    voxel units are three fused multiply-adds per axis with the rotation and
+    translation scaled by fl32(1/r) and rounded to FP32 (lookup_coords_fp32),
+    and its key is their floor; the residual and weights are then FP64;
   * only the single voxel holding the transformed point is used; points in
     no voxel contribute nothing and are not inliers;
   * e is the plain sum of d^T Omega d (no 1/2), b = sum J^T Omega e with
@@ -189,18 +191,48 @@ def relative_pose(pose_i, pose_j) -> tuple[np.ndarray, np.ndarray]:
     return R, t
 
 
-def lookup_transform_fp32(xyz32: np.ndarray, R: np.ndarray, t: np.ndarray) -> np.ndarray:
-    """The FP32 point transform that decides correspondences:
-        q_r = ((R32[r][0] x + R32[r][1] y) + R32[r][2] z) + t32[r]
-    every product and sum rounded to FP32, R32 = fl32(R), t32 = fl32(t)."""
-    R32 = np.asarray(R, dtype=np.float64).astype(np.float32)
-    t32 = np.asarray(t, dtype=np.float64).astype(np.float32)
+def fma32(a, b, c) -> np.ndarray:
+    """FP32 fused multiply-add: a * b + c for float32 operands, rounded once
+    to FP32 (round to nearest, ties to even).
+
+    The product of two float32 values is exact in FP64.  Knuth's two-sum
+    splits the FP64 sum into its rounding s and the exact error err
+    (a * b + c = s + err); s is then rounded to odd (replaced by its neighbour
+    towards err, which has an odd last bit, when err != 0 and s's last bit is
+    even), and one FP64 -> FP32 rounding of that is the correctly rounded
+    result: rounding to odd with at least two spare bits followed by rounding
+    to nearest equals one rounding to nearest (Boldo and Melquiond, "Emulation
+    of FMA and correctly rounded sums: proved algorithms using rounding to
+    odd", IEEE Trans. Computers 57(4), 2008).  Non-finite values pass through."""
+    a64 = np.asarray(a, dtype=np.float32).astype(np.float64)
+    b64 = np.asarray(b, dtype=np.float32).astype(np.float64)
+    c64 = np.asarray(c, dtype=np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore", over="ignore"):
+        p = a64 * b64
+        s = np.asarray(p + c64, dtype=np.float64)
+        bp = s - p
+        err = (p - (s - bp)) + (c64 - bp)
+        even = (s.view(np.int64) & 1) == 0
+        fix = np.isfinite(s) & (err != 0) & even
+        s = np.where(fix, np.nextafter(s, np.where(err > 0, np.inf, -np.inf)), s)
+        return s.astype(np.float32)
+
+
+def lookup_coords_fp32(xyz32: np.ndarray, R: np.ndarray, t: np.ndarray, s) -> np.ndarray:
+    """The FP32 coordinates, in voxel units, that decide correspondences
+    (Sec. III-A, Eq. (3): the voxel holding T_j^-1 T_i mu):
+        v_r = fma(S[r][2], z, fma(S[r][1], y, fma(S[r][0], x, u[r])))
+    with S = fl32(s R) and u = fl32(s t) (FP64 products, one rounding each),
+    every fma rounded once to FP32, and s = fl32(1/r) the map's scale."""
+    S = (np.float64(s) * np.asarray(R, dtype=np.float64)).astype(np.float32)
+    with np.errstate(over="ignore"):
+        u = (np.float64(s) * np.asarray(t, dtype=np.float64)).astype(np.float32)
     p = np.asarray(xyz32, dtype=np.float32).reshape(-1, 3)
     x, y, z = p[:, 0], p[:, 1], p[:, 2]
-    q = np.empty_like(p)
+    v = np.empty_like(p)
     for r in range(3):
-        q[:, r] = ((R32[r, 0] * x + R32[r, 1] * y) + R32[r, 2] * z) + t32[r]
-    return q
+        v[:, r] = fma32(S[r, 2], z, fma32(S[r, 1], y, fma32(S[r, 0], x, u[r])))
+    return v
 
 
 def _packed(keys: np.ndarray) -> np.ndarray:
@@ -211,12 +243,11 @@ def _packed(keys: np.ndarray) -> np.ndarray:
 def lookup(vmap: VoxelMap, xyz32: np.ndarray, R: np.ndarray, t: np.ndarray) -> np.ndarray:
     """Ordinal of the voxel of `vmap` containing each transformed point, or
     -1 when that voxel is empty or its key is outside the key range."""
-    q = lookup_transform_fp32(xyz32, R, t)
-    v = _scaled_fl32(q, vmap.scale)
+    v = lookup_coords_fp32(xyz32, R, t, vmap.scale)
     ok = np.all(np.isfinite(v), axis=1)
     kf = np.floor(np.where(np.isfinite(v), v, 0.0).astype(np.float64))
     ok &= np.all((kf >= -KEY_LIMIT) & (kf < KEY_LIMIT), axis=1)
-    corr = np.full(q.shape[0], -1, dtype=np.int64)
+    corr = np.full(v.shape[0], -1, dtype=np.int64)
     if vmap.n_voxels == 0 or not ok.any():
         return corr
     table = _packed(vmap.keys)                      # sorted because keys are

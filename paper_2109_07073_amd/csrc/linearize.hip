@@ -51,103 +51,158 @@ __device__ __forceinline__ void relative_pose64(const double *__restrict__ pi,
   for (int r = 0; r < 3; ++r) t[r] = (pj[r] * d0 + pj[3 + r] * d1) + pj[6 + r] * d2;
 }
 
-// The FP32 transform that decides correspondences, evaluated without fused
-// multiply-add in a fixed order.
-__device__ __forceinline__ void lookup_transform(const float R[9], const float t[3], float x,
-                                                 float y, float z, float q[3]) {
+// The FP32 coordinates, in voxel units, that decide the correspondence of a
+// point (the voxel holding T_j^-1 T_i mu, Sec. III-A): three fused
+// multiply-adds per axis with the rotation and translation scaled by the
+// map's fl32(1/r), each rounded once to FP32.
+__device__ __forceinline__ void lookup_coords(const float S[9], const float u[3], float x,
+                                              float y, float z, float v[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    v[r] = __builtin_fmaf(S[3 * r + 2], z,
+                          __builtin_fmaf(S[3 * r + 1], y, __builtin_fmaf(S[3 * r], x, u[r])));
+}
+
+// The plain FP32 transform R mu + t (fixed order, no fused multiply-add),
+// used only by the FP32 residual variant.
+__device__ __forceinline__ void transform_fp32(const float R[9], const float t[3], float x,
+                                               float y, float z, float q[3]) {
 #pragma clang fp contract(off)
   q[0] = ((R[0] * x + R[1] * y) + R[2] * z) + t[0];
   q[1] = ((R[3] * x + R[4] * y) + R[5] * z) + t[1];
   q[2] = ((R[6] * x + R[7] * y) + R[8] * z) + t[2];
 }
 
-// Global-address-space views: loads through them compile to global_load_*
-// (flat loads would also tie up the LDS counter).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef const f32x2 __attribute__((address_space(1))) gfloat2;
-typedef const float __attribute__((address_space(1))) gfloat;
-typedef const f32x4 __attribute__((address_space(1))) gfloat4;
+typedef float f32x3 __attribute__((ext_vector_type(3)));
 
-__device__ __forceinline__ void load_xyz(const float *px, int64_t n, int64_t i, float p[3]) {
-  gfloat *g = (gfloat *)px;
-  p[0] = __builtin_nontemporal_load(g + i);
-  p[1] = __builtin_nontemporal_load(g + n + i);
-  p[2] = __builtin_nontemporal_load(g + 2 * n + i);
+// ---------------------------------------------------------------- buffer loads
+// Clouds and maps are read through raw buffer resources: a uniform base in
+// scalar registers plus a 32-bit byte offset per lane (no 64-bit address
+// arithmetic per lane), and a load at or past the resource's size returns
+// zeros, so the coordinate prefetch past a cloud's last point needs no clamp.
+// The size limits of clouds and maps keep every offset below 2^32.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, no swizzle
+constexpr int kNT = 2;                  // nontemporal: streamed once
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, uint64_t bytes) {
+  const uint32_t num = bytes < 0xffffffffull ? uint32_t(bytes) : 0xffffffffu;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, int(num), kRsrcWord3);
 }
 
-typedef const uint32_t __attribute__((address_space(1))) gu32;
-typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-typedef const u64x2 __attribute__((address_space(1))) gu64x2;
+template <int AUX = 0>
+__device__ __forceinline__ float ld_f32(Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, AUX));
+}
+template <int AUX = 0>
+__device__ __forceinline__ f32x3 ld_f32x3(Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(f32x3, __builtin_amdgcn_raw_buffer_load_b96(r, int(off), 0, AUX));
+}
+template <int AUX = 0>
+__device__ __forceinline__ f32x4 ld_f32x4(Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, int(off), 0, AUX));
+}
 
-// Brick key, home record and bit of the voxel holding q (ok = false when a
-// voxel key would fall outside [-2^20, 2^20), which no voxel of any map has).
-struct VoxelKey {
-  bool ok;
-  uint64_t key;  // packed brick key
-  uint32_t h;    // home record
-  uint32_t bit;  // the voxel's bit in the brick's occupancy mask
+// The three coordinate planes of one tile, points [begin, end) of a source
+// cloud of n points: the prefetch past the tile's end reads zeros without
+// touching memory (it would otherwise fetch the next tile's lines).
+struct CloudRsrc {
+  Rsrc x, y, z;
 };
 
-__device__ __forceinline__ VoxelKey voxel_key(const float q[3], float s, uint32_t log2cap) {
-  const float vx = q[0] * s, vy = q[1] * s, vz = q[2] * s;
+__device__ __forceinline__ CloudRsrc tile_rsrc(const float *xyz, uint32_t n, uint32_t begin,
+                                               uint32_t end) {
+  const uint64_t bytes = 4ull * (end - begin);
+  return {make_rsrc(xyz + begin, bytes), make_rsrc(xyz + n + begin, bytes),
+          make_rsrc(xyz + 2ull * n + begin, bytes)};
+}
+
+// Point `i` of the tile (counted from its first point).
+__device__ __forceinline__ void load_xyz(const CloudRsrc &c, uint32_t i, float p[3]) {
+  const uint32_t off = i * 4u;
+  p[0] = ld_f32<kNT>(c.x, off);
+  p[1] = ld_f32<kNT>(c.y, off);
+  p[2] = ld_f32<kNT>(c.z, off);
+}
+
+// Brick key halves, home record and bit of the voxel holding the point with
+// lookup coordinates v.  Each coordinate is clamped to [-2^20 - 4, 2^20] (NaN
+// goes to the low end), so a point outside the key range names a brick that
+// no map holds.
+struct VoxelKey {
+  uint32_t klo, khi;  // packed brick key
+  uint32_t h;         // home record
+  uint32_t bit;       // the voxel's bit in the brick's occupancy mask
+};
+
+__device__ __forceinline__ VoxelKey voxel_key(const float v[3], uint32_t log2cap) {
+  const float vx = fminf(fmaxf(v[0], kClampLoF), kClampHiF);
+  const float vy = fminf(fmaxf(v[1], kClampLoF), kClampHiF);
+  const float vz = fminf(fmaxf(v[2], kClampLoF), kClampHiF);
+  const int32_t kx = int32_t(floorf(vx)), ky = int32_t(floorf(vy)), kz = int32_t(floorf(vz));
+  const uint32_t fx = brick_field(kx), fy = brick_field(ky), fz = brick_field(kz);
   VoxelKey r;
-  r.ok = (vx >= -kKeyLimitF) & (vx < kKeyLimitF) & (vy >= -kKeyLimitF) & (vy < kKeyLimitF) &
-         (vz >= -kKeyLimitF) & (vz < kKeyLimitF);
-  const int32_t kx = r.ok ? int32_t(floorf(vx)) : 0;
-  const int32_t ky = r.ok ? int32_t(floorf(vy)) : 0;
-  const int32_t kz = r.ok ? int32_t(floorf(vz)) : 0;
-  const uint32_t fx = uint32_t((kx >> 2) + kBrickBias), fy = uint32_t((ky >> 2) + kBrickBias);
-  const uint32_t fz = uint32_t((kz >> 2) + kBrickBias);
-  r.key = (uint64_t(fx) << (2 * kBrickBits)) | (uint64_t(fy) << kBrickBits) | uint64_t(fz);
+  r.klo = (fy << kBrickBits) | fz;
+  r.khi = (fx << (2 * kBrickBits - 32)) | (fy >> (32 - kBrickBits));
   r.bit = brick_bit(kx, ky, kz);
   r.h = brick_slot(fx, fy, fz, log2cap);
   return r;
 }
 
-// Issue the loads of a key's home record: key and mask (one 16-byte load)
-// and the payload base.
+// A brick record as loaded: key and mask (one 16-byte load) and the payload
+// base.
 struct RecordLoad {
-  u64x2 km;
+  f32x4 km;
   uint32_t base;
 };
 
-__device__ __forceinline__ RecordLoad load_record(const BrickRecord *bricks, uint32_t h) {
+__device__ __forceinline__ RecordLoad load_record(Rsrc rb, uint32_t h) {
   RecordLoad r;
-  r.km = *(gu64x2 *)(bricks + h);
-  r.base = *(gu32 *)(&bricks[h].base);
+  r.km = ld_f32x4(rb, h << 5);
+  r.base = __builtin_bit_cast(uint32_t, ld_f32(rb, (h << 5) + 16u));
   return r;
+}
+
+__device__ __forceinline__ uint64_t u64_of(float lo, float hi) {
+  return (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32) | __builtin_bit_cast(uint32_t, lo);
 }
 
 // Payload index of the voxel, or -1: the home record's brick, or the records
 // after it up to the first free one (linear probing), must hold the brick,
-// and its mask the voxel's bit.  At most `capacity` records are visited.
-__device__ __forceinline__ int find_voxel(const BrickRecord *bricks, uint32_t log2cap,
-                                          const VoxelKey &vk, const RecordLoad &home) {
-  uint64_t mask = home.km.y;
+// and its mask the voxel's bit.  Probing is rare (a home record of another
+// brick), so it runs behind one wave-uniform branch and the common path has
+// no divergent control flow.  At most `capacity` records are visited.
+__device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const VoxelKey &vk,
+                                          const RecordLoad &home) {
+  const uint64_t key = (uint64_t(vk.khi) << 32) | vk.klo;
+  uint64_t rkey = u64_of(home.km.x, home.km.y);
+  uint64_t mask = u64_of(home.km.z, home.km.w);
   uint32_t base = home.base;
-  if (home.km.x != vk.key) {
-    if (home.km.x == kEmptyKey) return -1;
-    // Rare: keep probing.  The full wait at the end leaves no load of this
-    // path in flight, so the common path's waits stay exact.
-    bool found = false;
-    const uint32_t cm = (1u << log2cap) - 1u;
-    uint32_t h = vk.h;
-    for (uint32_t p = 0; p < cm; ++p) {
-      h = (h + 1u) & cm;
-      const u64x2 km = *(gu64x2 *)(bricks + h);
-      if (km.x == vk.key) {
-        mask = km.y;
-        base = *(gu32 *)(&bricks[h].base);
-        found = true;
-        break;
+  const bool probe = rkey != key && rkey != kEmptyKey;
+  if (__ballot(probe) != 0) {
+    if (probe) {
+      const uint32_t cm = (1u << log2cap) - 1u;
+      uint32_t h = vk.h;
+      for (uint32_t p = 0; p < cm; ++p) {
+        h = (h + 1u) & cm;
+        const RecordLoad r = load_record(rb, h);
+        const uint64_t k2 = u64_of(r.km.x, r.km.y);
+        if (k2 == key) {
+          rkey = key;
+          mask = u64_of(r.km.z, r.km.w);
+          base = r.base;
+          break;
+        }
+        if (k2 == kEmptyKey) break;
       }
-      if (km.x == kEmptyKey) break;
     }
+    // leave no load of this path in flight, so the common path's waits
+    // stay exact
     __builtin_amdgcn_s_waitcnt(0);
-    if (!found) return -1;
   }
-  if (!((mask >> vk.bit) & 1ull)) return -1;
+  if (rkey != key || !((mask >> vk.bit) & 1ull)) return -1;
   return int(base + uint32_t(__popcll(mask & ((1ull << vk.bit) - 1ull))));
 }
 
@@ -320,8 +375,10 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
 
 // ---------------------------------------------------------------- factor constants
 struct FactorConsts {
-  float R[9];     // fl32(R): lookup transform and per-point algebra
-  float t[3];     // fl32(t): lookup transform
+  float S[9];     // fl32(s R): lookup coordinates
+  float u[3];     // fl32(s t): lookup coordinates
+  float R[9];     // fl32(R): per-point algebra and the FP32 residual
+  float t[3];     // fl32(t): FP32 residual
   double R64[9];  // R itself: FP64 residual and FP64 fused covariance
   double t64[3];  // t itself: FP64 residual
 };
@@ -501,14 +558,17 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
                                                       const double *__restrict__ poses) {
   double R[9], t[3];
   relative_pose64(poses + 12 * int64_t(fd.pose_i), poses + 12 * int64_t(fd.pose_j), R, t);
+  const double s = fd.scale;
   FactorConsts k;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
+    k.S[i] = uniform_f(float(s * R[i]));
     k.R[i] = uniform_f(float(R[i]));
     k.R64[i] = uniform_d(R[i]);
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
+    k.u[i] = uniform_f(float(s * t[i]));
     k.t[i] = uniform_f(float(t[i]));
     k.t64[i] = uniform_d(t[i]);
   }
@@ -543,33 +603,29 @@ struct Batch {
   int32_t ord;   // payload: voxel ordinal (loaded only for the corr output)
 };
 
-// Reads the entry of each lane and issues its 9 global loads (no branches:
+// Reads the entry of each lane and issues its buffer loads (no branches:
 // dead lanes of a partial batch read entry `head`, point 0 and payload 0).  Only
 // words that are used are loaded: a dead destination register could be
 // reused while its load is in flight, which forces an early wait.
 template <bool CORR>
 __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t e, bool live,
-                                           const float *pc, int64_t n, const Payload *payload) {
+                                           Rsrc rc, Rsrc rp) {
   B.x = Q.x[e];
   B.y = Q.y[e];
   B.z = Q.z[e];
   const int32_t idx = Q.idx[e];
   const int32_t pidx = Q.pidx[e];
   B.idx = live ? idx : 0;
-  // the point's covariance: 24 contiguous bytes, three 8-byte loads
-  gfloat2 *gc = (gfloat2 *)pc + 3 * int64_t(B.idx);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const f32x2 v = __builtin_nontemporal_load(gc + a);
-    B.c[2 * a] = v.x;
-    B.c[2 * a + 1] = v.y;
-  }
-  const Payload *pl = payload + (live ? pidx : 0);
-  gfloat4 *gp = (gfloat4 *)pl;
-  B.w0 = gp[0];
-  B.w1 = gp[1];
-  B.czz = *(gfloat *)(&pl->cov[5]);
-  if constexpr (CORR) B.ord = *(const int32_t __attribute__((address_space(1))) *)(&pl->ordinal);
+  // the point's covariance: 24 contiguous bytes, two 12-byte loads
+  const uint32_t co = uint32_t(B.idx) * 24u;
+  const f32x3 c0 = ld_f32x3<kNT>(rc, co), c1 = ld_f32x3<kNT>(rc, co + 12u);
+  B.c[0] = c0.x, B.c[1] = c0.y, B.c[2] = c0.z;
+  B.c[3] = c1.x, B.c[4] = c1.y, B.c[5] = c1.z;
+  const uint32_t po = uint32_t(live ? pidx : 0) << 6;
+  B.w0 = ld_f32x4(rp, po);
+  B.w1 = ld_f32x4(rp, po + 16u);
+  B.czz = ld_f32(rp, po + 32u);
+  if constexpr (CORR) B.ord = __builtin_bit_cast(int32_t, ld_f32(rp, po + 36u));
   // keep the other batch's math below these loads (hoisting it would make it
   // wait for that batch's loads before these are issued)
   __builtin_amdgcn_sched_barrier(0);
@@ -587,7 +643,7 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
   } else {
 #pragma clang fp contract(off)
     float q[3];
-    lookup_transform(k.R, k.t, B.x, B.y, B.z, q);
+    transform_fp32(k.R, k.t, B.x, B.y, B.z, q);
     e[0] = m[0] - q[0];
     e[1] = m[1] - q[1];
     e[2] = m[2] - q[2];
@@ -627,16 +683,16 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
   const FactorConsts k = factor_consts(fd, poses);
-  const int64_t n = fd.n;
-  const float *__restrict__ px = fd.xyz;
-  const float *__restrict__ pc = fd.cov;
-  const BrickRecord *__restrict__ bricks = fd.bricks;
-  const Payload *__restrict__ payload = fd.payload;
-  const int64_t begin = td.start;
-  const int64_t end = min(begin + int64_t(tile_points), n);
+  const uint32_t n = uint32_t(fd.n);
+  const uint32_t begin = uint32_t(td.start);
+  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const Rsrc rc = make_rsrc(fd.cov, 24ull * n);
+  const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
+  const Rsrc rp = make_rsrc(fd.payload, 64ull * fd.n_voxels);
   int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset : nullptr;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x >> 6;
   HitQueue &Q = queues[wave];
 
   SumsT acc;
@@ -644,13 +700,13 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   uint32_t head = 0, count = 0;  // wave-uniform ring state
   uint32_t hits = 0;             // wave-uniform hit count
 
-  // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead).
+  // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead;
+  // past the tile's end the loads return zeros and the lanes are invalid).
   float cur[kChunk][3];
-  int64_t base = begin + wave * 64;
+  uint32_t base = begin + wave * 64;
   if (base < end) {
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p)
-      load_xyz(px, n, min(base + p * kBlock + lane, end - 1), cur[p]);
+    for (int p = 0; p < kChunk; ++p) load_xyz(cx, base - begin + p * kBlock + lane, cur[p]);
   }
   while (base < end) {
     // ---- lookup phase: the brick records of all kChunk passes are in flight
@@ -661,26 +717,25 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     RecordLoad rec[kChunk];
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
-      float q[3];
-      lookup_transform(k.R, k.t, cur[p][0], cur[p][1], cur[p][2], q);
-      vk[p] = voxel_key(q, fd.scale, fd.log2cap);
+      float v[3];
+      lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
+      vk[p] = voxel_key(v, fd.log2cap);
     }
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) rec[p] = load_record(bricks, vk[p].h);
+    for (int p = 0; p < kChunk; ++p) rec[p] = load_record(rb, vk[p].h);
     __builtin_amdgcn_sched_barrier(0);
     float nxt[kChunk][3];
 #pragma unroll
     for (int p = 0; p < kChunk; ++p)
-      load_xyz(px, n, min(base + (kChunk + p) * kBlock + lane, end - 1), nxt[p]);
+      load_xyz(cx, base - begin + (kChunk + p) * kBlock + lane, nxt[p]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
-      const int64_t i = base + p * kBlock + lane;
-      const bool valid = i < end;
-      const int hs = find_voxel(bricks, fd.log2cap, vk[p], rec[p]);
-      const int h = (valid && vk[p].ok) ? hs : -1;
+      const uint32_t i = base + p * kBlock + lane;
+      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p]);
+      const int h = i < end ? hs : -1;
       if constexpr (CORR) {
-        if (valid && h < 0) pcorr[i] = -1;
+        if (i < end && h < 0) pcorr[i] = -1;
       }
       const uint64_t mask = __ballot(h >= 0);
       if (h >= 0) {
@@ -709,19 +764,19 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       // unrolled by two so that the buffers swap roles without copies (a
       // copy would wait for the loads it copies)
       Batch A, B;
-      batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
+      batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rp);
       head = ring_add(head, 64);
       uint32_t bi = 1;
       for (; bi + 1 < nb; bi += 2) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rp);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
-        batch_load<CORR>(A, Q, ring_add(head, lane), true, pc, n, payload);
+        batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rp);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       }
       if (bi < nb) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, pc, n, payload);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rp);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
@@ -733,9 +788,9 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     __builtin_amdgcn_wave_barrier();
   }
   if (count > 0) {  // last partial batch: dead lanes add nothing
-    const bool live = uint32_t(lane) < count;
+    const bool live = lane < count;
     Batch A;
-    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, pc, n, payload);
+    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rp);
     if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
   }
 
@@ -767,42 +822,41 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
   const FactorConsts k = factor_consts(fd, poses);
-  const int64_t n = fd.n;
-  const float *__restrict__ px = fd.xyz;
-  const int64_t begin = td.start;
-  const int64_t end = min(begin + int64_t(tile_points), n);
+  const uint32_t n = uint32_t(fd.n);
+  const uint32_t begin = uint32_t(td.start);
+  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   int hits = 0;
-  const float *__restrict__ pk = px;
   float cur[kOvlChunk][3];
-  int64_t base = begin + int64_t(threadIdx.x & ~63);
-  const int lane = threadIdx.x & 63;
+  uint32_t base = begin + (threadIdx.x & ~63u);
+  const uint32_t lane = threadIdx.x & 63;
   if (base < end) {
 #pragma unroll
-    for (int p = 0; p < kOvlChunk; ++p)
-      load_xyz(pk, n, min(base + p * kBlock + lane, end - 1), cur[p]);
+    for (int p = 0; p < kOvlChunk; ++p) load_xyz(cx, base - begin + p * kBlock + lane, cur[p]);
   }
   for (; base < end; base += kOvlChunk * kBlock) {
     VoxelKey vk[kOvlChunk];
     RecordLoad rec[kOvlChunk];
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p) {
-      float q[3];
-      lookup_transform(k.R, k.t, cur[p][0], cur[p][1], cur[p][2], q);
-      vk[p] = voxel_key(q, fd.scale, fd.log2cap);
+      float v[3];
+      lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
+      vk[p] = voxel_key(v, fd.log2cap);
     }
 #pragma unroll
-    for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_record(fd.bricks, vk[p].h);
+    for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_record(rb, vk[p].h);
     __builtin_amdgcn_sched_barrier(0);
     float nxt[kOvlChunk][3];
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p)
-      load_xyz(pk, n, min(base + (kOvlChunk + p) * kBlock + lane, end - 1), nxt[p]);
+      load_xyz(cx, base - begin + (kOvlChunk + p) * kBlock + lane, nxt[p]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p) {
       const bool valid = base + p * kBlock + lane < end;
-      const int hs = find_voxel(fd.bricks, fd.log2cap, vk[p], rec[p]);
-      hits += (valid && vk[p].ok && hs >= 0) ? 1 : 0;
+      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p]);
+      hits += (valid && hs >= 0) ? 1 : 0;
     }
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p)

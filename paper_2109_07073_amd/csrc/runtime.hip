@@ -203,8 +203,8 @@ int vgicp_voxelize(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, v
   *out = nullptr;
   if (!cloud) return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: cloud is NULL");
   if (cloud->n < 0) return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: n < 0");
-  if (cloud->n > INT32_MAX)
-    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: more than 2^31-1 points");
+  if (cloud->n > kMaxCloudPoints)
+    return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: more than 2^26 points");
   if (cloud->n > 0 && (!cloud->xyz || !cloud->cov))
     return fail(ctx, VGICP_EINVAL, "vgicp_voxelize: NULL point arrays with n > 0");
   if (cloud->n > 0 && (reinterpret_cast<uintptr_t>(cloud->cov) & 7u))
@@ -297,7 +297,7 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
                 "vgicp_factorset_create: tile_points must be a multiple of 256 in [256, 2^20]");
   for (int32_t s = 0; s < n_sources; ++s) {
     const vgicp_cloud &c = sources[s];
-    if (c.n < 0 || c.n > INT32_MAX || (c.n > 0 && (!c.xyz || !c.cov)) ||
+    if (c.n < 0 || c.n > kMaxCloudPoints || (c.n > 0 && (!c.xyz || !c.cov)) ||
         (c.n > 0 && (reinterpret_cast<uintptr_t>(c.cov) & 7u)))
       return fail(ctx, VGICP_EINVAL,
                   "vgicp_factorset_create: source " + std::to_string(s) + " is invalid");
@@ -356,6 +356,7 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     d.pose_j = x.pose_j;
     d.log2cap = m->log2cap;
     d.scale = m->scale;
+    d.n_voxels = uint32_t(m->n_voxels);
     corr_off += c.n;
   }
   fs->total_points = corr_off;

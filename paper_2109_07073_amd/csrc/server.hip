@@ -250,6 +250,7 @@ void launch_batch(vgicp_server srv, size_t si) {
       d.pose_j = int32_t(pose_base + x.pose_j);
       d.log2cap = tgt.map->log2cap;
       d.scale = tgt.map->scale;
+      d.n_voxels = uint32_t(tgt.map->n_voxels);
       d.tile_begin = int32_t(nt);
       for (int64_t st = 0; st < n; st += tp) s.h_tiles[nt++] = Tile{int32_t(nf), int32_t(st)};
       d.n_tiles = int32_t(nt - d.tile_begin);
@@ -530,7 +531,7 @@ int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_
                            double resolution, int32_t *frame_id) {
   if (!srv) return VGICP_EINVAL;
   if (!frame_id) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: frame_id is NULL");
-  if (n < 0 || n > INT32_MAX || (n > 0 && (!h_xyz || !h_cov)))
+  if (n < 0 || n > kMaxCloudPoints || (n > 0 && (!h_xyz || !h_cov)))
     return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: bad cloud");
   if (!std::isfinite(resolution) || !(resolution > 0.0))
     return srv_fail(srv, VGICP_EINVAL, "vgicp_server_add_frame: bad resolution");

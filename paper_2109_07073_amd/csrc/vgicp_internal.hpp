@@ -32,31 +32,55 @@ __host__ __device__ inline int32_t key_field(uint64_t key, int which) {
 }
 
 // ---------------------------------------------------------------- bricks
-// Voxels are grouped in bricks of 4 x 4 x 4.  A brick key packs floor(k / 4)
-// per axis as three biased 19-bit fields (57 bits); voxel (kx, ky, kz) is bit
+// Voxels are grouped in bricks of 4 x 4 x 4.  Voxel (kx, ky, kz) is bit
 // (kx & 3) << 4 | (ky & 3) << 2 | (kz & 3) of its brick's 64-bit occupancy
 // mask.  Consecutive points of a scan mostly fall in the same or neighbouring
 // bricks, so their lookups share brick records (and cache lines) instead of
 // scattering over a voxel-keyed table.
-constexpr int kBrickBits = 19;
-constexpr int32_t kBrickBias = 1 << 18;  // floor(k / 4) lies in [-2^18, 2^18)
+//
+// A brick is named by one field per axis, floor(k / 4) + 2^18 + 1, which is
+// in [1, 2^19] for keys in [-2^20, 2^20).  A lookup clamps the scaled
+// coordinate to [-2^20 - 4, 2^20] instead of testing the range, so a point
+// outside the key range (or NaN) gets field 0 or 2^19 + 1: a brick no map
+// holds.  Record keys pack the fields in 20 bits each (60 bits, never
+// kEmptyKey).
+constexpr int kBrickBits = 20;
+constexpr int32_t kBrickBias = (1 << 18) + 1;
+constexpr float kClampLoF = -1048580.0f;  // -2^20 - 4
+constexpr float kClampHiF = 1048576.0f;   // 2^20
 
-__host__ __device__ inline uint64_t pack_brick(int32_t kx, int32_t ky, int32_t kz) {
-  return (uint64_t(uint32_t((kx >> 2) + kBrickBias)) << (2 * kBrickBits)) |
-         (uint64_t(uint32_t((ky >> 2) + kBrickBias)) << kBrickBits) |
-         uint64_t(uint32_t((kz >> 2) + kBrickBias));
+__host__ __device__ inline uint32_t brick_field(int32_t k) {
+  return uint32_t((k >> 2) + kBrickBias);
+}
+
+__host__ __device__ inline uint64_t brick_key(uint32_t fx, uint32_t fy, uint32_t fz) {
+  return (uint64_t(fx) << (2 * kBrickBits)) | (uint64_t(fy) << kBrickBits) | uint64_t(fz);
 }
 
 __host__ __device__ inline uint32_t brick_bit(int32_t kx, int32_t ky, int32_t kz) {
   return (uint32_t(kx & 3) << 4) | (uint32_t(ky & 3) << 2) | uint32_t(kz & 3);
 }
 
-// Home record of a brick from its three biased 19-bit fields: a linear
-// combination with 24-bit odd multipliers (full-rate 24-bit multiplies on
-// gfx950) folded to 32 bits, then a 32-bit Fibonacci hash.  Neighbouring
-// bricks land on well-spread records, so the bricks a wave touches rarely
-// collide (about 1 % of waves probe past the home record on scan workloads,
-// against 12 % for a 64-bit hash of the packed key).
+// Brick-major sort key of an in-range voxel: the brick fields less one (19
+// bits each, 57 bits) above the voxel's bit in the brick.
+__host__ __device__ inline uint64_t brick_sort_key(int32_t kx, int32_t ky, int32_t kz) {
+  const uint64_t g = (uint64_t(brick_field(kx) - 1u) << 38) |
+                     (uint64_t(brick_field(ky) - 1u) << 19) | uint64_t(brick_field(kz) - 1u);
+  return (g << 6) | uint64_t(brick_bit(kx, ky, kz));
+}
+
+__host__ __device__ inline uint64_t brick_key_of_sort_key(uint64_t sk) {
+  const uint64_t g = sk >> 6;
+  const uint32_t m = (1u << 19) - 1u;
+  return brick_key(uint32_t(g >> 38) + 1u, (uint32_t(g >> 19) & m) + 1u, (uint32_t(g) & m) + 1u);
+}
+
+// Home record of a brick from its fields: a linear combination with 24-bit
+// odd multipliers (full-rate 24-bit multiplies on gfx950) folded to 32 bits,
+// then a 32-bit Fibonacci hash.  Neighbouring bricks land on well-spread
+// records, so the bricks a wave touches rarely collide (about 1 % of waves
+// probe past the home record on scan workloads, against 12 % for a 64-bit
+// hash of the packed key).
 __host__ __device__ inline uint32_t brick_slot(uint32_t fx, uint32_t fy, uint32_t fz,
                                                uint32_t log2cap) {
   const uint32_t k = fz + (fy & 0xffffffu) * 1403u + (fx & 0xffffffu) * 2968591u;
@@ -68,6 +92,11 @@ __host__ __device__ inline uint32_t brick_slot_of_key(uint64_t bkey, uint32_t lo
   return brick_slot(uint32_t(bkey >> (2 * kBrickBits)) & m, uint32_t(bkey >> kBrickBits) & m,
                     uint32_t(bkey) & m, log2cap);
 }
+
+// Size limits that keep every byte offset of a cloud or map within 32 bits
+// (the kernels address them through buffer resources).
+constexpr int64_t kMaxCloudPoints = int64_t(1) << 26;
+constexpr int64_t kMaxMapBricks = int64_t(1) << 24;
 
 // A voxel map is an open-addressed table of brick records (linear probing,
 // load factor at most 1/8) plus a dense payload array:
@@ -110,10 +139,10 @@ constexpr int kDefaultTile = 6 * kTileQuantum;  // 4608 points
 // Per-factor device descriptor (read with uniform loads by every tile).
 struct FactorDesc {
   const float *xyz;        // [3][n]
-  const float *cov;        // [6][n]
+  const float *cov;        // [n][6]
   const BrickRecord *bricks;  // target map: brick table
   const Payload *payload;     // target map: dense voxel payloads
-  int64_t n;          // source points
+  int64_t n;          // source points (at most kMaxCloudPoints)
   int64_t corr_offset;
   int32_t pose_i;
   int32_t pose_j;
@@ -121,6 +150,8 @@ struct FactorDesc {
   float scale;        // fl32(1/r) of the target map
   int32_t tile_begin; // first tile of this factor in the tile table
   int32_t n_tiles;
+  uint32_t n_voxels;  // target map: payloads
+  uint32_t pad;
 };
 
 // One tile: `count` source points of factor `factor` starting at `start`.

@@ -88,7 +88,7 @@ k_brick_sortkeys(const uint64_t *__restrict__ sorted_keys, const uint32_t *__res
   const uint64_t key = sorted_keys[seg[v]];
   const int32_t kx = key_field(key, 0), ky = key_field(key, 1), kz = key_field(key, 2);
   vkey[v] = key;
-  bsort[v] = (pack_brick(kx, ky, kz) << 6) | uint64_t(brick_bit(kx, ky, kz));
+  bsort[v] = brick_sort_key(kx, ky, kz);
   vord[v] = uint32_t(v);
 }
 
@@ -111,7 +111,7 @@ k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ 
   const uint32_t d1 = (b + 1 < n_bricks) ? bstart[b + 1] : uint32_t(n_voxels);
   uint64_t mask = 0;
   for (uint32_t d = d0; d < d1; ++d) mask |= 1ull << (bsort[d] & 63u);
-  const uint64_t key = bsort[d0] >> 6;
+  const uint64_t key = brick_key_of_sort_key(bsort[d0]);
   const uint32_t cmask = (1u << log2cap) - 1u;
   uint32_t h = brick_slot_of_key(key, log2cap);
   for (uint32_t probe = 0; probe <= cmask; ++probe) {
@@ -381,16 +381,17 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 
   // Load factor at most 1/8: a lookup in an empty brick (most misses of a
   // partial overlap) almost always stops at an empty home record or one
-  // probe later.  Slots are 32-bit indices, so the table stops at 2^31.
+  // probe later.  At most kMaxMapBricks bricks, so the table (at most 2^27
+  // records) stays within 32-bit byte offsets.
+  if (n_bricks > kMaxMapBricks) {
+    msg = "vgicp_voxelize: more than 2^24 occupied bricks in one map";
+    return VGICP_EINVAL;
+  }
   int64_t cap = 16;
   uint32_t log2cap = 4;
-  while (cap < 8 * n_bricks && cap < (int64_t(1) << 31)) {
+  while (cap < 8 * n_bricks) {
     cap <<= 1;
     ++log2cap;
-  }
-  if (cap < 2 * n_bricks) {
-    msg = "vgicp_voxelize: more than 2^30 bricks in one map";
-    return VGICP_EINVAL;
   }
   vgicp_map m = new (std::nothrow) vgicp_voxelmap_s();
   if (!m) {

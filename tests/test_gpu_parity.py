@@ -130,7 +130,7 @@ def test_voxelize_rejects_nonfinite_and_out_of_range(vg, ctx):
     with pytest.raises(vg.VgicpError) as ex:
         vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.0)
     assert ex.value.code == vg.EINVAL
-    # covariances must be 8-byte aligned (they are read 8 bytes at a time)
+    # covariances must be 8-byte aligned, as the interface states
     import torch
     dx, dc = vg.cloud_to_device(xyz, cov)
     buf = torch.zeros(6 * 300 + 1, dtype=torch.float32, device="cuda")
@@ -145,6 +145,30 @@ def test_voxelize_rejects_nonfinite_and_out_of_range(vg, ctx):
     # the context stays usable
     m = vg.voxelize(ctx, *vg.cloud_to_device(xyz, cov), 0.5)
     assert m.n_voxels == 1
+
+
+def test_clouds_above_the_size_limit_are_refused(vg, ctx):
+    """Clouds of more than 2^26 points are refused by the host-side checks,
+    before any device access (the counts here exceed the small buffers the
+    pointers name, which nothing reads)."""
+    import ctypes
+    xyz = np.zeros((4, 3), np.float32)
+    cov = np.tile(np.array([1, 0, 0, 1, 0, 1], np.float32), (4, 1))
+    dx, dc = vg.cloud_to_device(xyz, cov)
+    big = (1 << 26) + 1
+    c = vg.CCloud(dx.data_ptr(), dc.data_ptr(), big)
+    h = ctypes.c_void_p()
+    rc = vg._lib.vgicp_voxelize(ctx.handle, ctypes.byref(c), ctypes.c_double(0.5), ctypes.byref(h))
+    assert rc == vg.EINVAL and not h.value
+    assert "2^26" in vg._lib.vgicp_last_error(ctx.handle).decode()
+    m = vg.voxelize(ctx, dx, dc, 0.5)
+    cl = (vg.CCloud * 1)(c)
+    mp = (ctypes.c_void_p * 1)(m.handle)
+    fac = (vg.CFactor * 1)(vg.CFactor(0, 0, 0, 0))
+    fs = ctypes.c_void_p()
+    rc = vg._lib.vgicp_factorset_create(ctx.handle, cl, 1, mp, 1, fac, 1, 1, 0, ctypes.byref(fs))
+    assert rc == vg.EINVAL and not fs.value
+    ctx.synchronize()
 
 
 # ------------------------------------------------------ correspondences, H/b/e

@@ -30,6 +30,11 @@ def _pins_hold() -> bool:
         for o in range(0, vm.n_voxels, 7):
             m = txyz[inv == o].mean(0)
             assert np.allclose(vm.mean[o], m, rtol=1e-6, atol=1e-6)
+        # FP32 fused multiply-add: (1 + 2^-24) + 2^-80 lies just above the
+        # midpoint of 1 and 1 + 2^-23, so it rounds up
+        a, b = np.float32(24929 * 2.0 ** -12), np.float32(673 * 2.0 ** -12)
+        assert vo.fma32(a, b, np.float32(2.0 ** -80)) == np.float32(1 + 2.0 ** -23)
+        assert vo.fma32(a, b, np.float32(-(2.0 ** -80))) == np.float32(1.0)
         # correspondences against the exact motion and a box scan
         R, t = oracle.relative_pose(pi, pj)
         corr = oracle.lookup(vm, xyz, R, t)
@@ -118,6 +123,11 @@ def _voxelize_count_off_by_one(xyz, cov, r):
     return vm, inv
 
 
+def _fma32_two_roundings(a, b, c):
+    a64, b64, c64 = (np.asarray(v, np.float32).astype(np.float64) for v in (a, b, c))
+    return (a64 * b64 + c64).astype(np.float32)
+
+
 _orig_jac = vo.jacobians
 _orig_fused = vo.fused_information
 _orig_res = vo.residuals
@@ -134,6 +144,7 @@ MUTANTS = [
     ("relative_pose", _relpose_reversed),
     ("relative_pose", _relpose_transposed),
     ("voxelize", _voxelize_count_off_by_one),
+    ("fma32", _fma32_two_roundings),
 ]
 
 

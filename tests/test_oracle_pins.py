@@ -3,7 +3,8 @@ mathematics (CPU only).
 
   * voxel keys: hand-derived table (tests/golden/voxel_keys.txt);
   * voxel map: brute-force grouping with exact rational arithmetic;
-  * correspondences: linear scan over every voxel box;
+  * correspondences: linear scan over every voxel box; the FP32 fused
+    multiply-add against exact rational arithmetic;
   * relative pose: 4x4 inverse;
   * H, b: central finite differences of the frozen residual;
     gradient of the frozen cost = 2 b;
@@ -120,14 +121,76 @@ def test_relative_pose_equal_poses_is_exact_identity(tiny):
 
 # ---------------------------------------------------------- correspondences
 
-def test_lookup_transform_is_the_relative_motion(tiny):
+def _rn32(x: Fraction) -> np.float32:
+    """The float32 nearest to the rational x (ties to an even last bit),
+    chosen among the neighbours of a first guess by exact comparison."""
+    g = np.float32(float(x))
+    cands = [np.nextafter(g, np.float32(-np.inf)), g, np.nextafter(g, np.float32(np.inf))]
+    best = min(cands, key=lambda f: (abs(Fraction(float(f)) - x),
+                                     int(np.array(f, np.float32).view(np.int32)) & 1))
+    return np.float32(best)
+
+
+def _fma_cases():
+    """(a, b, c) float32 triples whose exact a*b + c lies on, or a hair off,
+    a midpoint between two float32 values, where rounding the FP64 sum to
+    FP32 (two roundings) goes the wrong way."""
+    two = np.float32
+    a, b = two(24929 * 2.0 ** -12), two(673 * 2.0 ** -12)   # a * b = 1 + 2^-24 exactly
+    tiny = two(2.0 ** -80)
+    return [(a, b, tiny), (a, b, -tiny), (a, b, two(0.0)),
+            (-a, b, -tiny), (a, -b, tiny), (a, b, two(2.0 ** -60)),
+            (two(3.0), two(1.0 / 3.0), two(-1.0))]
+
+
+def test_fma32_rounds_once_on_midpoint_cases():
+    """On sums that sit on or next to a float32 midpoint, fma32 equals the
+    exact sum rounded once, where the FP64 sum rounded to FP32 does not."""
+    wrong_twice = 0
+    for a, b, c in _fma_cases():
+        exact = Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))
+        want = _rn32(exact)
+        got = oracle.vgicp_oracle.fma32(a, b, c)
+        assert got.view(np.int32) == np.array(want).view(np.int32), (a, b, c)
+        twice = np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+        wrong_twice += int(twice != want)
+    assert wrong_twice >= 2
+
+
+def test_fma32_matches_exact_rounding_on_random_operands():
+    rng = np.random.default_rng(5)
+    n = 3000
+    a = (rng.standard_normal(n) * 10.0 ** rng.integers(-3, 4, n)).astype(np.float32)
+    b = (rng.standard_normal(n) * 10.0 ** rng.integers(-3, 4, n)).astype(np.float32)
+    c = (-(a.astype(np.float64) * b) * (1 + rng.standard_normal(n) * 1e-6)).astype(np.float32)
+    c[::3] = rng.standard_normal(c[::3].shape).astype(np.float32)
+    got = oracle.vgicp_oracle.fma32(a, b, c)
+    for k in range(n):
+        exact = Fraction(float(a[k])) * Fraction(float(b[k])) + Fraction(float(c[k]))
+        assert got[k].view(np.int32) == np.array(_rn32(exact)).view(np.int32), k
+
+
+def test_lookup_coords_are_the_scaled_relative_motion(tiny):
     xyz = tiny.sources[0][0]
     R, t = oracle.relative_pose(tiny.poses[0], tiny.poses[1])
-    q = oracle.vgicp_oracle.lookup_transform_fp32(xyz, R, t)
+    s = oracle.voxel_scale(0.5)
+    v = oracle.vgicp_oracle.lookup_coords_fp32(xyz, R, t, s)
     T = np.linalg.inv(hom(tiny.poses[1])) @ hom(tiny.poses[0])
-    q64 = xyz.astype(np.float64) @ T[:3, :3].T + T[:3, 3]
-    scale = np.abs(xyz).max() + np.abs(T[:3, 3]).max()
-    assert np.abs(q - q64).max() < 8 * np.finfo(np.float32).eps * scale
+    v64 = (xyz.astype(np.float64) @ T[:3, :3].T + T[:3, 3]) * float(s)
+    scale = (np.abs(xyz).max() + np.abs(T[:3, 3]).max()) * float(s)
+    assert np.abs(v - v64).max() < 8 * np.finfo(np.float32).eps * scale
+
+
+def test_lookup_coords_identity_pose_are_the_voxelization_coords(tiny):
+    """Under the identity the lookup coordinates are fl32(x * s), the
+    coordinates voxelization takes its keys from, so every point finds its
+    own voxel."""
+    xyz, cov = tiny.targets[0]
+    s = oracle.voxel_scale(0.5)
+    v = oracle.vgicp_oracle.lookup_coords_fp32(xyz, np.eye(3), np.zeros(3), s)
+    assert np.array_equal(v, (xyz.astype(np.float32) * s).astype(np.float32))
+    vm, inv = oracle.voxelize(xyz, cov, 0.5)
+    assert np.array_equal(oracle.lookup(vm, xyz, np.eye(3), np.zeros(3)), inv)
 
 
 @pytest.mark.parametrize("r", [0.5, 1.0])
@@ -136,9 +199,9 @@ def test_lookup_linear_scan(tiny, r):
     vm, _ = oracle.voxelize(*tgt, r)
     R, t = oracle.relative_pose(tiny.poses[0], tiny.poses[1])
     corr = oracle.lookup(vm, src, R, t)
-    q = oracle.vgicp_oracle.lookup_transform_fp32(src, R, t).astype(np.float64)
-    lo = vm.keys.astype(np.float64) * r                # (V, 3) voxel boxes
-    inside = np.all((q[:, None, :] >= lo[None]) & (q[:, None, :] < lo[None] + r), axis=2)
+    v = oracle.vgicp_oracle.lookup_coords_fp32(src, R, t, vm.scale).astype(np.float64)
+    lo = vm.keys.astype(np.float64)                    # (V, 3) voxel boxes, voxel units
+    inside = np.all((v[:, None, :] >= lo[None]) & (v[:, None, :] < lo[None] + 1.0), axis=2)
     want = np.where(inside.any(1), inside.argmax(1), -1)
     assert inside.sum(1).max() <= 1
     assert np.array_equal(corr, want)
