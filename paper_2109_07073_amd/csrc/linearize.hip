@@ -151,8 +151,8 @@ __device__ __forceinline__ VoxelKey voxel_key(const float v[3], uint32_t log2cap
   return r;
 }
 
-// A brick record as loaded: key and mask (one 16-byte load) and the payload
-// base.
+// A brick record as loaded: key and mask (one 16-byte load) and the index of
+// the brick's first voxel.
 struct RecordLoad {
   f32x4 km;
   uint32_t base;
@@ -584,8 +584,8 @@ constexpr uint32_t kRing = 64 * kChunk + 64;  // >= 63 left over + 64 * kChunk a
 
 struct HitQueue {
   float x[kRing], y[kRing], z[kRing];
-  int32_t idx[kRing];   // point index in the source cloud
-  int32_t pidx[kRing];  // payload index of its voxel in the target map
+  int32_t idx[kRing];   // point index in the tile
+  int32_t pidx[kRing];  // index of its voxel in the target map's dense arrays
 };
 
 __device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
@@ -598,34 +598,36 @@ struct Batch {
   float x, y, z;
   int32_t idx;
   float c[6];    // point covariance
-  f32x4 w0, w1;  // payload: mean (w0.xyz), cov xx..yz (w0.w, w1)
-  float czz;     // payload: cov zz
-  int32_t ord;   // payload: voxel ordinal (loaded only for the corr output)
+  f32x4 w0, w1;  // voxel statistics: mean (w0.xyz), cov xx..yz (w0.w, w1)
+  float czz;     // voxel statistics: cov zz
+  int32_t ord;   // voxel ordinal (loaded only for the corr output)
 };
 
 // Reads the entry of each lane and issues its buffer loads (no branches:
-// dead lanes of a partial batch read entry `head`, point 0 and payload 0).  Only
+// dead lanes of a partial batch read entry `head`, point 0 and voxel 0).  Only
 // words that are used are loaded: a dead destination register could be
 // reused while its load is in flight, which forces an early wait.
 template <bool CORR>
 __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t e, bool live,
-                                           Rsrc rc, Rsrc rp) {
+                                           Rsrc rc, Rsrc rs, Rsrc rz, Rsrc ri) {
   B.x = Q.x[e];
   B.y = Q.y[e];
   B.z = Q.z[e];
   const int32_t idx = Q.idx[e];
   const int32_t pidx = Q.pidx[e];
   B.idx = live ? idx : 0;
-  // the point's covariance: 24 contiguous bytes, two 12-byte loads
-  const uint32_t co = uint32_t(B.idx) * 24u;
+  // the point's covariance: 24 contiguous bytes, two 12-byte loads (the
+  // index is within the tile, below 2^20: a 24-bit multiply)
+  const uint32_t co = (uint32_t(B.idx) & 0xffffffu) * 24u;
   const f32x3 c0 = ld_f32x3<kNT>(rc, co), c1 = ld_f32x3<kNT>(rc, co + 12u);
   B.c[0] = c0.x, B.c[1] = c0.y, B.c[2] = c0.z;
   B.c[3] = c1.x, B.c[4] = c1.y, B.c[5] = c1.z;
-  const uint32_t po = uint32_t(live ? pidx : 0) << 6;
-  B.w0 = ld_f32x4(rp, po);
-  B.w1 = ld_f32x4(rp, po + 16u);
-  B.czz = ld_f32(rp, po + 32u);
-  if constexpr (CORR) B.ord = __builtin_bit_cast(int32_t, ld_f32(rp, po + 36u));
+  // the voxel's statistics: a 32-byte record and the zz term
+  const uint32_t v = uint32_t(live ? pidx : 0);
+  B.w0 = ld_f32x4(rs, v << 5);
+  B.w1 = ld_f32x4(rs, (v << 5) + 16u);
+  B.czz = ld_f32(rz, v << 2);
+  if constexpr (CORR) B.ord = __builtin_bit_cast(int32_t, ld_f32(ri, (v << 4) + 8u));
   // keep the other batch's math below these loads (hoisting it would make it
   // wait for that batch's loads before these are issued)
   __builtin_amdgcn_sched_barrier(0);
@@ -662,7 +664,7 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //           of the next pass's coordinates (a fixed set of loads per pass, so
 //           the key wait never waits for the prefetch); hits are appended to
 //           the wave's ring;
-//   math:   the full batches of 64 hits, double-buffered: a batch's payload
+//   math:   the full batches of 64 hits, double-buffered: a batch's voxel
 //           and covariance gathers are in flight during the previous batch's
 //           math.
 // The last partial batch runs at the end of the tile.
@@ -687,10 +689,12 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
-  const Rsrc rc = make_rsrc(fd.cov, 24ull * n);
+  const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
-  const Rsrc rp = make_rsrc(fd.payload, 64ull * fd.n_voxels);
-  int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset : nullptr;
+  const Rsrc rs = make_rsrc(fd.stats, 32ull * fd.n_voxels);
+  const Rsrc rz = make_rsrc(fd.cov_zz, 4ull * fd.n_voxels);
+  const Rsrc ri = make_rsrc(fd.info, 16ull * fd.n_voxels);
+  int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset + begin : nullptr;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = threadIdx.x >> 6;
   HitQueue &Q = queues[wave];
@@ -735,7 +739,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p]);
       const int h = i < end ? hs : -1;
       if constexpr (CORR) {
-        if (i < end && h < 0) pcorr[i] = -1;
+        if (i < end && h < 0) pcorr[i - begin] = -1;
       }
       const uint64_t mask = __ballot(h >= 0);
       if (h >= 0) {
@@ -745,7 +749,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
         Q.x[e] = cur[p][0];
         Q.y[e] = cur[p][1];
         Q.z[e] = cur[p][2];
-        Q.idx[e] = int32_t(i);
+        Q.idx[e] = int32_t(i - begin);
         Q.pidx[e] = h;
       }
       const uint32_t got = uint32_t(__popcll(mask));
@@ -764,19 +768,19 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       // unrolled by two so that the buffers swap roles without copies (a
       // copy would wait for the loads it copies)
       Batch A, B;
-      batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rp);
+      batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, rz, ri);
       head = ring_add(head, 64);
       uint32_t bi = 1;
       for (; bi + 1 < nb; bi += 2) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rp);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
-        batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rp);
+        batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
       }
       if (bi < nb) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rp);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
@@ -790,7 +794,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   if (count > 0) {  // last partial batch: dead lanes add nothing
     const bool live = lane < count;
     Batch A;
-    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rp);
+    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, rz, ri);
     if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
   }
 

@@ -349,7 +349,9 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     d.xyz = c.xyz;
     d.cov = c.cov;
     d.bricks = m->bricks;
-    d.payload = m->payload;
+    d.stats = m->stats;
+    d.cov_zz = m->cov_zz;
+    d.info = m->info;
     d.n = c.n;
     d.corr_offset = corr_off;
     d.pose_i = x.pose_i;

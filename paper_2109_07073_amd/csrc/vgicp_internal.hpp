@@ -99,14 +99,20 @@ constexpr int64_t kMaxCloudPoints = int64_t(1) << 26;
 constexpr int64_t kMaxMapBricks = int64_t(1) << 24;
 
 // A voxel map is an open-addressed table of brick records (linear probing,
-// load factor at most 1/8) plus a dense payload array:
+// load factor at most 1/8) plus dense per-voxel arrays:
 //   bricks[cap]  32-byte records {brick key (kEmptyKey when free), occupancy
-//                mask, payload index of the brick's first voxel}; a lookup
-//                reads key and mask with one 16-byte load and the base with
-//                a second load from the same record;
-//   payload[V]   the voxels' statistics, brick after brick and by mask bit
+//                mask, index of the brick's first voxel}; a lookup reads key
+//                and mask with one 16-byte load and the base with a second
+//                load from the same record;
+//   stats[V]     what a correspondence reads: mean and the covariance terms
+//                xx xy xz yy yz (32 bytes), brick after brick and by mask bit
 //                within a brick, so voxel b of a brick sits at
-//                base + popcount(mask & (2^b - 1)).
+//                base + popcount(mask & (2^b - 1)) and the voxels of a scan
+//                neighbourhood share cache lines;
+//   cov_zz[V]    the covariance term zz, in the same order (36 bytes per
+//                voxel in all, addressed by shifts);
+//   info[V]      in the same order, what only the map export and the
+//                correspondence output read (packed key, ordinal, count).
 struct alignas(32) BrickRecord {
   uint64_t key;
   uint64_t mask;
@@ -115,18 +121,18 @@ struct alignas(32) BrickRecord {
 };
 static_assert(sizeof(BrickRecord) == 32, "brick record layout");
 
-// A payload is 64 bytes so that it never straddles a 128-byte line.  The
-// packed voxel key is kept for the map export.
-struct alignas(64) Payload {
+struct alignas(32) VoxelStats {
   float mean[3];
-  float cov[6];  // xx xy xz yy yz zz
-  int32_t ordinal;
-  int32_t count;
-  int32_t pad0;
-  uint64_t key;
-  int32_t pad1[2];
+  float cov[5];  // xx xy xz yy yz (zz is in cov_zz)
 };
-static_assert(sizeof(Payload) == 64, "payload layout");
+static_assert(sizeof(VoxelStats) == 32, "voxel statistics layout");
+
+struct alignas(16) VoxelInfo {
+  uint64_t key;     // packed voxel key
+  int32_t ordinal;  // lexicographic rank of the key
+  int32_t count;    // points in the voxel
+};
+static_assert(sizeof(VoxelInfo) == 16, "voxel info layout");
 
 // ---------------------------------------------------------------- factors
 // Tiles.  A 256-thread block of k_linearize looks up kLookupPasses rows of
@@ -141,7 +147,9 @@ struct FactorDesc {
   const float *xyz;        // [3][n]
   const float *cov;        // [n][6]
   const BrickRecord *bricks;  // target map: brick table
-  const Payload *payload;     // target map: dense voxel payloads
+  const VoxelStats *stats;    // target map: per-voxel mean and covariance but zz
+  const float *cov_zz;        // target map: per-voxel covariance zz
+  const VoxelInfo *info;      // target map: per-voxel key, ordinal, count
   int64_t n;          // source points (at most kMaxCloudPoints)
   int64_t corr_offset;
   int32_t pose_i;
@@ -150,7 +158,7 @@ struct FactorDesc {
   float scale;        // fl32(1/r) of the target map
   int32_t tile_begin; // first tile of this factor in the tile table
   int32_t n_tiles;
-  uint32_t n_voxels;  // target map: payloads
+  uint32_t n_voxels;  // target map: voxels
   uint32_t pad;
 };
 
@@ -200,12 +208,14 @@ struct vgicp_voxelmap_s {
   float scale = 0.f;
   double resolution = 0.0;
   int64_t n_bricks = 0;
-  void *buffer = nullptr;             // one allocation: brick table, then payloads
+  void *buffer = nullptr;             // one allocation: brick table, stats, cov_zz, info
   vgicp::BrickRecord *bricks = nullptr;
-  vgicp::Payload *payload = nullptr;
+  vgicp::VoxelStats *stats = nullptr;
+  float *cov_zz = nullptr;
+  vgicp::VoxelInfo *info = nullptr;
   int64_t device_bytes() const {
     return capacity * int64_t(sizeof(vgicp::BrickRecord)) +
-           n_voxels * int64_t(sizeof(vgicp::Payload));
+           n_voxels * int64_t(sizeof(vgicp::VoxelStats) + sizeof(float) + sizeof(vgicp::VoxelInfo));
   }
 };
 

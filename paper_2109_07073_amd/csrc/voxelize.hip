@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(256)
 k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, int64_t n,
                 const uint32_t *__restrict__ sorted_idx, const uint32_t *__restrict__ seg,
                 const uint32_t *__restrict__ vord, const uint64_t *__restrict__ vkey,
-                int64_t n_voxels, Payload *__restrict__ payload) {
+                int64_t n_voxels, VoxelStats *__restrict__ stats, float *__restrict__ cov_zz,
+                VoxelInfo *__restrict__ info) {
   const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (d >= n_voxels) return;
   const uint32_t v = vord[d];
@@ -147,29 +148,32 @@ k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, in
     for (int a = 0; a < 6; ++a) sc[a] += double(cov[6 * int64_t(p) + a]);
   }
   const double cnt = double(e - b);
-  Payload pl;
+  VoxelStats st;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) pl.mean[a] = float(sm[a] / cnt);
+  for (int a = 0; a < 3; ++a) st.mean[a] = float(sm[a] / cnt);
 #pragma unroll
-  for (int a = 0; a < 6; ++a) pl.cov[a] = float(sc[a] / cnt);
-  pl.ordinal = int32_t(v);
-  pl.count = int32_t(e - b);
-  pl.pad0 = 0;
-  pl.key = vkey[v];
-  pl.pad1[0] = pl.pad1[1] = 0;
-  payload[d] = pl;
+  for (int a = 0; a < 5; ++a) st.cov[a] = float(sc[a] / cnt);
+  stats[d] = st;
+  cov_zz[d] = float(sc[5] / cnt);
+  VoxelInfo in;
+  in.key = vkey[v];
+  in.ordinal = int32_t(v);
+  in.count = int32_t(e - b);
+  info[d] = in;
 }
 
 __global__ void __launch_bounds__(256)
-k_export(const Payload *__restrict__ payload, int64_t n_voxels, int32_t *__restrict__ keys,
-         float *__restrict__ mean, float *__restrict__ cov, int32_t *__restrict__ count) {
+k_export(const VoxelStats *__restrict__ stats, const float *__restrict__ cov_zz,
+         const VoxelInfo *__restrict__ info, int64_t n_voxels, int32_t *__restrict__ keys, float *__restrict__ mean,
+         float *__restrict__ cov, int32_t *__restrict__ count) {
   const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (d >= n_voxels) return;
-  const Payload s = payload[d];
-  const int64_t o = s.ordinal;
+  const VoxelStats s = stats[d];
+  const VoxelInfo in = info[d];
+  const int64_t o = in.ordinal;
   if (keys) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(s.key, a);
+    for (int a = 0; a < 3; ++a) keys[3 * o + a] = key_field(in.key, a);
   }
   if (mean) {
 #pragma unroll
@@ -177,9 +181,10 @@ k_export(const Payload *__restrict__ payload, int64_t n_voxels, int32_t *__restr
   }
   if (cov) {
 #pragma unroll
-    for (int a = 0; a < 6; ++a) cov[6 * o + a] = s.cov[a];
+    for (int a = 0; a < 5; ++a) cov[6 * o + a] = s.cov[a];
+    cov[6 * o + 5] = cov_zz[d];
   }
-  if (count) count[o] = s.count;
+  if (count) count[o] = in.count;
 }
 
 static inline unsigned grid_for(int64_t n, int block = 256) {
@@ -406,10 +411,16 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
   m->scale = s;
   m->resolution = resolution;
   const size_t brick_bytes = align256(size_t(cap) * sizeof(BrickRecord));
-  hipError_t e = hipMalloc(&m->buffer, brick_bytes + size_t(n_voxels) * sizeof(Payload));
+  const size_t stats_bytes = align256(size_t(n_voxels) * sizeof(VoxelStats));
+  const size_t zz_bytes = align256(size_t(n_voxels) * sizeof(float));
+  hipError_t e = hipMalloc(&m->buffer, brick_bytes + stats_bytes + zz_bytes +
+                                           size_t(n_voxels) * sizeof(VoxelInfo));
   if (e == hipSuccess) {
-    m->bricks = static_cast<BrickRecord *>(m->buffer);
-    m->payload = reinterpret_cast<Payload *>(static_cast<char *>(m->buffer) + brick_bytes);
+    char *base = static_cast<char *>(m->buffer);
+    m->bricks = reinterpret_cast<BrickRecord *>(base);
+    m->stats = reinterpret_cast<VoxelStats *>(base + brick_bytes);
+    m->cov_zz = reinterpret_cast<float *>(base + brick_bytes + stats_bytes);
+    m->info = reinterpret_cast<VoxelInfo *>(base + brick_bytes + stats_bytes + zz_bytes);
   }
   if (e != hipSuccess) {
     delete m;
@@ -422,7 +433,7 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
                                                        n_voxels, m->bricks, log2cap);
     k_build_payload<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.idx_out,
                                                         sc.seg, vord_out, vkey, n_voxels,
-                                                        m->payload);
+                                                        m->stats, m->cov_zz, m->info);
   }
   e = hipGetLastError();
   if (e != hipSuccess) {
@@ -438,7 +449,8 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg) {
   if (m->n_voxels == 0) return VGICP_OK;
-  k_export<<<grid_for(m->n_voxels), 256, 0, ctx->stream>>>(m->payload, m->n_voxels, keys, mean,
+  k_export<<<grid_for(m->n_voxels), 256, 0, ctx->stream>>>(m->stats, m->cov_zz, m->info, m->n_voxels, keys,
+                                                           mean,
                                                            cov, count);
   HIP_TRY(hipGetLastError());
   return VGICP_OK;
