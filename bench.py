@@ -41,6 +41,8 @@ WORKLOADS = {
     "serving": dict(cfg=5),
     # local mapping: overlap-gated submaps of fully connected factor graphs (see run_local)
     "local": dict(cfg=6),
+    # precision study: batched4500 plus 450 ill-conditioned factors (see run_precision)
+    "precision": dict(cfg=4),
 }
 
 
@@ -154,6 +156,147 @@ def cpu_baseline(w, cpu_seconds: float = 24.0, workers: int = 1):
               f"linearized by the FP64 numpy oracle, voxel maps included, {workers} processes "
               f"of 1 thread, {wall:.1f} s wall, about {cpu_seconds:.0f} s of CPU work")
     return inl / wall, workers, sample, ids, outs
+
+
+def oracle_all(w, workers: int):
+    """The FP64 oracle over every factor of w (forked processes, no time
+    budget), as {factor: outputs}.  Must run before the GPU is touched.
+    Returns (outputs, correspondences per second, wall seconds)."""
+    import multiprocessing as mp
+    global _CPU_W
+    _CPU_W = w
+    order = np.arange(w.n_factors)
+    jobs = [(k, workers, order, float("inf")) for k in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    outs = {f: o for chunk, _ in res for f, o, _ in chunk}
+    corr = sum(int(o["inliers"]) for o in outs.values())
+    return outs, corr / wall, wall
+
+
+PRECISION_VARIANTS = [
+    # (accumulation, residual, fp64_kappa)
+    ("f32", "f64", 0.0), ("f32_comp", "f64", 0.0), ("f64", "f64", 0.0),
+    ("f32", "f32", 0.0), ("f32", "f64", 1e4), ("f64", "f64", 1e4),
+]
+
+
+def run_precision(args):
+    """Precision study at full size: the batched4500 round (k-NN covariances,
+    spectrum 1, 1, 1e-3, at the perturbed pose estimates) and 450
+    ill-conditioned factors (the first 450 pairs, analytic surface-normal
+    covariances with spectrum 1, 1, 1e-6) at the estimates and at the ground
+    truth.  For each accumulation / residual / FP64-gate variant: max and p99
+    relative Frobenius error of H, b and e over the factors against the FP64
+    oracle (every factor), the fraction of correspondences that took the FP64
+    fused covariance, and the device time of a round (HIP graph replay)."""
+    import copy
+    from synth import make_scan_workload
+    t_gen = time.perf_counter()
+    w = make_scan_workload(cfg=3, n_frames=1000, n_factors=4500, src_range=(5000, 40000),
+                           ill_eps=1e-6)
+    ill = copy.copy(w)
+    ill.sources = w.meta["ill"]["sources"]
+    ill.targets = w.meta["ill"]["targets"]
+    ill.factors = w.factors[:450].copy()
+    ill.meta = {}
+    ill_gt = copy.copy(ill)
+    ill_gt.poses = w.meta["poses_gt"]
+    sets = {"regular": w, "ill": ill, "ill_gt": ill_gt}
+    log(f"[bench] precision workload generated in {time.perf_counter() - t_gen:.1f} s")
+    workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+    refs, cpu_rate, cpu_wall = {}, {}, {}
+    for name, ws in sets.items():
+        refs[name], cpu_rate[name], cpu_wall[name] = oracle_all(ws, workers)
+        log(f"[bench] oracle {name}: {ws.n_factors} factors in {cpu_wall[name]:.1f} s")
+
+    import torch
+    from paper_2109_07073_amd import vgicp as vg
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    stream = torch.cuda.Stream()
+    ctx = vg.Context(0, stream=stream)
+    steps = max(1, min(args.steps, 20))
+    table, default_ms, default_corr = {}, None, None
+    with torch.cuda.stream(stream):
+        for name, ws in sets.items():
+            src, _ = vg.clouds_to_device(ws.sources)
+            tgt, _ = vg.clouds_to_device(ws.targets)
+            used = sorted(set(int(t) for t in ws.factors[:, 1]))
+            maps = [None] * len(tgt)
+            for t in used:
+                maps[t] = vg.voxelize(ctx, *tgt[t], ws.resolution)
+            # unused targets get an empty map (no factor refers to them)
+            empty = vg.voxelize(ctx, torch.zeros((3, 0), device="cuda"),
+                                torch.zeros((0, 6), device="cuda"), ws.resolution)
+            maps = [m if m is not None else empty for m in maps]
+            fs = vg.FactorSet(ctx, src, maps, ws.factors, ws.poses.shape[0],
+                              args.tile or 4608)
+            poses = torch.from_numpy(np.ascontiguousarray(ws.poses)).to("cuda")
+            ref = refs[name]
+            F = ws.n_factors
+            rH = np.stack([ref[f]["H"] for f in range(F)])
+            rb = np.stack([ref[f]["b"] for f in range(F)])
+            re_ = np.array([ref[f]["e"] for f in range(F)])
+            rin = np.array([ref[f]["inliers"] for f in range(F)])
+            for accum, resid, kappa in PRECISION_VARIANTS:
+                kw = dict(accum=accum, resid=resid, fp64_kappa=kappa)
+                out = vg.linearize_factors(ctx, fs, poses, use_graph=True, **kw)
+                for _ in range(3):
+                    vg.linearize_factors(ctx, fs, poses, use_graph=True, out=out, **kw)
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                for _ in range(steps):
+                    vg.linearize_factors(ctx, fs, poses, use_graph=True, out=out, **kw)
+                t1.record(stream)
+                stream.synchronize()
+                ms = t0.elapsed_time(t1) / steps
+                n64 = vg.fp64_points(ctx, fs)
+                H, b = out["H"].cpu().numpy(), out["b"].cpu().numpy()
+                e, inl = out["e"].cpu().numpy(), out["inliers"].cpu().numpy()
+                ok = rin > 0
+                def rel(g, r):
+                    num = np.linalg.norm((g - r).reshape(F, -1)[ok], axis=1)
+                    den = np.linalg.norm(r.reshape(F, -1)[ok], axis=1)
+                    return num / den
+                errs = {"H": rel(H, rH), "b": rel(b, rb), "e": rel(e, re_)}
+                key = f"{accum}/{resid}/{kappa:g}"
+                table.setdefault(key, {})[name] = {
+                    "max_rel_err": {k: float(v.max()) for k, v in errs.items()},
+                    "p99_rel_err": {k: float(np.percentile(v, 99)) for k, v in errs.items()},
+                    "inlier_mismatches": int((inl != rin).sum()),
+                    "fp64_fraction": n64 / max(1, int(rin.sum())),
+                    "ms_per_round": round(ms, 5),
+                }
+                if name == "regular" and (accum, resid, kappa) == PRECISION_VARIANTS[0]:
+                    default_ms, default_corr = ms, int(inl.sum())
+                log(f"[bench] {name:8s} {key:14s} {ms:.3f} ms  max H {errs['H'].max():.2e} "
+                    f"b {errs['b'].max():.2e} e {errs['e'].max():.2e}  FP64 {n64}")
+            del fs, maps, src, tgt
+    total_corr = sum(int(o["inliers"]) for r in refs.values() for o in r.values())
+    total_wall = sum(cpu_wall.values())
+    result = {
+        "metric": "point correspondences linearized/sec (1 GPU); p50/p99 linearization-round latency",
+        "value": default_corr / (default_ms * 1e-3),
+        "unit": "correspondences/s",
+        "n_gpus": 1, "steps": steps, "warmup": 3,
+        "ms_per_step": round(default_ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "precision study: corridor_1000frames_4500factors_r0.5 plus the "
+                               "first 450 pairs with surface-normal covariances (1, 1, 1e-6) "
+                               "at the pose estimates and at the ground truth",
+                   "factors": {k: v.n_factors for k, v in sets.items()},
+                   "tile_points": args.tile or 4608, "seed": [210907073, 3]},
+        "precision": table,
+        "cpu_baseline": {"value": total_corr / total_wall, "unit": "correspondences/s",
+                         "cores": workers, "kind": "oracle",
+                         "sample": f"every factor of the three sets ({sum(len(r) for r in refs.values())} "
+                                   f"factors, {total_corr} correspondences), {workers} processes "
+                                   f"of 1 thread, {total_wall:.1f} s wall"},
+    }
+    print(json.dumps(result))
 
 
 def run_serving(args):
@@ -541,6 +684,9 @@ def main():
         return
     if args.workload == "local":
         run_local(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
         return
     t_gen = time.perf_counter()
     w = build_workload(args.workload)

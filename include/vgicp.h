@@ -225,6 +225,15 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          int64_t *inliers, const int32_t *candidates, int32_t n_candidates,
                          int32_t *best_tile, double *best_ms);
 
+/* Precision diagnostics (the ill-conditioned case of Sec. III-A's fused
+ * covariance C'_k + R C_k R^T): the number of correspondences of the last
+ * vgicp_linearize_factors or vgicp_evaluate_errors call on fs that formed and
+ * inverted the fused covariance in FP64 because of opts.fp64_kappa (0 when that
+ * call had fp64_kappa = 0, and before any call).  Overlap calls do not change
+ * it.  Synchronizes ctx's stream.  n_points: host int64.
+ * Errors: EINVAL (NULL or foreign arguments), EHIP. */
+int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points);
+
 /* Free a factor set and its captured graphs (NULL accepted). */
 int vgicp_factorset_destroy(vgicp_factorset fs);
 

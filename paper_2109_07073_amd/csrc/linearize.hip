@@ -403,7 +403,7 @@ __device__ __forceinline__ double uniform_d(double v) {
 // and the FP64 relative rotation, rounded to FP32.  Used for ill-conditioned
 // points, where forming F' in FP32 already loses the small eigenvalue.
 // Returns false when F' is not positive definite.
-__device__ __noinline__ bool fused_information_fp64(const double R[9], const float S[6],
+__device__ __forceinline__ bool fused_information_fp64(const double R[9], const float S[6],
                                                     const float c[6], float o[6]) {
   const double s0 = S[0], s1 = S[1], s2 = S[2], s3 = S[3], s4 = S[4], s5 = S[5];
   double W[9];
@@ -439,12 +439,13 @@ __device__ __noinline__ bool fused_information_fp64(const double R[9], const flo
 // m - T mu in the target frame, S the voxel covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
 // the cost are added; without it only the cost.  With KAPPA, points whose
 // FP32 fused covariance is not positive definite or has a condition estimate
-// trace^3 / (27 det) above `kappa` take the FP64 fused covariance.
+// trace^3 / (27 det) above `kappa` take the FP64 fused covariance; `nwide`
+// counts them.
 template <bool LIN, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConsts &k,
                                                    float kappa, float mx, float my, float mz,
                                                    const float c[6], const float e[3],
-                                                   const float S[6]) {
+                                                   const float S[6], uint32_t &nwide) {
   // Contraction is off and every fused multiply-add is explicit, so the cost
   // comes out bit-identical in the linearization and the cost-only kernels.
 #pragma clang fp contract(off)
@@ -487,6 +488,7 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
     wide = !pd32 || (tr * tr * tr > (27.0f * kappa) * det);
   }
   if (wide) {
+    ++nwide;
     float o[6];
     if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
     o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
@@ -635,7 +637,7 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
 
 template <bool LIN, bool R64, bool CORR, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
-                                           float kappa, int32_t *pcorr) {
+                                           float kappa, int32_t *pcorr, uint32_t &nwide) {
   if constexpr (CORR) pcorr[B.idx] = B.ord;
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
@@ -650,7 +652,7 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
     e[1] = m[1] - q[1];
     e[2] = m[2] - q[2];
   }
-  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, e, S);
+  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, e, S, nwide);
 }
 
 // Linearization (LIN) or cost evaluation (!LIN) of one tile per block.
@@ -669,7 +671,7 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //           math.
 // The last partial batch runs at the end of the tile.
 template <int ACC, bool LIN, bool R64, bool CORR, bool KAPPA>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F32 ? 4 : 1)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_points,
             const double *__restrict__ poses, double *__restrict__ partials,
@@ -678,6 +680,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   using SumsT = Sums<ACC, N>;
   __shared__ typename SumsT::lds_t lds[kWaves * N];
   __shared__ int lds_cnt[kWaves];
+  __shared__ int lds_wide[kWaves];
   __shared__ HitQueue queues[kWaves];
 
   const int64_t tile = block_tile(tile_base);
@@ -703,6 +706,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   acc.zero();
   uint32_t head = 0, count = 0;  // wave-uniform ring state
   uint32_t hits = 0;             // wave-uniform hit count
+  uint32_t nwide = 0;            // per lane: hits with the FP64 fused covariance
 
   // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead;
   // past the tile's end the loads return zeros and the lanes are invalid).
@@ -774,18 +778,18 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
       } else {
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
       }
       count -= nb * 64;
     }
@@ -795,13 +799,15 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     const bool live = lane < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, rz, ri);
-    if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr);
+    if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
   }
 
   acc.wave_reduce();
+  const int wide = KAPPA ? wave_sum(int(nwide)) : 0;
   if (lane == kLastLane) {
     acc.store(lds, wave);
     lds_cnt[wave] = int(hits);
+    lds_wide[wave] = wide;
   }
   __syncthreads();
   double *__restrict__ out = partials + tile * kPartialStride;
@@ -812,6 +818,11 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += lds_cnt[w];
     out[kNumSums] = double(s);
+  } else if (threadIdx.x == 33) {
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += lds_wide[w];
+    out[kWideSlot] = double(s);
   }
 }
 

@@ -416,6 +416,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   e = hipMalloc(&fs->d_factors, fbytes);
   if (e == hipSuccess) e = hipMalloc(&fs->d_tiles, tbytes);
   if (e == hipSuccess) e = hipMalloc(&fs->d_partials, pbytes);
+  // zeroed so that the FP64-point count reads 0 before the first call
+  if (e == hipSuccess) e = hipMemsetAsync(fs->d_partials, 0, pbytes, ctx->stream);
   if (e == hipSuccess && n_factors > 0)
     e = hipMemcpyAsync(fs->d_factors, fs->h_factors.data(), fs->h_factors.size() * sizeof(FactorDesc),
                        hipMemcpyHostToDevice, ctx->stream);
@@ -473,6 +475,9 @@ int set_tiles(vgicp_ctx ctx, vgicp_factorset fs, int32_t tp, const char *who) {
     e = hipMalloc(&fs->d_tiles, size_t(nt) * sizeof(Tile));
     if (e == hipSuccess)
       e = hipMalloc(&fs->d_partials, size_t(nt) * kPartialStride * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemsetAsync(fs->d_partials, 0, size_t(nt) * kPartialStride * sizeof(double),
+                         ctx->stream);
     if (e == hipSuccess) fs->tiles_capacity = nt;
   }
   if (e == hipSuccess && fs->n_factors > 0)
@@ -794,6 +799,31 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc != VGICP_OK) return rc;
   if (best_tile) *best_tile = best;
   if (best_ms) *best_ms = best_t;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points) {
+  const char *who = "vgicp_factorset_fp64_points";
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  if (!n_points) return fail(ctx, VGICP_EINVAL, std::string(who) + ": n_points is NULL");
+  *n_points = 0;
+  if (fs->n_tiles == 0) return VGICP_OK;
+  // one double per tile partial, strided
+  std::vector<double> col(size_t(fs->n_tiles));
+  hipError_t e = hipMemcpy2DAsync(col.data(), sizeof(double), fs->d_partials + kWideSlot,
+                                  kPartialStride * sizeof(double), sizeof(double),
+                                  size_t(fs->n_tiles), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess)
+    return fail(ctx, VGICP_EHIP, std::string(who) + ": " + hipGetErrorString(e));
+  int64_t total = 0;
+  for (double v : col) total += int64_t(v);
+  *n_points = total;
   return VGICP_OK;
 }
 

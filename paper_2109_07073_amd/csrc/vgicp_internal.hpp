@@ -173,8 +173,11 @@ struct Tile {
 //   [21, 27) source-frame gradient
 //   27       cost
 //   28       inliers
+//   29       inliers whose fused covariance was formed in FP64 (linearize and
+//            cost kernels; 0 without the condition gate)
 constexpr int kPartialStride = 32;
 constexpr int kNumSums = 28;
+constexpr int kWideSlot = 29;
 
 // Error bits of the device error word.
 constexpr uint32_t kErrNonFinite = 1u;

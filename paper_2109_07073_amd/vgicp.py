@@ -92,6 +92,7 @@ _PROTOS = {
     "vgicp_server_last_error": (ctypes.c_char_p, [_vp]),
     "vgicp_server_add_frame": (ctypes.c_int, [_vp, _vp, _vp, _i64, _dbl, _P(_i32)]),
     "vgicp_server_remove_frame": (ctypes.c_int, [_vp, _i32]),
+    "vgicp_factorset_fp64_points": (ctypes.c_int, [_vp, _vp, _P(_i64)]),
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
@@ -493,6 +494,14 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
                                      ctypes.byref(c3), ctypes.byref(d)))
     fs.n_tiles, fs.tile_points = nt.value, d.value
     return best.value, ms.value
+
+
+def fp64_points(ctx: Context, fs: FactorSet) -> int:
+    """Correspondences of the last linearize / evaluate call on `fs` whose
+    fused covariance was formed in FP64 by the fp64_kappa gate (synchronizes)."""
+    n = ctypes.c_int64()
+    _check(_lib.vgicp_factorset_fp64_points(ctx.handle, fs.handle, ctypes.byref(n)), ctx.handle)
+    return n.value
 
 
 def assemble_system(ctx: Context, fs: FactorSet, H, b, out=None, with_offdiag: bool = True):

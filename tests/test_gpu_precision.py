@@ -105,3 +105,35 @@ def test_precision_study(vg, ctx, sets):
         plain = table[(name, "f64", "f64", 0.0)]
         assert max(gated["H"][0], gated["b"][0], gated["e"][0]) <= 1e-5, (name, gated)
         assert gated["H"][0] <= plain["H"][0], (name, plain, gated)
+
+
+def test_fp64_point_count(vg, ctx, sets):
+    """The count of correspondences that took the FP64 fused covariance: 0
+    without the gate and on a fresh factor set, at most the inliers, never
+    larger for a larger threshold, nonzero on the ill-conditioned set at the
+    ground truth, and the same from the cost-only kernel, per-factor launches
+    and overlap calls in between."""
+    w, ref = sets["ill_gt"]
+    g = GpuWorkload(vg, ctx, w)
+    assert vg.fp64_points(ctx, g.fs) == 0
+    g.linearize(fp64_kappa=0.0)
+    assert vg.fp64_points(ctx, g.fs) == 0
+    counts = []
+    for kappa in (1e3, 1e4, 1e5):
+        g.linearize(fp64_kappa=kappa)
+        counts.append(vg.fp64_points(ctx, g.fs))
+    print("FP64 points at kappa 1e3, 1e4, 1e5:", counts, "of", int(ref["inliers"].sum()))
+    assert counts[0] >= counts[1] >= counts[2]
+    assert 0 < counts[1] <= int(ref["inliers"].sum())
+    g.evaluate(fp64_kappa=1e4)
+    assert vg.fp64_points(ctx, g.fs) == counts[1]
+    g.overlap()
+    assert vg.fp64_points(ctx, g.fs) == counts[1]
+    g.linearize(fp64_kappa=1e4, schedule="per_factor")
+    assert vg.fp64_points(ctx, g.fs) == counts[1]
+    # well-conditioned k-NN covariances at the estimates need no FP64 at 1e4
+    # for most points
+    wr, refr = sets["regular"]
+    gr = GpuWorkload(vg, ctx, wr)
+    gr.linearize(fp64_kappa=1e4)
+    assert vg.fp64_points(ctx, gr.fs) < 0.5 * int(refr["inliers"].sum())
