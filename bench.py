@@ -332,6 +332,8 @@ def run_serving(args):
     n_factors = 0
     lat, corr_total, round_time, evictions, overlap_ms = [], 0, 0.0, 0, []
     round_ms, submit_ms = [], []
+    by_size = []                          # (resident keyframes, round ms, correspondences)
+    overlap_by_size = []                  # (resident keyframes, overlap request ms)
     t_start = time.perf_counter()
 
     def pose_rows(Ts):
@@ -383,6 +385,7 @@ def run_serving(args):
             t0 = time.perf_counter()
             ov = srv.submit("overlap", pairs, poses).wait()
             overlap_ms.append((time.perf_counter() - t0) * 1e3)
+            overlap_by_size.append((len(resident), overlap_ms[-1]))
             for (_, old, _, _), o in zip(pairs, ov.overlap):
                 if o >= 0.05:
                     adj[fid].add((fid, old))
@@ -406,9 +409,12 @@ def run_serving(args):
             round_time += t2 - t0
             round_ms.append((t2 - t0) * 1e3)
             submit_ms.append((t1 - t0) * 1e3)
+            corr_round = 0
             for r in done:
                 lat.append(r.latency_ms)
-                corr_total += int(r.inliers.sum())
+                corr_round += int(r.inliers.sum())
+            corr_total += corr_round
+            by_size.append((len(resident), round_ms[-1], corr_round))
         if f % 200 == 0:
             log(f"[serving] keyframe {f}: resident {len(resident)}, factors {n_factors}, "
                 f"global {len(glob)}, local {len(loc)}")
@@ -416,6 +422,23 @@ def run_serving(args):
     st = srv.stats()
     used, budget = srv.memory()
     srv.close()
+    # latency and throughput against the number of resident keyframes
+    bucket = 1000
+    size_table = []
+    for lo in range(0, n, bucket):
+        rs = [(ms, c) for k, ms, c in by_size if lo < k <= lo + bucket]
+        ovs = [ms for k, ms in overlap_by_size if lo < k <= lo + bucket]
+        if not rs:
+            continue
+        ms_r = np.array([a for a, _ in rs])
+        size_table.append({
+            "resident_keyframes": f"{lo + 1}-{lo + bucket}",
+            "round_p50_ms": round(float(np.percentile(ms_r, 50)), 4),
+            "round_p99_ms": round(float(np.percentile(ms_r, 99)), 4),
+            "correspondences_per_s": sum(c for _, c in rs) / (ms_r.sum() * 1e-3),
+            "overlap_request_p50_ms": round(float(np.percentile(ovs, 50)), 4) if ovs else None,
+            "overlap_request_p99_ms": round(float(np.percentile(ovs, 99)), 4) if ovs else None,
+        })
     result = {
         "metric": "point correspondences linearized/sec (1 GPU); p50/p99 linearization-round latency",
         "value": corr_total / round_time,
@@ -445,6 +468,7 @@ def run_serving(args):
                     "max_inflight_batches": st["max_inflight"], "evictions": evictions,
                     "resident_keyframes": len(resident), "factors_admitted": n_factors,
                     "device_bytes_resident": used, "wall_s": round(wall, 2)},
+        "by_map_size": size_table,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -666,7 +690,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="oracle processes for the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--keyframes", type=int, default=2000, help="serving: keyframes streamed")
+    ap.add_argument("--keyframes", type=int, default=4000, help="serving: keyframes streamed")
     ap.add_argument("--frames", type=int, default=600, help="local: frames streamed (10 Hz)")
     ap.add_argument("--window", type=int, default=20, help="serving: global optimizer window")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: memory budget")
