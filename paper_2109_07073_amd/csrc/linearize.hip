@@ -169,11 +169,12 @@ __device__ __forceinline__ uint64_t u64_of(float lo, float hi) {
   return (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32) | __builtin_bit_cast(uint32_t, lo);
 }
 
-// Payload index of the voxel, or -1: the home record's brick, or the records
-// after it up to the first free one (linear probing), must hold the brick,
+// Voxel index of the point, or -1: the home record's brick, or the records
+// after it at the same position of the following lines up to the first free
+// one (linear probing), must hold the brick,
 // and its mask the voxel's bit.  Probing is rare (a home record of another
 // brick), so it runs behind one wave-uniform branch and the common path has
-// no divergent control flow.  At most `capacity` records are visited.
+// no divergent control flow.  At most capacity / 4 records are visited.
 __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const VoxelKey &vk,
                                           const RecordLoad &home) {
   const uint64_t key = (uint64_t(vk.khi) << 32) | vk.klo;
@@ -185,8 +186,8 @@ __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const Voxel
     if (probe) {
       const uint32_t cm = (1u << log2cap) - 1u;
       uint32_t h = vk.h;
-      for (uint32_t p = 0; p < cm; ++p) {
-        h = (h + 1u) & cm;
+      for (uint32_t p = 0; p < (cm >> 2); ++p) {
+        h = (h + kProbeStep) & cm;
         const RecordLoad r = load_record(rb, h);
         const uint64_t k2 = u64_of(r.km.x, r.km.y);
         if (k2 == key) {
@@ -611,7 +612,7 @@ struct Batch {
 // reused while its load is in flight, which forces an early wait.
 template <bool CORR>
 __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t e, bool live,
-                                           Rsrc rc, Rsrc rs, Rsrc rz, Rsrc ri) {
+                                           Rsrc rc, Rsrc rs, Rsrc ri) {
   B.x = Q.x[e];
   B.y = Q.y[e];
   B.z = Q.z[e];
@@ -624,11 +625,12 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   const f32x3 c0 = ld_f32x3<kNT>(rc, co), c1 = ld_f32x3<kNT>(rc, co + 12u);
   B.c[0] = c0.x, B.c[1] = c0.y, B.c[2] = c0.z;
   B.c[3] = c1.x, B.c[4] = c1.y, B.c[5] = c1.z;
-  // the voxel's statistics: a 32-byte record and the zz term
+  // the voxel's statistics: 36 packed bytes
   const uint32_t v = uint32_t(live ? pidx : 0);
-  B.w0 = ld_f32x4(rs, v << 5);
-  B.w1 = ld_f32x4(rs, (v << 5) + 16u);
-  B.czz = ld_f32(rz, v << 2);
+  const uint32_t so = v * 36u;
+  B.w0 = ld_f32x4(rs, so);
+  B.w1 = ld_f32x4(rs, so + 16u);
+  B.czz = ld_f32(rs, so + 32u);
   if constexpr (CORR) B.ord = __builtin_bit_cast(int32_t, ld_f32(ri, (v << 4) + 8u));
   // keep the other batch's math below these loads (hoisting it would make it
   // wait for that batch's loads before these are issued)
@@ -694,8 +696,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
   const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
-  const Rsrc rs = make_rsrc(fd.stats, 32ull * fd.n_voxels);
-  const Rsrc rz = make_rsrc(fd.cov_zz, 4ull * fd.n_voxels);
+  const Rsrc rs = make_rsrc(fd.stats, 36ull * fd.n_voxels);
   const Rsrc ri = make_rsrc(fd.info, 16ull * fd.n_voxels);
   int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset + begin : nullptr;
   const uint32_t lane = threadIdx.x & 63;
@@ -772,19 +773,19 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       // unrolled by two so that the buffers swap roles without copies (a
       // copy would wait for the loads it copies)
       Batch A, B;
-      batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, rz, ri);
+      batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, ri);
       head = ring_add(head, 64);
       uint32_t bi = 1;
       for (; bi + 1 < nb; bi += 2) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
-        batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, rz, ri);
+        batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
       }
       if (bi < nb) {
-        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, rz, ri);
+        batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
         batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
         batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
@@ -798,7 +799,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   if (count > 0) {  // last partial batch: dead lanes add nothing
     const bool live = lane < count;
     Batch A;
-    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, rz, ri);
+    batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, ri);
     if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
   }
 

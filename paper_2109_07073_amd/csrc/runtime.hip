@@ -350,7 +350,6 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     d.cov = c.cov;
     d.bricks = m->bricks;
     d.stats = m->stats;
-    d.cov_zz = m->cov_zz;
     d.info = m->info;
     d.n = c.n;
     d.corr_offset = corr_off;

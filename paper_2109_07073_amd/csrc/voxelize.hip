@@ -114,12 +114,13 @@ k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ 
   const uint64_t key = brick_key_of_sort_key(bsort[d0]);
   const uint32_t cmask = (1u << log2cap) - 1u;
   uint32_t h = brick_slot_of_key(key, log2cap);
-  for (uint32_t probe = 0; probe <= cmask; ++probe) {
+  // the records of one position in the lines: cap / kProbeStep of them
+  for (uint32_t probe = 0; probe <= (cmask >> 2); ++probe) {
     const unsigned long long prev =
         atomicCAS(reinterpret_cast<unsigned long long *>(&bricks[h].key),
                   (unsigned long long)kEmptyKey, (unsigned long long)key);
     if (prev == kEmptyKey) break;
-    h = (h + 1u) & cmask;
+    h = (h + kProbeStep) & cmask;
   }
   bricks[h].mask = mask;
   bricks[h].base = d0;
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256)
 k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, int64_t n,
                 const uint32_t *__restrict__ sorted_idx, const uint32_t *__restrict__ seg,
                 const uint32_t *__restrict__ vord, const uint64_t *__restrict__ vkey,
-                int64_t n_voxels, VoxelStats *__restrict__ stats, float *__restrict__ cov_zz,
+                int64_t n_voxels, VoxelStats *__restrict__ stats,
                 VoxelInfo *__restrict__ info) {
   const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (d >= n_voxels) return;
@@ -152,9 +153,8 @@ k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, in
 #pragma unroll
   for (int a = 0; a < 3; ++a) st.mean[a] = float(sm[a] / cnt);
 #pragma unroll
-  for (int a = 0; a < 5; ++a) st.cov[a] = float(sc[a] / cnt);
+  for (int a = 0; a < 6; ++a) st.cov[a] = float(sc[a] / cnt);
   stats[d] = st;
-  cov_zz[d] = float(sc[5] / cnt);
   VoxelInfo in;
   in.key = vkey[v];
   in.ordinal = int32_t(v);
@@ -163,8 +163,8 @@ k_build_payload(const float *__restrict__ xyz, const float *__restrict__ cov, in
 }
 
 __global__ void __launch_bounds__(256)
-k_export(const VoxelStats *__restrict__ stats, const float *__restrict__ cov_zz,
-         const VoxelInfo *__restrict__ info, int64_t n_voxels, int32_t *__restrict__ keys, float *__restrict__ mean,
+k_export(const VoxelStats *__restrict__ stats, const VoxelInfo *__restrict__ info,
+         int64_t n_voxels, int32_t *__restrict__ keys, float *__restrict__ mean,
          float *__restrict__ cov, int32_t *__restrict__ count) {
   const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (d >= n_voxels) return;
@@ -181,8 +181,7 @@ k_export(const VoxelStats *__restrict__ stats, const float *__restrict__ cov_zz,
   }
   if (cov) {
 #pragma unroll
-    for (int a = 0; a < 5; ++a) cov[6 * o + a] = s.cov[a];
-    cov[6 * o + 5] = cov_zz[d];
+    for (int a = 0; a < 6; ++a) cov[6 * o + a] = s.cov[a];
   }
   if (count) count[o] = in.count;
 }
@@ -412,15 +411,13 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
   m->resolution = resolution;
   const size_t brick_bytes = align256(size_t(cap) * sizeof(BrickRecord));
   const size_t stats_bytes = align256(size_t(n_voxels) * sizeof(VoxelStats));
-  const size_t zz_bytes = align256(size_t(n_voxels) * sizeof(float));
-  hipError_t e = hipMalloc(&m->buffer, brick_bytes + stats_bytes + zz_bytes +
-                                           size_t(n_voxels) * sizeof(VoxelInfo));
+  hipError_t e =
+      hipMalloc(&m->buffer, brick_bytes + stats_bytes + size_t(n_voxels) * sizeof(VoxelInfo));
   if (e == hipSuccess) {
     char *base = static_cast<char *>(m->buffer);
     m->bricks = reinterpret_cast<BrickRecord *>(base);
     m->stats = reinterpret_cast<VoxelStats *>(base + brick_bytes);
-    m->cov_zz = reinterpret_cast<float *>(base + brick_bytes + stats_bytes);
-    m->info = reinterpret_cast<VoxelInfo *>(base + brick_bytes + stats_bytes + zz_bytes);
+    m->info = reinterpret_cast<VoxelInfo *>(base + brick_bytes + stats_bytes);
   }
   if (e != hipSuccess) {
     delete m;
@@ -433,7 +430,7 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
                                                        n_voxels, m->bricks, log2cap);
     k_build_payload<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.idx_out,
                                                         sc.seg, vord_out, vkey, n_voxels,
-                                                        m->stats, m->cov_zz, m->info);
+                                                        m->stats, m->info);
   }
   e = hipGetLastError();
   if (e != hipSuccess) {
@@ -449,7 +446,7 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg) {
   if (m->n_voxels == 0) return VGICP_OK;
-  k_export<<<grid_for(m->n_voxels), 256, 0, ctx->stream>>>(m->stats, m->cov_zz, m->info, m->n_voxels, keys,
+  k_export<<<grid_for(m->n_voxels), 256, 0, ctx->stream>>>(m->stats, m->info, m->n_voxels, keys,
                                                            mean,
                                                            cov, count);
   HIP_TRY(hipGetLastError());
