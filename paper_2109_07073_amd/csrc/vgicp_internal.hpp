@@ -32,11 +32,13 @@ __host__ __device__ inline int32_t key_field(uint64_t key, int which) {
 }
 
 // ---------------------------------------------------------------- bricks
-// Voxels are grouped in bricks of 4 x 4 x 4.  Voxel (kx, ky, kz) is bit
-// (kx & 3) << 4 | (ky & 3) << 2 | (kz & 3) of its brick's 64-bit occupancy
-// mask.  Consecutive points of a scan mostly fall in the same or neighbouring
-// bricks, so their lookups share brick records (and cache lines) instead of
-// scattering over a voxel-keyed table.
+// Voxels are grouped in bricks of 4 x 4 x 4.  A voxel's bit in its brick's
+// 64-bit occupancy mask interleaves the low two bits of its key per axis
+// (x1 y1 z1 x0 y0 z0, Morton order), so the voxels of a 2 x 2 x 2 corner of
+// a brick are consecutive in the dense per-voxel arrays.  Consecutive points
+// of a scan mostly fall in the same or neighbouring bricks, so their lookups
+// share brick records (and cache lines) instead of scattering over a
+// voxel-keyed table.
 //
 // A brick is named by one field per axis, floor(k / 4) + 2^18 + 1, which is
 // in [1, 2^19] for keys in [-2^20, 2^20).  A lookup clamps the scaled
@@ -58,7 +60,8 @@ __host__ __device__ inline uint64_t brick_key(uint32_t fx, uint32_t fy, uint32_t
 }
 
 __host__ __device__ inline uint32_t brick_bit(int32_t kx, int32_t ky, int32_t kz) {
-  return (uint32_t(kx & 3) << 4) | (uint32_t(ky & 3) << 2) | uint32_t(kz & 3);
+  return (uint32_t(kx & 2) << 4) | (uint32_t(ky & 2) << 3) | (uint32_t(kz & 2) << 2) |
+         (uint32_t(kx & 1) << 2) | (uint32_t(ky & 1) << 1) | uint32_t(kz & 1);
 }
 
 // Brick-major sort key of an in-range voxel: the brick fields less one (19
