@@ -63,7 +63,8 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
     """HBM bytes per linearize launch measured by rocprofv3 (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) for this workload, from
     profiles/k_linearize_<workload>.md, or None when there is no profile, the
-    kernel sources have changed since it was taken, or the tile size differs."""
+    kernel sources have changed since it was taken, or no figure was taken at
+    this tile size."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_linearize_{workload}.md")
     if not os.path.exists(path):
@@ -72,7 +73,8 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
     with open(path) as fh:
         for line in fh:
             key, _, val = line.strip().partition(": ")
-            if key in ("traffic_bytes_per_launch", "source_sha256_16", "tile_points"):
+            if key in ("traffic_bytes_per_launch", "source_sha256_16", "tile_points") or \
+                    key.startswith("traffic_bytes_per_launch_at_"):
                 fields[key] = val.strip()
     csrc = os.path.join(ROOT, "paper_2109_07073_amd", "csrc")
     h = hashlib.sha256()
@@ -81,9 +83,10 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
             h.update(fh.read())
     if fields.get("source_sha256_16") != h.hexdigest()[:16]:
         return None
-    if tile_points is not None and fields.get("tile_points") != str(tile_points):
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    if tile_points is None or fields.get("tile_points") == str(tile_points):
+        return float(fields["traffic_bytes_per_launch"])
+    other = fields.get(f"traffic_bytes_per_launch_at_{tile_points}")
+    return float(other) if other is not None else None
 
 
 def distinct_voxels(fs_sizes, corr_t):

@@ -213,7 +213,7 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
  * linearization round): after 10 warm-up rounds, time a linearization round
  * of this factor set at these poses for each candidate tile size (twice, in
  * forward and reverse order, keeping each candidate's best) (host int32 array of multiples of
- * 256 in [256, 2^20]; NULL = 4608, 3072, 2304, 1536, 768, whole lookup phases
+ * 256 in [256, 2^20]; NULL = 9216, 4608, 3072, 2304, 1536, 768, whole lookup phases
  * of a workgroup) and keep the fastest.  H, b, e, inliers are device buffers
  * as for vgicp_linearize_factors, overwritten by the trial rounds.  The
  * factor set's tiles change (results change only by FP32 summation order) and

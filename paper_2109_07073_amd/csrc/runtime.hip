@@ -738,9 +738,9 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc) return rc;
   if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": an output pointer is NULL");
-  static const int32_t kDefaultCandidates[] = {6 * kTileQuantum, 4 * kTileQuantum,
-                                               3 * kTileQuantum, 2 * kTileQuantum,
-                                               kTileQuantum};
+  static const int32_t kDefaultCandidates[] = {12 * kTileQuantum, 6 * kTileQuantum,
+                                               4 * kTileQuantum,  3 * kTileQuantum,
+                                               2 * kTileQuantum,  kTileQuantum};
   if (!candidates) {
     candidates = kDefaultCandidates;
     n_candidates = int32_t(sizeof(kDefaultCandidates) / sizeof(kDefaultCandidates[0]));
