@@ -424,3 +424,33 @@ def test_bad_arguments_raise(vg, ctx, cfg1):
         vg.linearize_factors(ctx, g.fs, g.poses[:1])
     with pytest.raises(vg.VgicpError):       # graph replay needs a side stream
         vg.linearize_factors(ctx, g.fs, g.poses, use_graph=True)
+
+
+@pytest.mark.parametrize("n,extent,r", [(60000, 12.0, 0.25), (200000, 30.0, 0.3),
+                                        (5000, 500.0, 0.5)])
+def test_dense_volumes_every_point_finds_its_voxel(vg, ctx, n, extent, r):
+    """Uniform random volumes (many occupied bricks packed together, so brick
+    records collide and lookups probe): under the identity every point finds
+    its own voxel, and under a random pose the correspondences equal the
+    oracle's, bit for bit."""
+    rng = np.random.default_rng(n)
+    xyz = (rng.random((n, 3)) * extent - extent / 2).astype(np.float32)
+    cov = np.tile(np.array([1, 0, 0, 1, 0, 1], np.float32), (n, 1))
+    vmap, inv = oracle.voxelize(xyz, cov, r)
+    eye = pose_rows(np.eye(4))[0]
+    T = np.eye(4)
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    th = 0.3
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    T[:3, :3] = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K)
+    T[:3, 3] = rng.normal(size=3)
+    poses = np.stack([eye, pose_rows(T)[0]])
+    w = Workload(name="dense", resolution=r, sources=[(xyz, cov)], targets=[(xyz, cov)],
+                 poses=poses, factors=np.array([[0, 0, 0, 0], [0, 0, 1, 0]], np.int32), meta={})
+    got = GpuWorkload(vg, ctx, w).linearize(with_corr=True)
+    corr = got["corr"].reshape(2, n)
+    assert np.array_equal(corr[0], inv.astype(np.int32))
+    R, t = oracle.relative_pose(poses[1], poses[0])
+    assert np.array_equal(corr[1], oracle.lookup(vmap, xyz, R, t).astype(np.int32))
+    assert got["inliers"][0] == n
