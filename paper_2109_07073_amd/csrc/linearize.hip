@@ -6,7 +6,8 @@
 // partial, and a second kernel adds a factor's partials in a fixed order.
 //
 // Per-point work is 3x3 algebra, not a dense contraction, so everything runs
-// on the vector ALUs in FP32; only the final per-factor sums are FP64.
+// on the vector ALUs: FP32 per-point algebra with the residual in FP64, FP64
+// per-factor sums.
 //
 // Source-frame form.  With T = T_j^-1 T_i = (R, t) and the right perturbation
 // of T_i, A_k = R [[mu]x, -I], so A^T Omega A = J'^T Omega' J' with
@@ -26,8 +27,9 @@ constexpr int kWaves = kBlock / 64;
 
 // ---------------------------------------------------------------- poses
 // T_j^-1 T_i in FP64 with a fixed evaluation order and no contraction, and
-// exactly (I, 0) for bitwise-equal poses.  The FP32 rounding of this pose
-// drives the correspondence decision, so its order is part of the contract.
+// exactly (I, 0) for bitwise-equal poses.  The FP32 rounding of this pose,
+// scaled by the map's 1/r, drives the correspondence decision, so its order is
+// part of the contract.
 __device__ __forceinline__ void relative_pose64(const double *__restrict__ pi,
                                                 const double *__restrict__ pj, double R[9],
                                                 double t[3]) {
@@ -81,7 +83,7 @@ typedef float f32x3 __attribute__((ext_vector_type(3)));
 // Clouds and maps are read through raw buffer resources: a uniform base in
 // scalar registers plus a 32-bit byte offset per lane (no 64-bit address
 // arithmetic per lane), and a load at or past the resource's size returns
-// zeros, so the coordinate prefetch past a cloud's last point needs no clamp.
+// zeros, so the coordinate prefetch past a tile's last point needs no clamp.
 // The size limits of clouds and maps keep every offset below 2^32.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, no swizzle
@@ -671,7 +673,9 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //   math:   the full batches of 64 hits, double-buffered: a batch's voxel
 //           and covariance gathers are in flight during the previous batch's
 //           math.
-// The last partial batch runs at the end of the tile.
+// The last partial batch runs at the end of the tile.  FP32 accumulation
+// asks for 4 waves per SIMD (at most 128 VGPRs); the FP64 and compensated
+// accumulators hold twice the registers and keep them.
 template <int ACC, bool LIN, bool R64, bool CORR, bool KAPPA>
 __global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F32 ? 4 : 1)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
