@@ -3,7 +3,8 @@
     python -m paper_2109_07073_amd.build
 
 Every source under csrc/ is compiled to an object with hipcc and the objects
-are linked into paper_2109_07073_amd/libvgicp.so.
+are linked into paper_2109_07073_amd/libvgicp.so; then the plain C client
+tests/c/vgicp_example.c is built against it with gcc.
 """
 
 from __future__ import annotations
@@ -67,7 +68,29 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    build_c_example(verbose)
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(ROOT, "tests", "c", "vgicp_example.c")
+EXAMPLE_BIN = os.path.join(ROOT, "tests", "c", "vgicp_example")
+
+
+def build_c_example(verbose: bool = False) -> str:
+    """A plain C client of the C ABI (gcc, C99, linked against libvgicp.so
+    and the HIP runtime of /opt/rocm), used by the tests."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           EXAMPLE_SRC, "-o", EXAMPLE_BIN, "-L", HERE, "-lvgicp",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           f"-Wl,-rpath,{HERE}", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"C example build failed:\n{res.stdout}\n{res.stderr}")
+    return EXAMPLE_BIN
 
 
 if __name__ == "__main__":
