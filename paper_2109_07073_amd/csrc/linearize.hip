@@ -167,23 +167,48 @@ __device__ __forceinline__ RecordLoad load_record(Rsrc rb, uint32_t h) {
   return r;
 }
 
+// Whether the table's occupancy bitset (staged in LDS) has record h's bit set.
+__device__ __forceinline__ bool home_occupied(const uint32_t *occ, uint32_t occ_mask, uint32_t h) {
+  return (occ[(h & occ_mask) >> 5] >> (h & 31u)) & 1u;
+}
+
+// The home record of a lookup, read only when its bit is set: otherwise the
+// offset lies past the table, so the load returns zeros without a memory
+// request (for a table of the largest size it reads the last record, which
+// the caller ignores).
+__device__ __forceinline__ RecordLoad load_home(Rsrc rb, uint32_t h, bool occupied) {
+  const uint32_t off = occupied ? (h << 5) : 0xffffffe0u;
+  RecordLoad r;
+  r.km = ld_f32x4(rb, off);
+  r.base = __builtin_bit_cast(uint32_t, ld_f32(rb, off + 16u));
+  return r;
+}
+
+// Copies a map's occupancy bitset into LDS (whole block; ends with a barrier).
+__device__ __forceinline__ void stage_occupancy(uint32_t *lds, const uint32_t *__restrict__ occ,
+                                                uint32_t occ_mask) {
+  const uint32_t words = (occ_mask + 1u) >> 5;
+  for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) lds[w] = occ[w];
+  __syncthreads();
+}
+
 __device__ __forceinline__ uint64_t u64_of(float lo, float hi) {
   return (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32) | __builtin_bit_cast(uint32_t, lo);
 }
 
-// Voxel index of the point, or -1: the home record's brick, or the records
-// after it at the same position of the following lines up to the first free
-// one (linear probing), must hold the brick,
+// Voxel index of the point, or -1: the home record (unless its occupancy bit
+// is clear), or the records after it at the same position of the following
+// lines up to the first free one (linear probing), must hold the brick,
 // and its mask the voxel's bit.  Probing is rare (a home record of another
 // brick), so it runs behind one wave-uniform branch and the common path has
 // no divergent control flow.  At most capacity / 4 records are visited.
 __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const VoxelKey &vk,
-                                          const RecordLoad &home) {
+                                          const RecordLoad &home, bool occupied) {
   const uint64_t key = (uint64_t(vk.khi) << 32) | vk.klo;
   uint64_t rkey = u64_of(home.km.x, home.km.y);
   uint64_t mask = u64_of(home.km.z, home.km.w);
   uint32_t base = home.base;
-  const bool probe = rkey != key && rkey != kEmptyKey;
+  const bool probe = occupied && rkey != key && rkey != kEmptyKey;
   if (__ballot(probe) != 0) {
     if (probe) {
       const uint32_t cm = (1u << log2cap) - 1u;
@@ -205,7 +230,7 @@ __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const Voxel
     // stay exact
     __builtin_amdgcn_s_waitcnt(0);
   }
-  if (rkey != key || !((mask >> vk.bit) & 1ull)) return -1;
+  if (!occupied || rkey != key || !((mask >> vk.bit) & 1ull)) return -1;
   return int(base + uint32_t(__popcll(mask & ((1ull << vk.bit) - 1ull))));
 }
 
@@ -688,11 +713,13 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   __shared__ int lds_cnt[kWaves];
   __shared__ int lds_wide[kWaves];
   __shared__ HitQueue queues[kWaves];
+  __shared__ uint32_t occ_lds[kOccMaxBits / 32];
 
   const int64_t tile = block_tile(tile_base);
   if (tile >= tile_end) return;
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
+  stage_occupancy(occ_lds, fd.occ, fd.occ_mask);
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
@@ -728,14 +755,16 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     // in flight.
     VoxelKey vk[kChunk];
     RecordLoad rec[kChunk];
+    bool occ[kChunk];
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
       float v[3];
       lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
       vk[p] = voxel_key(v, fd.log2cap);
+      occ[p] = home_occupied(occ_lds, fd.occ_mask, vk[p].h);
     }
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) rec[p] = load_record(rb, vk[p].h);
+    for (int p = 0; p < kChunk; ++p) rec[p] = load_home(rb, vk[p].h, occ[p]);
     __builtin_amdgcn_sched_barrier(0);
     float nxt[kChunk][3];
 #pragma unroll
@@ -745,7 +774,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
       const uint32_t i = base + p * kBlock + lane;
-      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p]);
+      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p], occ[p]);
       const int h = i < end ? hs : -1;
       if constexpr (CORR) {
         if (i < end && h < 0) pcorr[i - begin] = -1;
@@ -837,10 +866,12 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
           int64_t tile_base, int64_t tile_end, int32_t tile_points,
           const double *__restrict__ poses, double *__restrict__ partials) {
   __shared__ int lds_cnt[kWaves];
+  __shared__ uint32_t occ_lds[kOccMaxBits / 32];
   const int64_t tile = block_tile(tile_base);
   if (tile >= tile_end) return;
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
+  stage_occupancy(occ_lds, fd.occ, fd.occ_mask);
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
@@ -858,14 +889,16 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   for (; base < end; base += kOvlChunk * kBlock) {
     VoxelKey vk[kOvlChunk];
     RecordLoad rec[kOvlChunk];
+    bool occ[kOvlChunk];
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p) {
       float v[3];
       lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
       vk[p] = voxel_key(v, fd.log2cap);
+      occ[p] = home_occupied(occ_lds, fd.occ_mask, vk[p].h);
     }
 #pragma unroll
-    for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_record(rb, vk[p].h);
+    for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_home(rb, vk[p].h, occ[p]);
     __builtin_amdgcn_sched_barrier(0);
     float nxt[kOvlChunk][3];
 #pragma unroll
@@ -875,7 +908,7 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p) {
       const bool valid = base + p * kBlock + lane < end;
-      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p]);
+      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p], occ[p]);
       hits += (valid && hs >= 0) ? 1 : 0;
     }
 #pragma unroll

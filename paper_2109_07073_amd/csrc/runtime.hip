@@ -350,6 +350,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     d.cov = c.cov;
     d.bricks = m->bricks;
     d.stats = m->stats;
+    d.occ = m->occ;
+    d.occ_mask = occ_bits(m->capacity) - 1u;
     d.info = m->info;
     d.n = c.n;
     d.corr_offset = corr_off;

@@ -245,6 +245,8 @@ void launch_batch(vgicp_server srv, size_t si) {
       d.cov = src.cloud + src.cov_offset;
       d.bricks = tgt.map->bricks;
       d.stats = tgt.map->stats;
+      d.occ = tgt.map->occ;
+      d.occ_mask = occ_bits(tgt.map->capacity) - 1u;
       d.info = tgt.map->info;
       d.n = src.n;
       d.pose_i = int32_t(pose_base + x.pose_i);

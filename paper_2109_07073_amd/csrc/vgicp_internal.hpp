@@ -102,6 +102,17 @@ __host__ __device__ inline uint32_t brick_slot_of_key(uint64_t bkey, uint32_t lo
                     uint32_t(bkey) & m, log2cap);
 }
 
+// Occupancy bitset of a map's brick table: bit (h mod B) is set when record h
+// holds a brick, B = min(cap, kOccMaxBits) (at least 32).  A lookup whose home
+// record's bit is clear misses without reading the record (linear probing
+// never passes an empty record); a table larger than kOccMaxBits folds its
+// slots onto the bits, which only lets some lookups read their record.
+constexpr uint32_t kOccMaxBits = 1u << 16;  // 8 KB, staged in LDS per block
+
+__host__ __device__ inline uint32_t occ_bits(int64_t cap) {
+  return cap < 32 ? 32u : (cap > int64_t(kOccMaxBits) ? kOccMaxBits : uint32_t(cap));
+}
+
 // Size limits that keep every byte offset of a cloud or map within 32 bits
 // (the kernels address them through buffer resources).
 constexpr int64_t kMaxCloudPoints = int64_t(1) << 26;
@@ -164,6 +175,8 @@ struct FactorDesc {
   int32_t tile_begin; // first tile of this factor in the tile table
   int32_t n_tiles;
   uint32_t n_voxels;  // target map: voxels
+  const uint32_t *occ;  // target map: occupancy bitset of the brick table
+  uint32_t occ_mask;    // occ_bits(cap) - 1
   uint32_t pad;
 };
 
@@ -218,10 +231,11 @@ struct vgicp_voxelmap_s {
   int64_t n_bricks = 0;
   void *buffer = nullptr;             // one allocation: brick table, stats, info
   vgicp::BrickRecord *bricks = nullptr;
+  uint32_t *occ = nullptr;  // occupancy bitset, occ_bits(capacity) bits
   vgicp::VoxelStats *stats = nullptr;
   vgicp::VoxelInfo *info = nullptr;
   int64_t device_bytes() const {
-    return capacity * int64_t(sizeof(vgicp::BrickRecord)) +
+    return capacity * int64_t(sizeof(vgicp::BrickRecord)) + int64_t(vgicp::occ_bits(capacity) / 8) +
            n_voxels * int64_t(sizeof(vgicp::VoxelStats) + sizeof(vgicp::VoxelInfo));
   }
 };

@@ -65,7 +65,8 @@ k_segment_starts(const uint32_t *__restrict__ head, const uint32_t *__restrict__
 }
 
 __global__ void __launch_bounds__(256)
-k_fill_empty(BrickRecord *__restrict__ bricks, int64_t cap) {
+k_fill_empty(BrickRecord *__restrict__ bricks, int64_t cap, uint32_t *__restrict__ occ,
+             uint32_t occ_words) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < cap) {
     BrickRecord r;
@@ -75,6 +76,7 @@ k_fill_empty(BrickRecord *__restrict__ bricks, int64_t cap) {
     r.pad[0] = r.pad[1] = r.pad[2] = 0;
     bricks[i] = r;
   }
+  if (i < int64_t(occ_words)) occ[i] = 0u;
 }
 
 // Per voxel (in lexicographic order): its packed key and its brick-major sort
@@ -104,7 +106,7 @@ k_brick_heads(const uint64_t *__restrict__ bsort, int64_t n_voxels, uint32_t *__
 __global__ void __launch_bounds__(256)
 k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ bstart,
                int64_t n_bricks, int64_t n_voxels, BrickRecord *__restrict__ bricks,
-               uint32_t log2cap) {
+               uint32_t log2cap, uint32_t *__restrict__ occ, uint32_t occ_mask) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= n_bricks) return;
   const uint32_t d0 = bstart[b];
@@ -124,6 +126,8 @@ k_build_bricks(const uint64_t *__restrict__ bsort, const uint32_t *__restrict__ 
   }
   bricks[h].mask = mask;
   bricks[h].base = d0;
+  const uint32_t bit = h & occ_mask;
+  atomicOr(&occ[bit >> 5], 1u << (bit & 31u));
 }
 
 // One thread per voxel, by dense (brick-major) position d: sequential FP64
@@ -410,24 +414,29 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
   m->scale = s;
   m->resolution = resolution;
   const size_t brick_bytes = align256(size_t(cap) * sizeof(BrickRecord));
+  const uint32_t obits = occ_bits(cap);
+  const size_t occ_bytes = align256(size_t(obits / 8));
   const size_t stats_bytes = align256(size_t(n_voxels) * sizeof(VoxelStats));
-  hipError_t e =
-      hipMalloc(&m->buffer, brick_bytes + stats_bytes + size_t(n_voxels) * sizeof(VoxelInfo));
+  hipError_t e = hipMalloc(&m->buffer, brick_bytes + occ_bytes + stats_bytes +
+                                           size_t(n_voxels) * sizeof(VoxelInfo));
   if (e == hipSuccess) {
     char *base = static_cast<char *>(m->buffer);
     m->bricks = reinterpret_cast<BrickRecord *>(base);
-    m->stats = reinterpret_cast<VoxelStats *>(base + brick_bytes);
-    m->info = reinterpret_cast<VoxelInfo *>(base + brick_bytes + stats_bytes);
+    m->occ = reinterpret_cast<uint32_t *>(base + brick_bytes);
+    m->stats = reinterpret_cast<VoxelStats *>(base + brick_bytes + occ_bytes);
+    m->info = reinterpret_cast<VoxelInfo *>(base + brick_bytes + occ_bytes + stats_bytes);
   }
   if (e != hipSuccess) {
     delete m;
     msg = std::string("vgicp_voxelize: hipMalloc of the voxel map: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP;
   }
-  k_fill_empty<<<grid_for(cap), 256, 0, st>>>(m->bricks, cap);
+  k_fill_empty<<<grid_for(std::max<int64_t>(cap, obits / 32)), 256, 0, st>>>(
+      m->bricks, cap, m->occ, obits / 32);
   if (n_voxels > 0) {
     k_build_bricks<<<grid_for(n_bricks), 256, 0, st>>>(sc.bsort_out, sc.bstart, n_bricks,
-                                                       n_voxels, m->bricks, log2cap);
+                                                       n_voxels, m->bricks, log2cap, m->occ,
+                                                       obits - 1);
     k_build_payload<<<grid_for(n_voxels), 256, 0, st>>>(cloud->xyz, cloud->cov, n, sc.idx_out,
                                                         sc.seg, vord_out, vkey, n_voxels,
                                                         m->stats, m->info);

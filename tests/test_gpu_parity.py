@@ -73,16 +73,16 @@ def test_voxelize_bitexact(vg, ctx, ragged, r):
         ref, _ = oracle.voxelize(xyz, cov, r)
         assert m.n_voxels == ref.n_voxels
         # brick table: the smallest power of two >= max(16, 8 * bricks), the
-        # bricks being the distinct floor(key / 4); 32-byte records plus 52
-        # bytes per voxel (32-byte statistics record, the zz term, 16 bytes of
-        # key, ordinal and count)
+        # bricks being the distinct floor(key / 4); 32-byte records, an
+        # occupancy bitset of min(cap, 2^16) bits (at least 32), plus 52 bytes
+        # per voxel (36 bytes of statistics, 16 of key, ordinal and count)
         n_bricks = (np.unique(np.floor_divide(ref.keys, 4), axis=0).shape[0]
                     if ref.n_voxels else 0)
         cap = 16
         while cap < 8 * n_bricks:
             cap *= 2
         assert m.capacity == cap
-        assert m.device_bytes == 32 * cap + 52 * m.n_voxels
+        assert m.device_bytes == 32 * cap + max(32, min(cap, 1 << 16)) // 8 + 52 * m.n_voxels
         got = _export_np(m)
         assert np.array_equal(got["keys"], ref.keys.astype(np.int32))
         assert np.array_equal(got["count"], ref.count.astype(np.int32))
