@@ -189,7 +189,13 @@ int vgicp_map_free(vgicp_map map);
  * ------------------------------------------------------------------------ */
 
 /* sources: host array of n_sources cloud descriptors (device data, caller
- * owned, must outlive the factor set); maps: host array of n_maps handles;
+ * owned, read during this call only): the factor set keeps its own copy of
+ * every source cloud a factor uses, its points in Morton order of cells of the
+ * finest resolution among the maps that cloud is matched against, so that
+ * neighbouring points of a wave look up neighbouring voxels (40 bytes of
+ * device memory per point; results differ from the caller's order only by
+ * FP32 summation order, and per-point outputs keep the caller's order);
+ * maps: host array of n_maps handles (they must outlive the factor set);
  * factors: host array of n_factors rows; n_poses: length of the pose arrays
  * later calls pass; tile_points: source points per workgroup tile, a multiple
  * of 256 in [256, 1<<20], or 0 for automatic: the first of 4608, 3072, 2304,

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvgicp.so")
 ARCH = os.environ.get("VGICP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip"]
+SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip", "reorder.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

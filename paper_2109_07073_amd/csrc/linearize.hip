@@ -664,10 +664,28 @@ __device__ __forceinline__ void batch_load(Batch &B, const HitQueue &Q, uint32_t
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Per-point correspondence output of one tile: the value of the tile's point
+// `local` goes to the caller's index of that point (through the factor's
+// permutation when its source is a reordered copy).
+struct CorrOut {
+  int32_t *base;        // corr + corr_offset (+ tile begin without a permutation)
+  const int32_t *perm;  // permutation from the tile's first point, or NULL
+  __device__ __forceinline__ void put(uint32_t local, int32_t v) const {
+    base[perm ? uint32_t(perm[local]) : local] = v;
+  }
+};
+
+template <bool CORR>
+__device__ __forceinline__ CorrOut corr_out(int32_t *corr, const FactorDesc &fd, uint32_t begin) {
+  if constexpr (!CORR) return {nullptr, nullptr};
+  if (fd.perm) return {corr + fd.corr_offset, fd.perm + begin};
+  return {corr + fd.corr_offset + begin, nullptr};
+}
+
 template <bool LIN, bool R64, bool CORR, bool KAPPA, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
-                                           float kappa, int32_t *pcorr, uint32_t &nwide) {
-  if constexpr (CORR) pcorr[B.idx] = B.ord;
+                                           float kappa, const CorrOut &pcorr, uint32_t &nwide) {
+  if constexpr (CORR) pcorr.put(uint32_t(B.idx), B.ord);
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
   float e[3];
@@ -729,7 +747,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const Rsrc rs = make_rsrc(fd.stats, 36ull * fd.n_voxels);
   const Rsrc ri = make_rsrc(fd.info, 16ull * fd.n_voxels);
-  int32_t *__restrict__ pcorr = CORR ? corr + fd.corr_offset + begin : nullptr;
+  const CorrOut pcorr = corr_out<CORR>(corr, fd, begin);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = threadIdx.x >> 6;
   HitQueue &Q = queues[wave];
@@ -777,7 +795,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p], occ[p]);
       const int h = i < end ? hs : -1;
       if constexpr (CORR) {
-        if (i < end && h < 0) pcorr[i - begin] = -1;
+        if (i < end && h < 0) pcorr.put(i - begin, -1);
       }
       const uint64_t mask = __ballot(h >= 0);
       if (h >= 0) {

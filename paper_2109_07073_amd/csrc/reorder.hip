@@ -1,0 +1,162 @@
+// Resident, spatially ordered copies of the source clouds of a factor set.
+//
+// A linearization round streams every source point once and gathers the
+// target voxel of each (Sec. III-A).  Consecutive points of a scan in its
+// recorded order can lie far apart (a ring of a rotating sensor, thinned),
+// so the 64 lanes of a wave touch many brick records and voxel statistics
+// lines.  A factor set therefore keeps its own copy of each source cloud with
+// the points in Morton order of cells at the finest resolution among the maps
+// the cloud is matched against: neighbours in memory are neighbours in space,
+// and a rigid transform keeps them neighbours in the target map.  The copy is
+// made once; every round reads it instead of the caller's arrays.  Per-point
+// outputs are written at the caller's index through the stored permutation.
+// The results are the same up to FP32 summation order (integer outputs are
+// identical).
+
+#include "vgicp_internal.hpp"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+namespace vgicp {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr float kCellLo = -1048576.0f;  // -2^20
+constexpr float kCellHi = 1048575.0f;   //  2^20 - 1
+
+// Cell index on one axis, offset to [0, 2^21); NaN and out-of-range values
+// clamp to the ends (any order of such points is valid).
+__device__ __forceinline__ uint32_t cell21(float x, float inv_cell) {
+  const float q = fminf(fmaxf(floorf(x * inv_cell), kCellLo), kCellHi);
+  return uint32_t(int32_t(q) + 1048576);
+}
+
+// The 21 low bits of v moved to every third bit (bit k to bit 3k).
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// Morton key (63 bits, x most significant within each bit triple) and the
+// point's own index of every point of one cloud.
+__global__ void __launch_bounds__(kThreads)
+k_morton_keys(const float *__restrict__ xyz, uint32_t n, float inv_cell,
+              uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t cx = cell21(xyz[i], inv_cell);
+  const uint32_t cy = cell21(xyz[uint64_t(n) + i], inv_cell);
+  const uint32_t cz = cell21(xyz[2ull * n + i], inv_cell);
+  keys[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+  idx[i] = i;
+}
+
+// Copy point perm[i] of the cloud to position i of the ordered copy
+// (coordinates as three planes, covariances as six floats per point).
+__global__ void __launch_bounds__(kThreads)
+k_gather_points(const float *__restrict__ xyz, const float *__restrict__ cov, uint32_t n,
+                const int32_t *__restrict__ perm, float *__restrict__ xyz_out,
+                float *__restrict__ cov_out) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t j = uint32_t(perm[i]);
+  xyz_out[i] = xyz[j];
+  xyz_out[uint64_t(n) + i] = xyz[uint64_t(n) + j];
+  xyz_out[2ull * n + i] = xyz[2ull * n + j];
+  const float2 *src = reinterpret_cast<const float2 *>(cov + 6 * j);
+  float2 *dst = reinterpret_cast<float2 *>(cov_out + 6ull * i);
+  dst[0] = src[0];
+  dst[1] = src[1];
+  dst[2] = src[2];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
+                               const std::vector<double> &cell, void **buffer,
+                               std::vector<SortedSource> &out, hipStream_t st) {
+  *buffer = nullptr;
+  out.assign(size_t(n_sources), SortedSource{});
+  // layout: per used cloud, covariances [n][6], coordinates [3][n], permutation [n]
+  size_t total = 0;
+  uint32_t nmax = 0;
+  std::vector<size_t> off(size_t(n_sources), 0);
+  for (int32_t s = 0; s < n_sources; ++s) {
+    const int64_t n = sources[s].n;
+    if (!(cell[size_t(s)] > 0.0) || n <= 0) continue;
+    off[size_t(s)] = total;
+    total += align256(24 * size_t(n)) + align256(12 * size_t(n)) + align256(4 * size_t(n));
+    nmax = std::max(nmax, uint32_t(n));
+  }
+  if (total == 0) return hipSuccess;
+
+  size_t sort_bytes = 0;
+  for (int32_t s = 0; s < n_sources; ++s) {
+    if (!(cell[size_t(s)] > 0.0) || sources[s].n <= 0) continue;
+    size_t b = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, b, static_cast<const uint64_t *>(nullptr),
+                                             static_cast<uint64_t *>(nullptr),
+                                             static_cast<const uint32_t *>(nullptr),
+                                             static_cast<uint32_t *>(nullptr),
+                                             uint32_t(sources[s].n), 0, 63, st);
+    if (e != hipSuccess) return e;
+    sort_bytes = std::max(sort_bytes, b);
+  }
+  const size_t kbytes = align256(8 * size_t(nmax));
+  const size_t ibytes = align256(4 * size_t(nmax));
+  char *tmp = nullptr;
+  hipError_t e = hipMalloc(buffer, total);
+  if (e == hipSuccess) e = hipMalloc(&tmp, 2 * kbytes + ibytes + align256(sort_bytes));
+  if (e != hipSuccess) {
+    if (*buffer) (void)hipFree(*buffer);
+    *buffer = nullptr;
+    return e;
+  }
+  uint64_t *keys_in = reinterpret_cast<uint64_t *>(tmp);
+  uint64_t *keys_out = reinterpret_cast<uint64_t *>(tmp + kbytes);
+  uint32_t *idx_in = reinterpret_cast<uint32_t *>(tmp + 2 * kbytes);
+  void *sort_tmp = tmp + 2 * kbytes + ibytes;
+
+  char *base = static_cast<char *>(*buffer);
+  for (int32_t s = 0; s < n_sources && e == hipSuccess; ++s) {
+    const vgicp_cloud &c = sources[s];
+    if (!(cell[size_t(s)] > 0.0) || c.n <= 0) continue;
+    const uint32_t n = uint32_t(c.n);
+    char *p = base + off[size_t(s)];
+    float *cov_s = reinterpret_cast<float *>(p);
+    float *xyz_s = reinterpret_cast<float *>(p + align256(24 * size_t(n)));
+    int32_t *perm = reinterpret_cast<int32_t *>(p + align256(24 * size_t(n)) + align256(12 * size_t(n)));
+    const uint32_t grid = (n + kThreads - 1) / kThreads;
+    k_morton_keys<<<grid, kThreads, 0, st>>>(c.xyz, n, float(1.0 / cell[size_t(s)]), keys_in, idx_in);
+    e = hipGetLastError();
+    size_t b = align256(sort_bytes);
+    if (e == hipSuccess)
+      e = rocprim::radix_sort_pairs(sort_tmp, b, keys_in, keys_out, idx_in,
+                                    reinterpret_cast<uint32_t *>(perm), n, 0, 63, st);
+    if (e == hipSuccess) {
+      k_gather_points<<<grid, kThreads, 0, st>>>(c.xyz, c.cov, n, perm, xyz_s, cov_s);
+      e = hipGetLastError();
+    }
+    out[size_t(s)] = SortedSource{xyz_s, cov_s, perm};
+  }
+  // the temporaries are reused cloud after cloud on the stream; free them
+  // once the last gather has run
+  const hipError_t se = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = se;
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    (void)hipFree(*buffer);
+    *buffer = nullptr;
+    out.assign(size_t(n_sources), SortedSource{});
+  }
+  return e;
+}
+
+}  // namespace vgicp

@@ -332,6 +332,24 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   fs->tile_points = tile_points;
   fs->h_factors.resize(size_t(n_factors));
 
+  // Ordered copies of the source clouds that factors use, in cells of the
+  // finest resolution among the maps each cloud is matched against.
+  std::vector<SortedSource> sorted;
+  {
+    std::vector<double> cell(size_t(n_sources), 0.0);
+    for (int64_t f = 0; f < n_factors; ++f) {
+      double &c = cell[size_t(factors[f].src)];
+      const double r = maps[factors[f].tgt]->resolution;
+      c = (c == 0.0) ? r : std::min(c, r);
+    }
+    const hipError_t se =
+        make_sorted_sources(sources, n_sources, cell, &fs->d_sorted, sorted, ctx->stream);
+    if (se != hipSuccess) {
+      vgicp_factorset_destroy(fs);
+      return hip_fail(ctx, "vgicp_factorset_create", se);
+    }
+  }
+
   // Tile order: factors grouped by target map so that consecutive tiles (and
   // therefore one XCD's share of the grid) reuse the same hash table.
   std::vector<int64_t> order(static_cast<size_t>(n_factors));
@@ -346,8 +364,10 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     std::memset(&d, 0, sizeof(d));
     const vgicp_cloud &c = sources[x.src];
     const vgicp_voxelmap_s *m = maps[x.tgt];
-    d.xyz = c.xyz;
-    d.cov = c.cov;
+    const SortedSource &ss = sorted[size_t(x.src)];
+    d.xyz = ss.xyz ? ss.xyz : c.xyz;
+    d.cov = ss.xyz ? ss.cov : c.cov;
+    d.perm = ss.perm;
     d.bricks = m->bricks;
     d.stats = m->stats;
     d.occ = m->occ;
@@ -519,6 +539,7 @@ int vgicp_factorset_destroy(vgicp_factorset fs) {
   if (fs->d_factors) (void)hipFree(fs->d_factors);
   if (fs->d_tiles) (void)hipFree(fs->d_tiles);
   if (fs->d_partials) (void)hipFree(fs->d_partials);
+  if (fs->d_sorted) (void)hipFree(fs->d_sorted);
   for (int64_t *p : {fs->d_pose_off, fs->d_pose_ent, fs->d_pair_off, fs->d_pair_ent})
     if (p) (void)hipFree(p);
   delete fs;

@@ -566,6 +566,33 @@ int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_
       rc = VGICP_EHIP;
       msg = "vgicp_server_add_frame: voxelization failed";
     }
+    // Then the frame's points are put in Morton order of cells of its own
+    // resolution (the order a factor set gives a cloud matched against maps of
+    // that resolution), so that its rounds read neighbouring voxels together.
+    // Requests have no per-point outputs, so the permutation is not kept.
+    if (rc == VGICP_OK && n > 0) {
+      const std::vector<double> cell{resolution};
+      std::vector<SortedSource> ss;
+      void *buf = nullptr;
+      hipStream_t st = srv->ingest.stream;
+      hipError_t se = make_sorted_sources(&c, 1, cell, &buf, ss, st);
+      if (se == hipSuccess && buf) {
+        se = hipMemcpyAsync(fr.cloud, ss[0].xyz, size_t(3 * n) * sizeof(float),
+                            hipMemcpyDeviceToDevice, st);
+        if (se == hipSuccess)
+          se = hipMemcpyAsync(fr.cloud + fr.cov_offset, ss[0].cov, size_t(6 * n) * sizeof(float),
+                              hipMemcpyDeviceToDevice, st);
+        const hipError_t ye = hipStreamSynchronize(st);
+        if (se == hipSuccess) se = ye;
+      }
+      if (buf) (void)hipFree(buf);
+      if (se != hipSuccess) {
+        vgicp_map_free(fr.map);
+        fr.map = nullptr;
+        rc = se == hipErrorOutOfMemory ? VGICP_ENOMEM : VGICP_EHIP;
+        msg = std::string("vgicp_server_add_frame: ") + hipGetErrorString(se);
+      }
+    }
   }
   if (rc != VGICP_OK) {
     (void)hipFree(fr.cloud);

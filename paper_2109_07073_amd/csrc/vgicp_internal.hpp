@@ -178,7 +178,26 @@ struct FactorDesc {
   const uint32_t *occ;  // target map: occupancy bitset of the brick table
   uint32_t occ_mask;    // occ_bits(cap) - 1
   uint32_t pad;
+  // Caller's index of each source point when xyz/cov are a reordered copy of
+  // the caller's cloud (per-point outputs are written at it); NULL when the
+  // points are in the caller's order.
+  const int32_t *perm;
 };
+
+// A factor set's ordered copy of one source cloud (Morton order of cells),
+// with the caller's index of each point.
+struct SortedSource {
+  const float *xyz = nullptr;   // [3][n]
+  const float *cov = nullptr;   // [n][6]
+  const int32_t *perm = nullptr;  // [n]
+};
+
+// Ordered copies of the clouds s with cell[s] > 0 and n > 0, in one device
+// allocation returned in *buffer (NULL when there is none); out[s] points into
+// it.  Enqueued on st and synchronized before returning.
+hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
+                               const std::vector<double> &cell, void **buffer,
+                               std::vector<SortedSource> &out, hipStream_t st);
 
 // One tile: `count` source points of factor `factor` starting at `start`.
 struct Tile {
@@ -265,6 +284,7 @@ struct vgicp_factorset_s {
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
   std::vector<vgicp::FactorDesc> h_factors;
   std::vector<int64_t> tile_order;  // factors in tile order (grouped by target map)
+  void *d_sorted = nullptr;  // device: ordered copies of the source clouds
   int64_t tiles_capacity = 0;       // tiles d_tiles and d_partials have room for
   std::vector<GraphEntry> graphs;
   // System assembly: contributions to each pose (CSR over poses, entries are
