@@ -78,7 +78,7 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
                 fields[key] = val.strip()
     csrc = os.path.join(ROOT, "paper_2109_07073_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("linearize.hip", "voxelize.hip", "vgicp_internal.hpp"):
+    for f in ("linearize.hip", "voxelize.hip", "vgicp_internal.hpp", "reorder.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256_16") != h.hexdigest()[:16]:
