@@ -454,3 +454,43 @@ def test_dense_volumes_every_point_finds_its_voxel(vg, ctx, n, extent, r):
     R, t = oracle.relative_pose(poses[1], poses[0])
     assert np.array_equal(corr[1], oracle.lookup(vmap, xyz, R, t).astype(np.int32))
     assert got["inliers"][0] == n
+
+
+# ----------------------------------------------------- factor-set source copies
+
+def test_factor_set_reads_the_caller_clouds_only_at_creation(vg, ctx, scans):
+    """A factor set keeps its own (spatially ordered) copy of every source
+    cloud: overwriting the caller's arrays afterwards changes no output."""
+    import torch
+    g = GpuWorkload(vg, ctx, scans)
+    before = g.linearize(with_corr=True)
+    for (x, c) in g.src:
+        x.fill_(float("nan"))
+        c.fill_(float("nan"))
+    torch.cuda.synchronize()
+    after = g.linearize(with_corr=True)
+    for k in ("H", "b", "e", "inliers", "corr"):
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_point_order_changes_only_the_summation_order(vg, ctx, scans):
+    """Shuffling the points of every source cloud leaves the correspondences
+    (which follow their points) and the inlier counts identical, and H, b, e
+    within the tolerance: the library orders each cloud itself."""
+    rng = np.random.default_rng(5)
+    perms = [rng.permutation(x.shape[0]) for (x, _) in scans.sources]
+    shuffled = Workload(name="shuffled", resolution=scans.resolution,
+                        sources=[(x[p], c[p]) for (x, c), p in zip(scans.sources, perms)],
+                        targets=scans.targets, poses=scans.poses, factors=scans.factors, meta={})
+    a = GpuWorkload(vg, ctx, scans).linearize(with_corr=True)
+    b = GpuWorkload(vg, ctx, shuffled).linearize(with_corr=True)
+    assert np.array_equal(a["inliers"], b["inliers"])
+    off = 0
+    for s in scans.factors[:, 0]:
+        n = scans.sources[s][0].shape[0]
+        assert np.array_equal(a["corr"][off:off + n][perms[s]], b["corr"][off:off + n])
+        off += n
+    for f in range(len(scans.factors)):
+        if a["inliers"][f]:
+            for k in ("H", "b", "e"):
+                assert rel_fro(b[k][f], a[k][f]) <= TOL, (f, k)
