@@ -768,7 +768,9 @@ def main():
     t_vox = time.perf_counter() - t0
     n_vox = int(sum(m.n_voxels for m in maps))
     map_bytes = int(sum(m.device_bytes for m in maps))
+    t0 = time.perf_counter()
     fs = vg.FactorSet(ctx, src, maps, w.factors, w.poses.shape[0], args.tile)
+    t_fs = time.perf_counter() - t0     # includes the Morton-ordered source copies
     poses = torch.from_numpy(np.ascontiguousarray(w.poses)).to("cuda")
     tuned = None
     if not args.tile:      # measure the candidate tile sizes and keep the fastest
@@ -954,6 +956,7 @@ def main():
         },
         "stages": {
             "voxelize_all_maps_ms": round(t_vox * 1e3, 3),
+            "factorset_create_ms": round(t_fs * 1e3, 3),
             "maps": len(maps),
             "overlap_all_pairs_ms": round(t_ov * 1e3, 4),
             "overlap_one_pair_50k_ms": {"device_p50": float(np.percentile(pair_dev_ms, 50)),
