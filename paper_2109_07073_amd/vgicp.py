@@ -329,16 +329,18 @@ def voxelize(ctx: Context, xyz, cov, resolution: float) -> VoxelMap:
 class FactorSet:
     """Factor list bound to its source clouds and target maps.
 
-    sources: list of (xyz (3,n), cov (n,6)) device tensors (kept alive here);
-    maps: list of VoxelMap; factors: (F, 4) rows (src, tgt, pose_i, pose_j)."""
+    sources: list of (xyz (3,n), cov (n,6)) device tensors, read only while the
+    set is created (the library keeps its own Morton-ordered copy of each cloud a
+    factor uses); maps: list of VoxelMap (kept alive here); factors: (F, 4) rows
+    (src, tgt, pose_i, pose_j)."""
 
     def __init__(self, ctx: Context, sources, maps, factors, n_poses: int, tile_points: int = 0):
         torch = _torch()
         self._ctx = ctx
-        self._sources = list(sources)
+        sources = list(sources)
         self._maps = list(maps)
-        cl = (CCloud * max(1, len(self._sources)))()
-        for k, (x, c) in enumerate(self._sources):
+        cl = (CCloud * max(1, len(sources)))()
+        for k, (x, c) in enumerate(sources):
             n = int(x.shape[1])
             _dev_tensor(x, torch.float32, (3, n), f"sources[{k}].xyz")
             _dev_tensor(c, torch.float32, (n, 6), f"sources[{k}].cov")
@@ -350,7 +352,7 @@ class FactorSet:
         self.factors = np.asarray(factors, dtype=np.int32).reshape(-1, 4).copy()
         self.n_poses = int(n_poses)
         h = ctypes.c_void_p()
-        _check(_lib.vgicp_factorset_create(ctx.handle, cl, len(self._sources), mp, len(self._maps),
+        _check(_lib.vgicp_factorset_create(ctx.handle, cl, len(sources), mp, len(self._maps),
                                            arr, nf, self.n_poses, int(tile_points), ctypes.byref(h)),
                ctx.handle)
         self._h = h
@@ -359,7 +361,7 @@ class FactorSet:
                                          ctypes.byref(d)))
         self.n_factors, self.n_tiles, self.total_points = a.value, b.value, c.value
         self.tile_points = d.value
-        self.source_sizes = np.array([int(self._sources[s][0].shape[1]) for s in self.factors[:, 0]],
+        self.source_sizes = np.array([int(sources[s][0].shape[1]) for s in self.factors[:, 0]],
                                      dtype=np.int64)
         n = ctypes.c_int64()
         _check(_lib.vgicp_factorset_pairs(h, ctypes.byref(n), None))
