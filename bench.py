@@ -182,6 +182,30 @@ def cpu_baseline(w, cpu_seconds: float = 24.0, workers: int = 1):
     return inl / wall, workers, sample, ids, outs
 
 
+def cpu_single_process(w, seconds: float = 3.0):
+    """The same oracle in this one process (one thread), on the first factors
+    of the same seeded order for about `seconds`: correspondences per second."""
+    global _CPU_W
+    _CPU_W = w
+    order = np.random.default_rng(7).permutation(w.n_factors)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):      # the worker's own one-thread limit ends here too
+        outs, t = _oracle_worker((0, 1, order, seconds))
+    return sum(int(o["inliers"]) for _, o, _ in outs) / t, len(outs)
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def oracle_all(w, workers: int):
     """The FP64 oracle over every factor of w (forked processes, no time
     budget), as {factor: outputs}.  Must run before the GPU is touched.
@@ -748,6 +772,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu_run = cpu_baseline(w, workers=max(1, min(args.cpu_workers, os.cpu_count() or 1)))
         log(f"[bench] cpu baseline: {cpu_run[2]}")
+        cpu_single = cpu_single_process(w)
+        log(f"[bench] cpu baseline, one process: {cpu_single[0] / 1e6:.2f} M corr/s "
+            f"({cpu_single[1]} factors)")
 
     import torch
     from paper_2109_07073_amd import vgicp as vg
@@ -894,7 +921,9 @@ def main():
     if cpu_run is not None:
         rate, cores, sample, ids, outs = cpu_run
         cpu = {"value": rate, "unit": "correspondences/s", "cores": cores, "kind": "oracle",
-               "sample": sample}
+               "sample": sample, "single_process_value": cpu_single[0],
+               "single_process_factors": cpu_single[1], "host_cpu": host_cpu_model(),
+               "host_logical_cpus": os.cpu_count()}
         Hg, bg, eg = out["H"].cpu().numpy(), out["b"].cpu().numpy(), out["e"].cpu().numpy()
         errs = {"H": 0.0, "b": 0.0, "e": 0.0}
         for f, o in zip(ids, outs):

@@ -28,3 +28,15 @@ def test_profiled_traffic_follows_the_sources():
     assert t is None or 12 * 101_596_832 < t < 3 * 3.88e9
     assert bench.profiled_traffic("batched4500", 1536) is None
     assert bench.profiled_traffic("no_such_workload") is None
+
+
+def test_single_process_oracle_rate_and_host_model():
+    """The baseline's one-process oracle rate runs in-process on a bounded
+    sample and the host's CPU model is named."""
+    import bench
+    from synth import make_tiny_workload
+    w = make_tiny_workload(seed=3, n_src=[300, 200], n_tgt=[400, 300], resolution=0.5,
+                           n_factors=2, half=4.0, height=2.0)
+    rate, n = bench.cpu_single_process(w, seconds=0.2)
+    assert n >= 1 and rate >= 0.0
+    assert bench.host_cpu_model()
