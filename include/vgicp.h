@@ -352,7 +352,10 @@ int vgicp_server_destroy(vgicp_server srv);
 const char *vgicp_server_last_error(vgicp_server srv);
 
 /* Register a keyframe: host arrays h_xyz [3][n] and h_cov [n][6] are copied
- * to server-owned device memory and voxelized at `resolution`.  Returns its id.
+ * to server-owned device memory and voxelized at `resolution`; the copy then
+ * keeps the points in Morton order of cells of that resolution (the order a
+ * factor set gives a cloud matched against maps of that resolution, so
+ * results agree bit for bit; requests have no per-point outputs).  Returns its id.
  * Errors: EINVAL (n outside [0, 2^26], NULL arrays, bad resolution), ENONFINITE,
  * ERANGE, EFULL (the frame would exceed the memory
  * budget; nothing is kept), ENOMEM, EHIP. */
