@@ -12,6 +12,9 @@ from .vgicp_oracle import (  # noqa: F401
     voxelize,
     relative_pose,
     lookup,
+    fused_covariance,
+    positive_definite,
+    fused_information,
     linearize_factor,
     evaluate_factor,
     overlap_factor,

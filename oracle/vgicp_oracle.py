@@ -264,10 +264,39 @@ def lookup(vmap: VoxelMap, xyz32: np.ndarray, R: np.ndarray, t: np.ndarray) -> n
 # per-correspondence terms (Sec. III-A, Eqs. (2), (4)-(6))
 # --------------------------------------------------------------------------
 
-def fused_information(Sigma_v: np.ndarray, C_k: np.ndarray, R: np.ndarray) -> np.ndarray:
-    """Omega_k = (C'_k + R C_k R^T)^-1 for (n, 3, 3) stacks, FP64."""
-    F = Sigma_v + np.einsum("ab,nbc,dc->nad", R, C_k, R)
-    return np.linalg.inv(F), F
+def fused_covariance(Sigma_v: np.ndarray, C_k: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """F_k = C'_k + R C_k R^T for (n, 3, 3) stacks, FP64 (Eq. (2))."""
+    return Sigma_v + np.einsum("ab,nbc,dc->nad", R, C_k, R)
+
+
+def positive_definite(F: np.ndarray) -> np.ndarray:
+    """Rows of an (n, 3, 3) stack that are positive definite: every entry
+    finite and the three leading principal minors positive (Sylvester's
+    criterion)."""
+    F = np.asarray(F, dtype=np.float64)
+    ok = np.all(np.isfinite(F), axis=(1, 2))
+    out = np.zeros(F.shape[0], dtype=bool)
+    if ok.any():
+        G = F[ok]
+        d1 = G[:, 0, 0]
+        d2 = G[:, 0, 0] * G[:, 1, 1] - G[:, 0, 1] * G[:, 1, 0]
+        d3 = np.linalg.det(G)
+        out[ok] = (d1 > 0) & (d2 > 0) & (d3 > 0)
+    return out
+
+
+def fused_information(Sigma_v: np.ndarray, C_k: np.ndarray, R: np.ndarray) -> tuple:
+    """Omega_k = (C'_k + R C_k R^T)^-1 for (n, 3, 3) stacks, FP64 (Eq. (2)).
+
+    Returns (Omega, good).  Only rows whose fused covariance is positive
+    definite are inverted; the others (singular, indefinite or non-finite:
+    Eq. (2) defines no weight for them) get Omega = 0 and good = False."""
+    F = fused_covariance(Sigma_v, C_k, R)
+    good = positive_definite(F)
+    Omega = np.zeros_like(F)
+    if good.any():
+        Omega[good] = np.linalg.inv(F[good])
+    return Omega, good
 
 
 def residuals(m_v: np.ndarray, R: np.ndarray, t: np.ndarray, mu: np.ndarray) -> tuple:
@@ -287,13 +316,6 @@ def jacobians(R: np.ndarray, mu: np.ndarray, q: np.ndarray) -> tuple:
     B[:, :, :3] = -_skew(q)
     B[:, :, 3:] = np.eye(3)[None]
     return A, B
-
-
-def _positive_definite(F: np.ndarray) -> np.ndarray:
-    d1 = F[:, 0, 0]
-    d2 = F[:, 0, 0] * F[:, 1, 1] - F[:, 0, 1] * F[:, 1, 0]
-    d3 = np.linalg.det(F)
-    return (d1 > 0) & (d2 > 0) & (d3 > 0) & np.all(np.isfinite(F), axis=(1, 2))
 
 
 def linearize_factor(src_xyz32, src_cov32, vmap: VoxelMap, pose_i, pose_j):
@@ -316,8 +338,7 @@ def linearize_factor(src_xyz32, src_cov32, vmap: VoxelMap, pose_i, pose_j):
         m_v = vmap.mean[corr[hit]].astype(np.float64)
         S_v = _unpack_cov(vmap.cov[corr[hit]])
         res, q = residuals(m_v, R, t, mu)
-        Omega, F = fused_information(S_v, C_k, R)
-        good = _positive_definite(F)
+        Omega, good = fused_information(S_v, C_k, R)
         A, B = jacobians(R, mu, q)
         J = np.concatenate([A, B], axis=2)[good]          # (n, 3, 12)
         Om = Omega[good]

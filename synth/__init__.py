@@ -13,6 +13,8 @@ from .scenes import (  # noqa: F401
     make_single_factor,
     make_scan_workload,
     make_tiny_workload,
+    make_degenerate_workload,
+    DEGENERATE_COVS,
     pose_rows,
     rng_for,
     stream_scan_frames,

@@ -221,6 +221,98 @@ def make_tiny_workload(seed: int, n_src: int, n_tgt: int, resolution: float,
 
 
 # --------------------------------------------------------------------------
+# hits with degenerate covariances
+# --------------------------------------------------------------------------
+
+# Point covariances (xx, xy, xz, yy, yz, zz) of the degenerate kinds.
+DEGENERATE_COVS = {
+    "zero": [0.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+    "rank1": [1.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+    "rank2": [1.0, 0.0, 0.0, 1.0, 0.0, 0.0],
+    "indefinite": [-3.0, 0.0, 0.0, -3.0, 0.0, -3.0],
+    "nan": [1.0, np.nan, 0.0, 1.0, 0.0, 1.0],
+    "inf": [np.inf, 0.0, 0.0, 1.0, 0.0, 1.0],
+    "neg_inf": [1.0, 0.0, 0.0, 1.0, 0.0, -np.inf],
+}
+
+
+def make_degenerate_workload(seed: int = 0, n_regular: int = 400, n_target: int = 600,
+                             per_kind: int = 6, resolution: float = 0.5) -> Workload:
+    """Factors whose sources mix regular points with points of degenerate
+    covariance placed where the target has points, so that they fall in
+    target voxels.
+
+    The target is a small room scene (k-NN covariances) plus eight pads of
+    three points each with zero covariance, centred in 0.5 m cells at
+    x = 5.25 ... 12.25 m on the x axis (cells that hold no other point).
+    Degenerate source points are copies of target points carried into the
+    source frame: "zero", "rank1" and "rank2" ones at the pads (where the
+    voxel covariance is zero, so the fused covariance is 0 or singular),
+    "indefinite", "nan", "inf" and "neg_inf" ones at regular target points.
+
+    factor 0: regular + zero/indefinite/nan/inf/neg_inf, relative pose of
+              0.1 m and 2 degrees on top of a random target pose
+    factor 1: regular + every kind, relative pose exactly a 90 degree turn
+              about z with no translation (target pose I), so that the
+              rank-deficient covariances stay exactly singular
+    factor 2: factor 0's degenerate points alone
+    factor 3: factor 0's regular points alone
+    meta["kinds"][f] lists the kind of every source point of factor f
+    ("regular" or a key of DEGENERATE_COVS)."""
+    rng = rng_for(101, seed)
+    half, height = 3.0, 2.0
+    tx, _ = room_points(rng, n_target, half=half, height=height)
+    tcov = knn_covariances(tx, 10, 1e-3)
+    pads = np.array([[5.25 + k, 0.25, 0.25] for k in range(8)])
+    pad_pts = np.repeat(pads, 3, axis=0) + rng.uniform(-0.1, 0.1, size=(24, 3))
+    tgt_xyz = np.concatenate([tx, pad_pts]).astype(np.float32)
+    tgt_cov = np.concatenate([tcov, np.zeros((24, 6))]).astype(np.float32)
+
+    def carried(x, T):
+        """Points given in the target frame, expressed in a source frame whose
+        relative pose to the target is T (source -> target)."""
+        R, t = T[:3, :3], T[:3, 3]
+        return (np.asarray(x, np.float64) - t) @ R
+
+    def source(T, kinds_wanted, with_regular=True):
+        pts, covs, kinds = [], [], []
+        if with_regular:
+            rx, _ = room_points(rng, n_regular, half=half, height=height)
+            pts.append(carried(rx, T))
+            covs.append(knn_covariances(pts[-1], 10, 1e-3))
+            kinds += ["regular"] * n_regular
+        for kind in kinds_wanted:
+            if kind in ("zero", "rank1", "rank2"):
+                at = pad_pts[rng.choice(24, size=per_kind, replace=False)]
+            else:
+                at = tx[rng.choice(n_target, size=per_kind, replace=False)]
+            pts.append(carried(at, T))
+            covs.append(np.tile(np.array(DEGENERATE_COVS[kind]), (per_kind, 1)))
+            kinds += [kind] * per_kind
+        return np.concatenate(pts), np.concatenate(covs), kinds
+
+    Tj0 = random_perturbation(rng, 1.0, 30.0)
+    Trel0 = random_perturbation(rng, 0.1, 2.0)
+    Ti0 = Tj0 @ Trel0
+    Rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    Trel1 = np.eye(4)
+    Trel1[:3, :3] = Rz
+    generic = ["zero", "indefinite", "nan", "inf", "neg_inf"]
+    s0x, s0c, k0 = source(Trel0, generic)
+    s1x, s1c, k1 = source(Trel1, list(DEGENERATE_COVS))
+    deg = np.array([k != "regular" for k in k0])
+    sources = [(s0x, s0c), (s1x, s1c), (s0x[deg], s0c[deg]), (s0x[~deg], s0c[~deg])]
+    kinds = [k0, k1, [k for k in k0 if k != "regular"], ["regular"] * int((~deg).sum())]
+    poses = pose_rows([Ti0, Tj0, Trel1, np.eye(4)])
+    factors = np.array([[0, 0, 0, 1], [1, 0, 2, 3], [2, 0, 0, 1], [3, 0, 0, 1]], dtype=np.int32)
+    return Workload(
+        name=f"degenerate_{seed}", resolution=resolution,
+        sources=[_f32_cloud(x, c) for (x, c) in sources],
+        targets=[(tgt_xyz, tgt_cov)], poses=poses, factors=factors,
+        meta={"seed": [SEED_BASE, 101, seed], "kinds": kinds})
+
+
+# --------------------------------------------------------------------------
 # urban corridor scene and HDL-64-like ring scans
 # --------------------------------------------------------------------------
 

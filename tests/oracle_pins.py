@@ -234,3 +234,57 @@ def global_null_space(poses):
         A[3:, 3:] = R
         cols.append(A)
     return np.vstack(cols)
+
+
+def degenerate_pins(w):
+    """Pins of the reading for hits whose fused covariance is not positive
+    definite (Eq. (2) gives them no weight): each such hit is an inlier and
+    adds exactly nothing.  `w` is synth.make_degenerate_workload().  Raises
+    AssertionError (or LinAlgError from an oracle that inverts a singular
+    matrix) when a pin fails.
+
+      * every degenerate point lies, under the exact 4x4 relative motion, in
+        the box of the voxel the oracle assigns it (a hit by geometry);
+      * inliers = every hit, degenerate ones included;
+      * the factor of degenerate points alone: H = 0, b = 0, e = 0 exactly;
+      * a factor with degenerate points equals, bit for bit, the factor of
+        its regular points alone, and that one matches central finite
+        differences of the frozen residual;
+      * the exact 90 degree factor (rank-one and rank-two covariances stay
+        exactly singular) equals the oracle on its regular points alone."""
+    vm = oracle.voxelize(*w.targets[0], w.resolution)[0]
+    kinds = w.meta["kinds"]
+    outs = []
+    for f, (s, _, pi, pj) in enumerate(w.factors):
+        xyz, cov = w.sources[s]
+        out = oracle.linearize_factor(xyz, cov, vm, w.poses[pi], w.poses[pj])
+        outs.append(out)
+        deg = np.array([k != "regular" for k in kinds[f]])
+        corr = out["corr"]
+        assert np.all(corr[deg] >= 0), f"factor {f}: a degenerate point misses"
+        T = np.linalg.inv(hom(w.poses[pj])) @ hom(w.poses[pi])
+        q = xyz[deg].astype(np.float64) @ T[:3, :3].T + T[:3, 3]
+        lo = vm.keys[corr[deg]] * w.resolution
+        assert np.all((q >= lo - 1e-6) & (q < lo + w.resolution + 1e-6)), f"factor {f}: box"
+        assert out["inliers"] == int((corr >= 0).sum()), f"factor {f}: inliers"
+    # degenerate points only
+    assert outs[2]["inliers"] == len(kinds[2])
+    assert not outs[2]["H"].any() and not outs[2]["b"].any() and outs[2]["e"] == 0.0
+    # with and without the degenerate points
+    n_deg0 = sum(k != "regular" for k in kinds[0])
+    assert outs[0]["inliers"] == outs[3]["inliers"] + n_deg0
+    for k in ("H", "b"):
+        assert np.array_equal(outs[0][k], outs[3][k]), k
+    assert outs[0]["e"] == outs[3]["e"]
+    fd = fd_hessian_factor(*w.sources[3], vm, w.poses[0], w.poses[1])
+    assert rel_err(outs[0]["H"], fd["H"]) < 1e-7 and rel_err(outs[0]["b"], fd["b"]) < 1e-7
+    assert abs(outs[0]["e"] - fd["e"]) <= 1e-10 * abs(fd["e"])
+    # exact 90 degree turn, every kind
+    reg1 = np.array([k == "regular" for k in kinds[1]])
+    x1, c1 = w.sources[1]
+    alone = oracle.linearize_factor(x1[reg1], c1[reg1], vm, w.poses[2], w.poses[3])
+    assert outs[1]["inliers"] == alone["inliers"] + int((~reg1).sum())
+    for k in ("H", "b"):
+        assert np.array_equal(outs[1][k], alone[k]), k
+    assert outs[1]["e"] == alone["e"]
+    return outs

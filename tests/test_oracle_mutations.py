@@ -204,3 +204,72 @@ def test_planted_assembly_mistake_is_caught(monkeypatch, fn):
     monkeypatch.setattr(vo, "assemble_system", fn)
     monkeypatch.setattr(oracle, "assemble_system", fn)
     assert not _assembly_pins_hold()
+
+
+# ------------------------------------------- degenerate fused covariances (R9)
+
+def _degenerate_pins_hold() -> bool:
+    from synth import make_degenerate_workload
+    from tests.oracle_pins import degenerate_pins
+    try:
+        degenerate_pins(make_degenerate_workload())
+    except (AssertionError, np.linalg.LinAlgError):
+        return False
+    return True
+
+
+_orig_pd = vo.positive_definite
+_orig_lin = vo.linearize_factor
+
+
+def _pd_without_third_minor(F):
+    """Sylvester's criterion stopped at the 2x2 minor."""
+    F = np.asarray(F, np.float64)
+    with np.errstate(all="ignore"):
+        return (F[:, 0, 0] > 0) & (F[:, 0, 0] * F[:, 1, 1] - F[:, 0, 1] ** 2 > 0)
+
+
+def _fused_inverts_before_masking(S, C, R):
+    """Every row inverted, the positive-definite mask applied only afterwards."""
+    F = vo.fused_covariance(S, C, R)
+    return np.linalg.inv(F), _orig_pd(F)
+
+
+def _fused_pseudo_inverse_for_all(S, C, R):
+    """Non-positive-definite rows weighted by a pseudo-inverse instead of
+    being left out."""
+    F = vo.fused_covariance(S, C, R)
+    F = np.where(np.isfinite(F), F, 0.0)
+    return np.linalg.pinv(F), np.ones(F.shape[0], dtype=bool)
+
+
+def _lin_counts_only_weighted_hits(xyz, cov, vmap, pi, pj):
+    """Inliers counted after the positive-definite test instead of before."""
+    out = _orig_lin(xyz, cov, vmap, pi, pj)
+    hit = out["corr"] >= 0
+    if hit.any():
+        Cs = vo._unpack_cov(np.asarray(cov, np.float32).reshape(-1, 6)[hit])
+        Sv = vo._unpack_cov(vmap.cov[out["corr"][hit]])
+        _, good = _orig_fused(Sv, Cs, out["R"])
+        out["inliers"] = int(good.sum())
+    return out
+
+
+DEG_MUTANTS = [
+    ("positive_definite", _pd_without_third_minor),
+    ("fused_information", _fused_inverts_before_masking),
+    ("fused_information", _fused_pseudo_inverse_for_all),
+    ("linearize_factor", _lin_counts_only_weighted_hits),
+]
+
+
+def test_unmodified_oracle_passes_its_degenerate_pins():
+    assert _degenerate_pins_hold()
+
+
+@pytest.mark.parametrize("name,fn", DEG_MUTANTS, ids=[f.__name__ for _, f in DEG_MUTANTS])
+def test_planted_degenerate_mistake_is_caught(monkeypatch, name, fn):
+    monkeypatch.setattr(vo, name, fn)
+    monkeypatch.setattr(oracle, name, fn)
+    with np.errstate(all="ignore"):
+        assert not _degenerate_pins_hold()

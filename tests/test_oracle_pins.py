@@ -12,7 +12,10 @@ mathematics (CPU only).
     space, b orthogonal to it, invariance under a common rigid motion;
   * isotropic covariances: point-to-point ICP normal equations;
   * single-point factors derived by hand (tests/golden/single_point_factors.json);
-  * overlap: self overlap is 1, a far cloud 0, hits equal inliers.
+  * overlap: self overlap is 1, a far cloud 0, hits equal inliers;
+  * hits whose fused covariance is not positive definite (zero, rank one or
+    two, indefinite, NaN or infinite entries): inliers that add nothing,
+    against the same factor without them and finite differences.
 """
 
 import json
@@ -24,8 +27,8 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import make_single_factor, make_tiny_workload, pose_rows
-from tests.oracle_pins import (fd_cost_gradient, fd_hessian_factor, hom,
+from synth import make_degenerate_workload, make_single_factor, make_tiny_workload, pose_rows
+from tests.oracle_pins import (degenerate_pins, fd_cost_gradient, fd_hessian_factor, hom,
                                icp_normal_equations, null_space_basis,
                                rel_err, rows)
 
@@ -324,6 +327,31 @@ def test_empty_source_and_no_hits(tiny):
     assert out["inliers"] == 0 and out["e"] == 0.0 and not out["H"].any()
     assert oracle.overlap_factor(np.zeros((0, 3), np.float32), vm, tiny.poses[0],
                                  tiny.poses[1]) == (0, 0.0)
+
+
+def test_degenerate_fused_covariance_hits_count_and_add_nothing():
+    """Reading of Eq. (2) where the fused covariance C'_k + R C_k R^T has no
+    inverse or is not positive definite: the hit counts as an inlier and
+    adds nothing to H, b or e."""
+    w = make_degenerate_workload()
+    outs = degenerate_pins(w)
+    assert all(np.all(np.isfinite(o["H"])) and np.all(np.isfinite(o["b"])) for o in outs)
+    # every kind is present and its fused covariance really is degenerate
+    assert set(w.meta["kinds"][1]) == {"regular", "zero", "rank1", "rank2", "indefinite",
+                                       "nan", "inf", "neg_inf"}
+
+
+def test_positive_definite_test_on_textbook_matrices():
+    """Sylvester's criterion on matrices whose definiteness is known."""
+    F = np.stack([np.eye(3), np.diag([1.0, 1.0, 0.0]), np.diag([1.0, -1.0, 1.0]),
+                  np.zeros((3, 3)), np.full((3, 3), np.nan), np.diag([np.inf, 1.0, 1.0]),
+                  np.array([[2.0, 1.0, 0.0], [1.0, 2.0, 1.0], [0.0, 1.0, 2.0]]),
+                  np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 1.0]])])
+    assert oracle.positive_definite(F).tolist() == [True, False, False, False, False, False,
+                                                    True, False]
+    Om, good = oracle.fused_information(F, np.zeros_like(F), np.eye(3))
+    assert good.tolist() == oracle.positive_definite(F).tolist()
+    assert np.allclose(Om[0], np.eye(3)) and not Om[1:6].any()
 
 
 # ----------------------------------------------------------------- overlap
