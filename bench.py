@@ -291,7 +291,7 @@ def run_precision(args):
             rin = np.array([ref[f]["inliers"] for f in range(F)])
             for accum, resid, kappa in PRECISION_VARIANTS:
                 kw = dict(accum=accum, resid=resid, fp64_kappa=kappa)
-                out = vg.linearize_factors(ctx, fs, poses, use_graph=True, **kw)
+                out = vg.linearize_factors(ctx, fs, poses, **kw)
                 for _ in range(3):
                     vg.linearize_factors(ctx, fs, poses, use_graph=True, out=out, **kw)
                 t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -907,7 +907,8 @@ def main():
                  "launches_per_step": 2 * F}
 
     # ---- error-only round (cost evaluation for trial steps)
-    ev = vg.evaluate_errors(ctx, fs, poses, accum=args.accum, use_graph=True)
+    ev = vg.evaluate_errors(ctx, fs, poses, accum=args.accum)
+    vg.evaluate_errors(ctx, fs, poses, accum=args.accum, use_graph=True, out=ev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -28,8 +28,9 @@
  *       cov: float32 [n][6]  (per point xx, xy, xz, yy, yz, zz of the
  *                              symmetric 3x3 covariance; 8-byte aligned): only
  *                              points that fall in a voxel read theirs
- *     The caller owns them and keeps them alive while any factor set that
- *     references them is used.
+ *     The caller owns them.  vgicp_voxelize and vgicp_factorset_create read
+ *     them during the call only (a factor set keeps its own copy of every
+ *     source cloud), so they may be freed once those calls return.
  *   - A pose is 12 float64 values: R (3x3, row-major) then t; it maps sensor
  *     coordinates to world coordinates, x_world = R x + t.
  *   - Factor (i, j) matches the source cloud (in frame i) against the voxel map
@@ -64,7 +65,8 @@ extern "C" {
 
 /* Accumulation of the per-point Hessian, gradient and cost terms. */
 #define VGICP_ACC_F32 0      /* FP32 per lane and across the workgroup              */
-#define VGICP_ACC_F32_COMP 1 /* FP32 with two-sum compensation                      */
+#define VGICP_ACC_F32_COMP 1 /* FP32 per lane, two-sum compensated across the lanes of
+                                a wave, FP64 across waves and tiles                   */
 #define VGICP_ACC_F64 2      /* FP64 from the first per-point term                  */
 
 /* Residual e_k = mu'_k - T mu_k of the per-point terms.  The correspondence
@@ -231,6 +233,24 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          int64_t *inliers, const int32_t *candidates, int32_t n_candidates,
                          int32_t *best_tile, double *best_ms);
 
+/* Target-order source copies.  A round streams every source point once and
+ * gathers the statistics of the target voxel it falls in (Sec. III-A, Eq. (3)
+ * correspondences); the gathers share cache lines when consecutive points of a
+ * wave fall in neighbouring voxels.  This call gives every factor its own copy
+ * of its source cloud (40 bytes of device memory per point, replacing the
+ * per-cloud Morton-ordered copies) with the points in the order of the target
+ * voxels they fall in at `poses` (device float64 [n_poses][12]): voxel after
+ * voxel in the order of the map's statistics records (bricks of 4 x 4 x 4,
+ * Morton order within a brick), points of one voxel in their previous order,
+ * and points that fall in no voxel last.  The order stays good while the
+ * poses move by small steps (an optimizer's iterations); call it again after
+ * large moves.  Results at any poses are unchanged up to FP32 summation order
+ * (integer and per-point outputs are identical).  Captured graphs are
+ * dropped.  Synchronizes ctx's stream.
+ * Errors: EINVAL (NULL or foreign arguments, more than 2^31 - 1 source points
+ * in the set), ENOMEM, EHIP (on failure the set is unchanged). */
+int vgicp_factorset_reorder(vgicp_ctx ctx, vgicp_factorset fs, const double *poses);
+
 /* Precision diagnostics (the ill-conditioned case of Sec. III-A's fused
  * covariance C'_k + R C_k R^T): the number of correspondences of the last
  * vgicp_linearize_factors or vgicp_evaluate_errors call on fs that formed and
@@ -239,6 +259,12 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
  * it.  Synchronizes ctx's stream.  n_points: host int64.
  * Errors: EINVAL (NULL or foreign arguments), EHIP. */
 int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points);
+
+/* Number of HIP graphs the factor set holds.  Graph replay (opts.use_graph)
+ * captures one graph per (poses, outputs, options) set and keeps at most 8:
+ * capturing another first waits for the context's stream and drops the least
+ * recently replayed one.  Errors: EINVAL. */
+int vgicp_factorset_graph_count(vgicp_factorset fs, int64_t *n_graphs);
 
 /* Free a factor set and its captured graphs (NULL accepted). */
 int vgicp_factorset_destroy(vgicp_factorset fs);
@@ -309,6 +335,63 @@ int vgicp_overlap(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, int64_
                   double *overlap);
 
 /* --------------------------------------------------------------------------
+ * Keyframe control by overlap (Sec. III-B local mapping, Sec. III-C global
+ * mapping).  The overlap of a cloud against a map is Eq. (8) with the pose
+ * T_map^-1 T_cloud, counted exactly on the GPU as in vgicp_overlap; the
+ * comparisons with the thresholds are made on the host in FP64.
+ * ------------------------------------------------------------------------ */
+
+/* Admission rule of a factor by its overlap. */
+#define VGICP_GATE_ABOVE 0    /* admit when overlap > threshold (the paper's th^G_min rule) */
+#define VGICP_GATE_AT_LEAST 1 /* admit when overlap >= threshold                          */
+
+/* Overlap-gated factor creation (Sec. III-C: a matching-cost factor joins
+ * the new keyframe and every earlier one whose overlap exceeds th^G_min,
+ * e.g. 2.5 %).  `cloud` (host struct, device xyz [3][n]; cov is not read) at
+ * host pose h_pose [12] is checked against each of the n_maps maps at host
+ * poses h_map_poses [n_maps][12]: h_hits [n_maps] (host int64, may be NULL)
+ * and h_overlap [n_maps] (host float64, may be NULL) receive the counts and
+ * rates, h_admitted [n_maps] (host int32) 1 for every map admitted by
+ * `threshold` under `rule` (VGICP_GATE_*), *n_admitted (may be NULL) their
+ * number.  Synchronizes ctx's stream (the outputs are on the host).
+ * Errors: EINVAL (NULL or foreign arguments, a non-finite pose or threshold,
+ * an unknown rule), ENOMEM, EHIP. */
+int vgicp_connect(vgicp_ctx ctx, const vgicp_cloud *cloud, const double *h_pose,
+                  const vgicp_map *maps, const double *h_map_poses, int32_t n_maps,
+                  double threshold, int32_t rule, int64_t *h_hits, double *h_overlap,
+                  int32_t *h_admitted, int32_t *n_admitted);
+
+/* Local-mapping rules (Sec. III-B). */
+typedef struct {
+  double skip_above;  /* th^L_max: a frame whose overlap with the submap's last frame
+                         is above this is skipped (the sensor has not moved), e.g. 0.95 */
+  double close_below; /* th^L_min: the submap closes when the overlap between its newest
+                         and first frames is below this, e.g. 0.10                     */
+  int32_t max_frames; /* N^L_max: the submap closes when it would hold more frames     */
+  int32_t reserved;   /* must be 0                                                     */
+} vgicp_submap_rules;
+
+/* Decisions of vgicp_submap_step for an arriving frame. */
+#define VGICP_SUBMAP_START 0  /* the submap was empty: the frame starts it                  */
+#define VGICP_SUBMAP_SKIP 1   /* overlap with the last frame > skip_above: not inserted     */
+#define VGICP_SUBMAP_INSERT 2 /* inserted (factors to every frame of the submap follow)     */
+#define VGICP_SUBMAP_CLOSE 3  /* inserted, and the submap closes: overlap with the first
+                                 frame < close_below, or n_submap + 1 > max_frames        */
+
+/* The local-mapping decision for `frame` (host struct, device xyz) at host
+ * pose h_pose, arriving at a submap of n_submap frames whose first and last
+ * frames have maps `first` and `last` at host poses h_first_pose and
+ * h_last_pose (equal when n_submap is 1; all ignored when n_submap is 0).
+ * *overlap_last and *overlap_first (may be NULL) receive the overlaps of the
+ * frame against the last and first maps (0 when n_submap is 0).  The
+ * decision is made in that order: START, SKIP, CLOSE, INSERT.  Synchronizes
+ * ctx's stream.  Errors: EINVAL, ENOMEM, EHIP. */
+int vgicp_submap_step(vgicp_ctx ctx, const vgicp_submap_rules *rules, const vgicp_cloud *frame,
+                      const double *h_pose, vgicp_map first, const double *h_first_pose,
+                      vgicp_map last, const double *h_last_pose, int32_t n_submap,
+                      int32_t *decision, double *overlap_first, double *overlap_last);
+
+/* --------------------------------------------------------------------------
  * Serving: continuous batching of factor requests over resident keyframes.
  *
  * The paper's optimizer issues every cost task of an iteration to the GPU,
@@ -353,9 +436,13 @@ const char *vgicp_server_last_error(vgicp_server srv);
 
 /* Register a keyframe: host arrays h_xyz [3][n] and h_cov [n][6] are copied
  * to server-owned device memory and voxelized at `resolution`; the copy then
- * keeps the points in Morton order of cells of that resolution (the order a
- * factor set gives a cloud matched against maps of that resolution, so
- * results agree bit for bit; requests have no per-point outputs).  Returns its id.
+ * keeps the points in Morton order of cells of that resolution.  That is the
+ * order a factor set gives a source cloud whose maps all have this resolution,
+ * so a server factor and a factor-set factor agree bit for bit when every
+ * target of that source in the factor set has the source frame's resolution
+ * and both use the same tile_points; otherwise the points are summed in
+ * another order and they agree within FP32 summation error (integer outputs
+ * always agree).  Requests have no per-point outputs.  Returns its id.
  * Errors: EINVAL (n outside [0, 2^26], NULL arrays, bad resolution), ENONFINITE,
  * ERANGE, EFULL (the frame would exceed the memory
  * budget; nothing is kept), ENOMEM, EHIP. */
@@ -386,6 +473,25 @@ int vgicp_server_poll(vgicp_server srv, int64_t ticket, int *done);
 /* Block until the request completes; *latency_ms (may be NULL) receives the
  * time from submit to outputs written.  Errors: EINVAL, EHIP (a batch failed). */
 int vgicp_server_wait(vgicp_server srv, int64_t ticket, double *latency_ms);
+
+/* vgicp_connect over resident frames: frame id `frame` at h_pose against the
+ * frames candidates [n_candidates] at h_candidate_poses [n_candidates][12],
+ * as overlap requests batched with the server's other work (split so that
+ * each carries at most max_batch_poses poses) and waited for.  Outputs as for
+ * vgicp_connect.  Errors: EINVAL (unknown frames, bad arguments,
+ * max_batch_poses < 2), EHIP. */
+int vgicp_server_connect(vgicp_server srv, int32_t frame, const double *h_pose,
+                         const int32_t *candidates, const double *h_candidate_poses,
+                         int32_t n_candidates, double threshold, int32_t rule, int64_t *h_hits,
+                         double *h_overlap, int32_t *h_admitted, int32_t *n_admitted);
+
+/* vgicp_submap_step over resident frames (`first` and `last` are frame ids;
+ * one overlap request of two rows, which needs max_batch_poses >= 3).
+ * Errors: EINVAL, EHIP. */
+int vgicp_server_submap_step(vgicp_server srv, const vgicp_submap_rules *rules, int32_t frame,
+                             const double *h_pose, int32_t first, const double *h_first_pose,
+                             int32_t last, const double *h_last_pose, int32_t n_submap,
+                             int32_t *decision, double *overlap_first, double *overlap_last);
 
 /* Counters: batches launched and requests completed so far, the largest number
  * of requests merged into one batch, and the largest number of batches that

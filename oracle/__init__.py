@@ -18,6 +18,8 @@ from .vgicp_oracle import (  # noqa: F401
     linearize_factor,
     evaluate_factor,
     overlap_factor,
+    factor_admitted,
+    submap_decision,
     linearize_workload,
     overlap_workload,
     build_maps,

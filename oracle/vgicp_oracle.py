@@ -16,6 +16,8 @@ GPU-accelerated GICP Matching Cost Factors", IEEE RA-L 2021.
   linearize_factor  Sec. III-A, Eqs. (2)-(6): error, Hessian factor, b
   evaluate_factor   Sec. III-A, Eq. (3): the matching cost alone
   overlap_factor    Sec. III-B, Eqs. (7)-(8): voxel overlap rate
+  factor_admitted   Sec. III-C: overlap-gated factor creation
+  submap_decision   Sec. III-B: skip / insert / close of a local submap
   assemble_system   Sec. III-D: the factors' Hessians summed into the
                     global linear system over all poses
 
@@ -369,6 +371,37 @@ def overlap_factor(src_xyz32, vmap: VoxelMap, pose_i, pose_j):
     hits = int((corr >= 0).sum())
     n = int(np.asarray(src_xyz32).reshape(-1, 3).shape[0])
     return hits, (hits / n if n else 0.0)
+
+
+# --------------------------------------------------------------------------
+# keyframe control by overlap (Sec. III-B local mapping, Sec. III-C global)
+# --------------------------------------------------------------------------
+
+def factor_admitted(overlap: float, threshold: float, at_least: bool = False) -> bool:
+    """Sec. III-C: a matching-cost factor is created for a keyframe pair whose
+    overlap rate is larger than th^G_min.  at_least=True is the variant that
+    also admits an overlap equal to the threshold."""
+    return overlap >= threshold if at_least else overlap > threshold
+
+
+def submap_decision(n_submap: int, overlap_last: float, overlap_first: float,
+                    skip_above: float, close_below: float, max_frames: int) -> str:
+    """Sec. III-B, for a frame arriving at a submap of n_submap frames, given
+    its overlap with the submap's last frame and with its first frame:
+      * an empty submap: the frame starts it ("start");
+      * overlap with the last frame above th^L_max: the sensor has not moved
+        and the frame is skipped ("skip");
+      * otherwise the frame is inserted; the submap is then closed when the
+        overlap between its first and newest (this) frame is below th^L_min
+        or it holds more than N^L_max frames ("close"), else it stays open
+        ("insert")."""
+    if n_submap == 0:
+        return "start"
+    if overlap_last > skip_above:
+        return "skip"
+    if overlap_first < close_below or n_submap + 1 > max_frames:
+        return "close"
+    return "insert"
 
 
 # --------------------------------------------------------------------------

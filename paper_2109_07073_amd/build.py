@@ -22,7 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvgicp.so")
 ARCH = os.environ.get("VGICP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip", "reorder.hip"]
+SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip", "reorder.hip",
+           "mapping.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

@@ -353,20 +353,19 @@ __device__ __forceinline__ void residual64(const double R[9], const double t[3],
   }
 }
 
+// Compensated FP32: a lane adds its few terms of a tile (about 36 points, 40 %
+// of them hits, at the largest tile) in plain FP32, like VGICP_ACC_F32, so it
+// keeps the same registers and occupancy; the reduction over the 64 lanes of
+// a wave carries a (sum, error) pair through every DPP step with two-sum, and
+// waves and tiles are then added in FP64.
 template <int N>
 struct Sums<VGICP_ACC_F32_COMP, N> {
   float v[N];
-  float c[N];
   __device__ void zero() {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = c[i] = 0.f;
+    for (int i = 0; i < N; ++i) v[i] = 0.f;
   }
-  __device__ __forceinline__ void add(int i, float x) {
-    float s, err;
-    two_sum(v[i], x, s, err);
-    v[i] = s;
-    c[i] += err;
-  }
+  __device__ __forceinline__ void add(int i, float x) { v[i] += x; }
   // Each DPP step adds a partner's (sum, compensation) pair with two-sum.
   template <int CTRL, int ROW_MASK = 0xf>
   __device__ __forceinline__ static void step(float &v, float &c) {
@@ -380,17 +379,20 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
   __device__ void wave_reduce() {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      step<0xb1>(v[i], c[i]);
-      step<0x4e>(v[i], c[i]);
-      step<0x141>(v[i], c[i]);
-      step<0x140>(v[i], c[i]);
-      step<0x142, 0xa>(v[i], c[i]);
-      step<0x143, 0xc>(v[i], c[i]);
+      float c = 0.f;
+      step<0xb1>(v[i], c);
+      step<0x4e>(v[i], c);
+      step<0x141>(v[i], c);
+      step<0x140>(v[i], c);
+      step<0x142, 0xa>(v[i], c);
+      step<0x143, 0xc>(v[i], c);
+      wide[i] = double(v[i]) + double(c);
     }
   }
+  double wide[N];  // the wave's (sum + compensation) in FP64, after wave_reduce
   __device__ void store(double *lds, int wave) const {
 #pragma unroll
-    for (int i = 0; i < N; ++i) lds[wave * N + i] = double(v[i]) + double(c[i]);
+    for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
   }
   using lds_t = double;
   __device__ static double finish(const double *lds, int i) {
@@ -451,7 +453,10 @@ __device__ __forceinline__ bool fused_information_fp64(const double R[9], const 
   const double a02 = f01 * f12 - f02 * f11, a11 = f00 * f22 - f02 * f02;
   const double a12 = f01 * f02 - f00 * f12, a22 = f00 * f11 - f01 * f01;
   const double det = f00 * a00 + f01 * a01 + f02 * a02;
-  if (!(f00 > 0.0 && a22 > 0.0 && det > 0.0)) return false;
+  // leading minors f00, a22 (of the upper 2x2) and det positive; a finite
+  // det also excludes every infinite entry (each one makes det infinite or
+  // NaN, or a22 negative), and NaN fails every comparison
+  if (!(f00 > 0.0 && a22 > 0.0 && det > 0.0 && det < __builtin_huge_val())) return false;
   const double inv = 1.0 / det;
   o[0] = float(a00 * inv);
   o[1] = float(a01 * inv);
@@ -509,7 +514,10 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
   const float a22 = FMA(f00, f11, -(f01 * f01));
   const float det = FMA(f02, a02, FMA(f01, a01, f00 * a00));
   float o00, o01, o02, o11, o12, o22;
-  const bool pd32 = (f00 > 0.f) & (a22 > 0.f) & (det > 0.f);
+  // positive definite: leading minors f00, a22 (upper 2x2) and det positive.
+  // An infinite entry makes det infinite or NaN (or a22 negative), so a
+  // finite det also excludes those; NaN fails every comparison.
+  const bool pd32 = (f00 > 0.f) & (a22 > 0.f) & (det > 0.f) & (det < __builtin_huge_valf());
   bool wide = false;
   if constexpr (KAPPA) {
     const float tr = (f00 + f11) + f22;
@@ -716,11 +724,12 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 //   math:   the full batches of 64 hits, double-buffered: a batch's voxel
 //           and covariance gathers are in flight during the previous batch's
 //           math.
-// The last partial batch runs at the end of the tile.  FP32 accumulation
-// asks for 4 waves per SIMD (at most 128 VGPRs); the FP64 and compensated
-// accumulators hold twice the registers and keep them.
+// The last partial batch runs at the end of the tile.  FP32 and compensated
+// accumulation ask for 4 waves per SIMD (at most 128 VGPRs; both keep one
+// FP32 sum per lane); the FP64 accumulators hold twice the registers and
+// keep them.
 template <int ACC, bool LIN, bool R64, bool CORR, bool KAPPA>
-__global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F32 ? 4 : 1)
+__global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_points,
             const double *__restrict__ poses, double *__restrict__ partials,
@@ -943,6 +952,56 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
     for (int w = 0; w < kWaves; ++w) s += lds_cnt[w];
     partials[tile * kPartialStride + kNumSums] = double(s);
   }
+}
+
+// ---------------------------------------------------------------- target order
+// Sort keys for putting each factor's source points in the order of the
+// target voxels they fall in at the given poses: for point i of factor f (in
+// the factor set's current copy), the index of its voxel in the map's dense
+// arrays (brick after brick, Morton order within a brick: the order of the
+// statistics records a round reads) or 0xffffffff for a point in no voxel,
+// with f in the high 32 bits; the value is i.  Keys go to the factor's
+// per-point output range (corr_offset).  One 256-thread block per tile,
+// blocks in tile order.
+__global__ void __launch_bounds__(kBlock)
+k_voxel_order_keys(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
+                   int64_t n_tiles, int32_t tile_points, const double *__restrict__ poses,
+                   uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const Tile td = tiles[tile];
+  const FactorDesc fd = factors[td.factor];
+  const FactorConsts k = factor_consts(fd, poses);
+  const uint32_t n = uint32_t(fd.n);
+  const uint32_t begin = uint32_t(td.start);
+  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
+  const uint64_t hi = uint64_t(uint32_t(td.factor)) << 32;
+  // whole waves run every pass (the ballot in find_voxel); lanes past the
+  // tile's end read zeros and write nothing
+  for (uint32_t i0 = begin; i0 < end; i0 += kBlock) {
+    const uint32_t i = i0 + threadIdx.x;
+    float p[3];
+    load_xyz(cx, i - begin, p);
+    float v[3];
+    lookup_coords(k.S, k.u, p[0], p[1], p[2], v);
+    const VoxelKey vk = voxel_key(v, fd.log2cap);
+    const RecordLoad rec = load_home(rb, vk.h, true);
+    const int h = find_voxel(rb, fd.log2cap, vk, rec, true);
+    if (i < end) {
+      keys[fd.corr_offset + i] = hi | (h >= 0 ? uint64_t(uint32_t(h)) : 0xffffffffull);
+      vals[fd.corr_offset + i] = i;
+    }
+  }
+}
+
+hipError_t launch_voxel_order_keys(const vgicp_factorset_s *fs, const double *poses,
+                                   uint64_t *keys, uint32_t *vals, hipStream_t st) {
+  if (fs->n_tiles <= 0) return hipSuccess;
+  k_voxel_order_keys<<<unsigned(fs->n_tiles), kBlock, 0, st>>>(
+      fs->d_factors, fs->d_tiles, fs->n_tiles, fs->tile_points, poses, keys, vals);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- reduce

@@ -77,7 +77,111 @@ k_gather_points(const float *__restrict__ xyz, const float *__restrict__ cov, ui
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Position q of the sorted (factor, voxel) keys is point q - corr_offset of
+// factor f = key >> 32 in its new copy; it takes point vals[q] of the old
+// copy (coordinates, covariance, and the caller's index through the old
+// permutation, or vals[q] itself when the old copy is the caller's cloud).
+__global__ void __launch_bounds__(kThreads)
+k_gather_factor_points(const FactorDesc *__restrict__ old_desc,
+                       const FactorDesc *__restrict__ new_desc, const uint64_t *__restrict__ keys,
+                       const uint32_t *__restrict__ vals, uint64_t total) {
+  const uint64_t q = uint64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (q >= total) return;
+  const uint32_t f = uint32_t(keys[q] >> 32);
+  const uint64_t i = vals[q];
+  const FactorDesc &o = old_desc[f];
+  const FactorDesc &d = new_desc[f];
+  const uint64_t n = uint64_t(o.n);
+  const uint64_t local = q - uint64_t(d.corr_offset);
+  float *xyz = const_cast<float *>(d.xyz);
+  xyz[local] = o.xyz[i];
+  xyz[n + local] = o.xyz[n + i];
+  xyz[2 * n + local] = o.xyz[2 * n + i];
+  const float2 *src = reinterpret_cast<const float2 *>(o.cov + 6 * i);
+  float2 *dst = reinterpret_cast<float2 *>(const_cast<float *>(d.cov) + 6 * local);
+  dst[0] = src[0];
+  dst[1] = src[1];
+  dst[2] = src[2];
+  const_cast<int32_t *>(d.perm)[local] = o.perm ? o.perm[i] : int32_t(i);
+}
+
 }  // namespace
+
+hipError_t launch_voxel_order_keys(const vgicp_factorset_s *fs, const double *poses,
+                                   uint64_t *keys, uint32_t *vals, hipStream_t st);
+
+hipError_t reorder_by_target(vgicp_factorset_s *fs, const double *poses, hipStream_t st) {
+  const int64_t total = fs->total_points;
+  if (fs->n_factors == 0 || total == 0) return hipSuccess;
+  // new per-factor copies: covariances [n][6], coordinates [3][n], permutation [n]
+  std::vector<FactorDesc> nd = fs->h_factors;
+  size_t bytes = 0;
+  std::vector<size_t> off(nd.size(), 0);
+  for (size_t f = 0; f < nd.size(); ++f) {
+    const size_t n = size_t(nd[f].n);
+    off[f] = bytes;
+    if (n) bytes += align256(24 * n) + align256(12 * n) + align256(4 * n);
+  }
+  int end_bit = 32;
+  while (end_bit < 64 && (uint64_t(fs->n_factors - 1) >> (end_bit - 32)) != 0) ++end_bit;
+  size_t sort_bytes = 0;
+  hipError_t e = rocprim::radix_sort_pairs(
+      nullptr, sort_bytes, static_cast<const uint64_t *>(nullptr), static_cast<uint64_t *>(nullptr),
+      static_cast<const uint32_t *>(nullptr), static_cast<uint32_t *>(nullptr), size_t(total), 0,
+      end_bit, st);
+  if (e != hipSuccess) return e;
+  const size_t kb = align256(8 * size_t(total)), vb = align256(4 * size_t(total));
+  const size_t db = align256(sizeof(FactorDesc) * nd.size());
+  char *buf = nullptr, *tmp = nullptr;
+  e = hipMalloc(&buf, std::max<size_t>(bytes, 1));
+  if (e == hipSuccess) e = hipMalloc(&tmp, 2 * kb + 2 * vb + db + align256(sort_bytes));
+  if (e != hipSuccess) {
+    if (buf) (void)hipFree(buf);
+    return e;
+  }
+  for (size_t f = 0; f < nd.size(); ++f) {
+    const size_t n = size_t(nd[f].n);
+    char *p = buf + off[f];
+    nd[f].cov = n ? reinterpret_cast<float *>(p) : nullptr;
+    nd[f].xyz = n ? reinterpret_cast<float *>(p + align256(24 * n)) : nullptr;
+    nd[f].perm = n ? reinterpret_cast<int32_t *>(p + align256(24 * n) + align256(12 * n)) : nullptr;
+  }
+  uint64_t *keys_in = reinterpret_cast<uint64_t *>(tmp);
+  uint64_t *keys_out = reinterpret_cast<uint64_t *>(tmp + kb);
+  uint32_t *vals_in = reinterpret_cast<uint32_t *>(tmp + 2 * kb);
+  uint32_t *vals_out = reinterpret_cast<uint32_t *>(tmp + 2 * kb + vb);
+  FactorDesc *d_new = reinterpret_cast<FactorDesc *>(tmp + 2 * kb + 2 * vb);
+  void *sort_tmp = tmp + 2 * kb + 2 * vb + db;
+  e = launch_voxel_order_keys(fs, poses, keys_in, vals_in, st);
+  if (e == hipSuccess)
+    e = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys_in, keys_out, vals_in, vals_out,
+                                  size_t(total), 0, end_bit, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_new, nd.data(), sizeof(FactorDesc) * nd.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const uint64_t grid = (uint64_t(total) + kThreads - 1) / kThreads;
+    k_gather_factor_points<<<unsigned(grid), kThreads, 0, st>>>(fs->d_factors, d_new, keys_out,
+                                                                vals_out, uint64_t(total));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(fs->d_factors, nd.data(), sizeof(FactorDesc) * nd.size(),
+                       hipMemcpyHostToDevice, st);
+  const hipError_t se = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = se;
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    // the device descriptors may already name the new copies: put the old ones back
+    (void)hipMemcpy(fs->d_factors, fs->h_factors.data(), sizeof(FactorDesc) * nd.size(),
+                    hipMemcpyHostToDevice);
+    (void)hipFree(buf);
+    return e;
+  }
+  if (fs->d_sorted) (void)hipFree(fs->d_sorted);
+  fs->d_sorted = buf;
+  fs->h_factors = nd;
+  return hipSuccess;
+}
 
 hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
                                const std::vector<double> &cell, void **buffer,

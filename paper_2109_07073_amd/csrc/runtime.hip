@@ -102,9 +102,13 @@ hipError_t fold_timing(vgicp_ctx ctx) {
 
 }  // namespace
 
+int vgicp::set_error(vgicp_ctx ctx, int code, const std::string &msg) {
+  return fail(ctx, code, msg);
+}
+
 extern "C" {
 
-int vgicp_version(void) { return 100; }
+int vgicp_version(void) { return 200; }
 
 const char *vgicp_last_error(vgicp_ctx ctx) {
   return ctx ? ctx->last_error.c_str() : g_thread_error.c_str();
@@ -189,6 +193,8 @@ int vgicp_ctx_destroy(vgicp_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)fold_timing(ctx);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->map_ws) (void)hipFree(ctx->map_ws);
+  if (ctx->map_host) (void)hipHostFree(ctx->map_host);
   if (ctx->err_word) (void)hipFree(ctx->err_word);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
@@ -529,6 +535,13 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
   return VGICP_OK;
 }
 
+int vgicp_factorset_graph_count(vgicp_factorset fs, int64_t *n_graphs) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_graph_count: fs is NULL");
+  if (!n_graphs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_graph_count: n_graphs is NULL");
+  *n_graphs = int64_t(fs->graphs.size());
+  return VGICP_OK;
+}
+
 int vgicp_factorset_destroy(vgicp_factorset fs) {
   if (!fs) return VGICP_OK;
   (void)hipSetDevice(fs->device);
@@ -636,6 +649,17 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
     if (x.poses == poses && x.H == H && x.b == b && x.e == e && x.inl == inl && x.corr == corr &&
         x.accum == o.accum && x.resid == o.resid && x.kappa == o.fp64_kappa && x.kind == kind)
       g = &x;
+  if (!g && fs->graphs.size() >= kMaxGraphs) {
+    // drop the least recently replayed graph (after its last launch is done)
+    size_t lru = 0;
+    for (size_t k = 1; k < fs->graphs.size(); ++k)
+      if (fs->graphs[k].last_use < fs->graphs[lru].last_use) lru = k;
+    err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return hip_fail(ctx, who, err);
+    (void)hipGraphExecDestroy(fs->graphs[lru].exec);
+    (void)hipGraphDestroy(fs->graphs[lru].graph);
+    fs->graphs.erase(fs->graphs.begin() + std::ptrdiff_t(lru));
+  }
   if (!g) {
     GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fp64_kappa, kind};
     err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -656,6 +680,7 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
     fs->graphs.push_back(ng);
     g = &fs->graphs.back();
   }
+  g->last_use = ++fs->graph_clock;
   err = hipGraphLaunch(g->exec, st);
   if (err != hipSuccess) return hip_fail(ctx, "hipGraphLaunch", err);
   return VGICP_OK;
@@ -821,6 +846,25 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc != VGICP_OK) return rc;
   if (best_tile) *best_tile = best;
   if (best_ms) *best_ms = best_t;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_reorder(vgicp_ctx ctx, vgicp_factorset fs, const double *poses) {
+  const char *who = "vgicp_factorset_reorder";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  if (fs->total_points > int64_t(INT32_MAX))
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": more than 2^31 - 1 source points");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = reorder_by_target(fs, poses, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  // captured graphs read the descriptors at run time, but drop them anyway so
+  // that no graph outlives the copies it was captured with
+  for (auto &g : fs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  fs->graphs.clear();
   return VGICP_OK;
 }
 

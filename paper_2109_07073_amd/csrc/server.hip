@@ -449,6 +449,8 @@ std::shared_ptr<Request> find_request(vgicp_server srv, int64_t ticket) {
 
 }  // namespace
 
+int64_t vgicp::server_max_batch_poses(vgicp_server srv) { return srv->cfg.max_batch_poses; }
+
 extern "C" {
 
 int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server *out) {

@@ -199,6 +199,12 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
                                const std::vector<double> &cell, void **buffer,
                                std::vector<SortedSource> &out, hipStream_t st);
 
+// Replace the source copies of fs by per-factor copies with each factor's
+// points in the order of the target voxels they fall in at `poses` (device)
+// (points in no voxel last; equal keys keep their order), updating the device
+// descriptors.  Synchronizes st.  On failure fs is unchanged.
+hipError_t reorder_by_target(vgicp_factorset_s *fs, const double *poses, hipStream_t st);
+
 // One tile: `count` source points of factor `factor` starting at `start`.
 struct Tile {
   int32_t factor;
@@ -220,6 +226,13 @@ constexpr int kWideSlot = 29;
 constexpr uint32_t kErrNonFinite = 1u;
 constexpr uint32_t kErrRange = 2u;
 
+// Records `msg` as the last error of ctx (or of the calling thread when ctx
+// is NULL) and returns `code`.
+int set_error(vgicp_ctx ctx, int code, const std::string &msg);
+
+// The poses one batch of a server holds (its max_batch_poses).
+int64_t server_max_batch_poses(vgicp_server srv);
+
 }  // namespace vgicp
 
 // Objects behind the opaque handles of the C ABI.
@@ -233,6 +246,12 @@ struct vgicp_context_s {
   uint32_t *err_word = nullptr;       // device
   uint32_t *host_pinned = nullptr;    // pinned host word pair for small readbacks
   int cu_count = 0;
+  // Growable workspace of the keyframe calls (vgicp_connect,
+  // vgicp_submap_step): device tables and pinned host staging.
+  void *map_ws = nullptr;
+  size_t map_ws_bytes = 0;
+  void *map_host = nullptr;
+  size_t map_host_bytes = 0;
   // Kernel timing (see vgicp_ctx_set_timing).
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[VGICP_KERNEL_KINDS];
@@ -270,7 +289,12 @@ struct GraphEntry {
   int kind;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;  // factor set's replay counter at the last launch
 };
+
+// Captured graphs a factor set keeps; capturing one more drops the least
+// recently replayed.
+constexpr size_t kMaxGraphs = 8;
 
 struct vgicp_factorset_s {
   int device = 0;
@@ -287,6 +311,7 @@ struct vgicp_factorset_s {
   void *d_sorted = nullptr;  // device: ordered copies of the source clouds
   int64_t tiles_capacity = 0;       // tiles d_tiles and d_partials have room for
   std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   // System assembly: contributions to each pose (CSR over poses, entries are
   // factor * 4 + side (0 = as pose i, 1 = as pose j) + 2 for a factor whose
   // two poses coincide, on its pose-i entry) and to each

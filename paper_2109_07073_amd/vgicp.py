@@ -24,6 +24,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vgicp.h")
 
 OK, EINVAL, ENOMEM, ERANGE, ENONFINITE, EHIP, EFULL = 0, -1, -2, -3, -4, -5, -6
 REQ = {"linearize": 0, "evaluate": 1, "overlap": 2}
+GATE = {"above": 0, "at_least": 1}
+SUBMAP = {0: "start", 1: "skip", 2: "insert", 3: "close"}
 ACC = {"f32": 0, "f32_comp": 1, "f64": 2}
 KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
@@ -49,6 +51,11 @@ class COpts(ctypes.Structure):
     _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32),
                 ("fp64_kappa", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class CSubmapRules(ctypes.Structure):
+    _fields_ = [("skip_above", ctypes.c_double), ("close_below", ctypes.c_double),
+                ("max_frames", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CServerConfig(ctypes.Structure):
@@ -79,6 +86,7 @@ _PROTOS = {
                                               _i64, _i32, _i32, _P(_vp)]),
     "vgicp_factorset_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)]),
     "vgicp_factorset_destroy": (ctypes.c_int, [_vp]),
+    "vgicp_factorset_graph_count": (ctypes.c_int, [_vp, _P(_i64)]),
     "vgicp_factorset_pairs": (ctypes.c_int, [_vp, _P(_i64), _vp]),
     "vgicp_factorset_tune": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp,
                                             _i32, _P(_i32), _P(_dbl)]),
@@ -93,12 +101,21 @@ _PROTOS = {
     "vgicp_server_add_frame": (ctypes.c_int, [_vp, _vp, _vp, _i64, _dbl, _P(_i32)]),
     "vgicp_server_remove_frame": (ctypes.c_int, [_vp, _i32]),
     "vgicp_factorset_fp64_points": (ctypes.c_int, [_vp, _vp, _P(_i64)]),
+    "vgicp_factorset_reorder": (ctypes.c_int, [_vp, _vp, _vp]),
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
     "vgicp_server_poll": (ctypes.c_int, [_vp, _i64, _P(ctypes.c_int)]),
     "vgicp_server_wait": (ctypes.c_int, [_vp, _i64, _P(_dbl)]),
     "vgicp_server_stats": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)]),
+    "vgicp_connect": (ctypes.c_int, [_vp, _P(CCloud), _vp, _P(_vp), _vp, _i32, _dbl, _i32, _vp,
+                                     _vp, _vp, _P(_i32)]),
+    "vgicp_submap_step": (ctypes.c_int, [_vp, _P(CSubmapRules), _P(CCloud), _vp, _vp, _vp, _vp,
+                                         _vp, _i32, _P(_i32), _P(_dbl), _P(_dbl)]),
+    "vgicp_server_connect": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _dbl, _i32, _vp, _vp,
+                                            _vp, _P(_i32)]),
+    "vgicp_server_submap_step": (ctypes.c_int, [_vp, _P(CSubmapRules), _i32, _vp, _i32, _vp, _i32,
+                                                _vp, _i32, _P(_i32), _P(_dbl), _P(_dbl)]),
 }
 
 
@@ -181,17 +198,42 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
-def _dev_tensor(t, dtype, shape=None, name="tensor"):
+def _dev_tensor(t, dtype, shape=None, name="tensor", on_gpu=True):
+    """Check a tensor the library reads or writes: dtype, shape, contiguity,
+    then (unless on_gpu is False) that it lives on the GPU; ValueError on the
+    first mismatch, before anything reaches the library."""
     torch = _torch()
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
-    if not t.is_contiguous():
-        raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if on_gpu and not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
     return t
+
+
+def _check_outputs(out, specs):
+    """`out` must hold a tensor for every (key, dtype, shape) of `specs`."""
+    if not isinstance(out, dict):
+        raise ValueError("out must be a dict of tensors")
+    for key, dtype, shape in specs:
+        if key not in out:
+            raise ValueError(f"out is missing '{key}'")
+        _dev_tensor(out[key], dtype, shape, f"out['{key}']", on_gpu=False)
+    for key, dtype, shape in specs:
+        _dev_tensor(out[key], dtype, shape, f"out['{key}']")
+    return out
+
+
+def _graph_needs_out(use_graph, out):
+    if use_graph and out is None:
+        raise ValueError("use_graph=True needs out=: a graph is captured per output pointer "
+                         "set, so fresh outputs on every call would capture a new graph each "
+                         "time")
 
 
 def cloud_to_device(xyz, cov, device="cuda"):
@@ -374,6 +416,12 @@ class FactorSet:
     def handle(self):
         return self._h
 
+    def graph_count(self) -> int:
+        """HIP graphs the factor set holds for graph replay (at most 8)."""
+        n = ctypes.c_int64()
+        _check(_lib.vgicp_factorset_graph_count(self._h, ctypes.byref(n)))
+        return n.value
+
     def destroy(self):
         if getattr(self, "_h", None):
             _lib.vgicp_factorset_destroy(self._h)
@@ -412,9 +460,14 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     and corr (total_points,) when asked.  `out` may supply the same dict of
     preallocated tensors (needed for graph replay with stable pointers)."""
     torch = _torch()
+    _graph_needs_out(use_graph, out)
+    F = fs.n_factors
+    specs = [("H", torch.float64, (F, 12, 12)), ("b", torch.float64, (F, 12)),
+             ("e", torch.float64, (F,)), ("inliers", torch.int64, (F,))]
+    if out is not None:
+        _check_outputs(out, specs)
     _check_poses(fs, poses)
     dev = f"cuda:{ctx.device}"
-    F = fs.n_factors
     if out is None:
         out = {"H": torch.empty((F, 12, 12), dtype=torch.float64, device=dev),
                "b": torch.empty((F, 12), dtype=torch.float64, device=dev),
@@ -422,13 +475,9 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
         if with_corr:
             out["corr"] = torch.empty((fs.total_points,), dtype=torch.int32, device=dev)
-    _dev_tensor(out["H"], torch.float64, (F, 12, 12), "H")
-    _dev_tensor(out["b"], torch.float64, (F, 12), "b")
-    _dev_tensor(out["e"], torch.float64, (F,), "e")
-    _dev_tensor(out["inliers"], torch.int64, (F,), "inliers")
     corr = out.get("corr")
     if corr is not None:
-        _dev_tensor(corr, torch.int32, (fs.total_points,), "corr")
+        _dev_tensor(corr, torch.int32, (fs.total_points,), "out['corr']")
     o = _opts(accum, schedule, use_graph, resid, fp64_kappa)
     _check(_lib.vgicp_linearize_factors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                         out["H"].data_ptr(), out["b"].data_ptr(),
@@ -443,9 +492,12 @@ def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
                     resid: str = "f64", fp64_kappa: float = 0.0):
     """Matching cost e (F,) and inliers (F,) without Jacobians."""
     torch = _torch()
+    _graph_needs_out(use_graph, out)
+    F = fs.n_factors
+    if out is not None:
+        _check_outputs(out, [("e", torch.float64, (F,)), ("inliers", torch.int64, (F,))])
     _check_poses(fs, poses)
     dev = f"cuda:{ctx.device}"
-    F = fs.n_factors
     if out is None:
         out = {"e": torch.empty((F,), dtype=torch.float64, device=dev),
                "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
@@ -458,9 +510,11 @@ def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
 def overlap(ctx: Context, fs: FactorSet, poses, out=None):
     """Overlap hit counts (F,) int64 and rates (F,) float64 (Eqs. (7)-(8))."""
     torch = _torch()
+    F = fs.n_factors
+    if out is not None:
+        _check_outputs(out, [("hits", torch.int64, (F,)), ("overlap", torch.float64, (F,))])
     _check_poses(fs, poses)
     dev = f"cuda:{ctx.device}"
-    F = fs.n_factors
     if out is None:
         out = {"hits": torch.empty((F,), dtype=torch.int64, device=dev),
                "overlap": torch.empty((F,), dtype=torch.float64, device=dev)}
@@ -498,6 +552,15 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
     return best.value, ms.value
 
 
+def reorder_by_target(ctx: Context, fs: FactorSet, poses):
+    """Give every factor its own copy of its source points in the order of the
+    target voxels they fall in at `poses` (vgicp_factorset_reorder);
+    synchronizes.  Results change only by FP32 summation order."""
+    torch = _torch()
+    _check_poses(fs, poses)
+    _check(_lib.vgicp_factorset_reorder(ctx.handle, fs.handle, poses.data_ptr()), ctx.handle)
+
+
 def fp64_points(ctx: Context, fs: FactorSet) -> int:
     """Correspondences of the last linearize / evaluate call on `fs` whose
     fused covariance was formed in FP64 by the fp64_kappa gate (synchronizes)."""
@@ -532,6 +595,81 @@ def assemble_system(ctx: Context, fs: FactorSet, H, b, out=None, with_offdiag: b
                                       hoff.data_ptr() if (hoff is not None and K) else None),
            ctx.handle)
     return out
+
+
+# ------------------------------------------------------ keyframe control
+
+
+def _pose12(p, name="pose"):
+    a = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1))
+    if a.shape != (12,):
+        raise ValueError(f"{name} must hold 12 values (R row-major, then t)")
+    return a
+
+
+def _poses_n12(p, n, name="poses"):
+    a = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1, 12))
+    if a.shape[0] != n:
+        raise ValueError(f"{name} must be ({n}, 12)")
+    return a
+
+
+def _rules(skip_above=0.95, close_below=0.10, max_frames=15):
+    return CSubmapRules(float(skip_above), float(close_below), int(max_frames), 0)
+
+
+def connect(ctx: Context, xyz, pose, maps, map_poses, threshold: float = 0.025,
+            rule: str = "above"):
+    """Overlap-gated factor creation (Sec. III-C): the overlap of the device
+    cloud xyz (3, n) at `pose` (12,) against every map at map_poses (k, 12),
+    and which of them `threshold` admits (rule "above": overlap > threshold,
+    the paper's; "at_least": >=).  Returns dict of host arrays hits (k,),
+    overlap (k,), admitted (k,) bool."""
+    torch = _torch()
+    n = int(xyz.shape[1]) if xyz.dim() == 2 else -1
+    _dev_tensor(xyz, torch.float32, (3, n), "xyz")
+    maps = list(maps)
+    k = len(maps)
+    P = _pose12(pose)
+    MP = _poses_n12(map_poses, k, "map_poses")
+    if rule not in GATE:
+        raise ValueError(f"rule must be one of {sorted(GATE)}")
+    c = CCloud(xyz.data_ptr() if n else None, None, n)
+    mp = (ctypes.c_void_p * max(1, k))(*[m.handle for m in maps])
+    hits = np.zeros(max(k, 1), np.int64)
+    ov = np.zeros(max(k, 1), np.float64)
+    adm = np.zeros(max(k, 1), np.int32)
+    na = ctypes.c_int32()
+    _check(_lib.vgicp_connect(ctx.handle, ctypes.byref(c), P.ctypes.data, mp, MP.ctypes.data, k,
+                              float(threshold), GATE[rule], hits.ctypes.data, ov.ctypes.data,
+                              adm.ctypes.data, ctypes.byref(na)), ctx.handle)
+    return {"hits": hits[:k], "overlap": ov[:k], "admitted": adm[:k].astype(bool)}
+
+
+def submap_step(ctx: Context, xyz, pose, first=None, first_pose=None, last=None,
+                last_pose=None, n_submap: int = 0, skip_above: float = 0.95,
+                close_below: float = 0.10, max_frames: int = 15):
+    """Local-mapping decision (Sec. III-B) for the device cloud xyz (3, n) at
+    `pose` arriving at a submap of n_submap frames whose first and last frames
+    have maps `first` and `last` at their poses.  Returns (decision,
+    overlap_first, overlap_last) with decision one of "start", "skip",
+    "insert", "close"."""
+    torch = _torch()
+    n = int(xyz.shape[1]) if xyz.dim() == 2 else -1
+    _dev_tensor(xyz, torch.float32, (3, n), "xyz")
+    r = _rules(skip_above, close_below, max_frames)
+    c = CCloud(xyz.data_ptr() if n else None, None, n)
+    P = _pose12(pose)
+    if n_submap > 0:
+        FP, LP = _pose12(first_pose, "first_pose"), _pose12(last_pose, "last_pose")
+        fh, lh, fp, lp = first.handle, last.handle, FP.ctypes.data, LP.ctypes.data
+    else:
+        fh = lh = fp = lp = None
+    d, of, ol = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.vgicp_submap_step(ctx.handle, ctypes.byref(r), ctypes.byref(c), P.ctypes.data,
+                                  fh, fp, lh, lp, int(n_submap), ctypes.byref(d),
+                                  ctypes.byref(of), ctypes.byref(ol)), ctx.handle)
+    return SUBMAP[d.value], of.value, ol.value
 
 
 # ---------------------------------------------------------------- serving
@@ -624,6 +762,47 @@ class Server:
         r.ticket = t.value
         self._inflight[r.ticket] = r
         return r
+
+    def connect(self, frame: int, pose, candidates, candidate_poses, threshold: float = 0.025,
+                rule: str = "above"):
+        """vgicp_server_connect: overlap of resident frame `frame` at `pose`
+        against the resident frames `candidates` at candidate_poses, batched
+        with the server's other requests.  Returns dict hits, overlap,
+        admitted (host arrays)."""
+        cand = np.ascontiguousarray(np.asarray(candidates, np.int32).reshape(-1))
+        k = cand.size
+        P = _pose12(pose)
+        CP = _poses_n12(candidate_poses, k, "candidate_poses")
+        if rule not in GATE:
+            raise ValueError(f"rule must be one of {sorted(GATE)}")
+        hits = np.zeros(max(k, 1), np.int64)
+        ov = np.zeros(max(k, 1), np.float64)
+        adm = np.zeros(max(k, 1), np.int32)
+        na = ctypes.c_int32()
+        _check_srv(_lib.vgicp_server_connect(self._h, int(frame), P.ctypes.data, cand.ctypes.data,
+                                             CP.ctypes.data, k, float(threshold), GATE[rule],
+                                             hits.ctypes.data, ov.ctypes.data, adm.ctypes.data,
+                                             ctypes.byref(na)), self)
+        return {"hits": hits[:k], "overlap": ov[:k], "admitted": adm[:k].astype(bool)}
+
+    def submap_step(self, frame: int, pose, first: int = -1, first_pose=None, last: int = -1,
+                    last_pose=None, n_submap: int = 0, skip_above: float = 0.95,
+                    close_below: float = 0.10, max_frames: int = 15):
+        """vgicp_server_submap_step over resident frames; returns (decision,
+        overlap_first, overlap_last)."""
+        r = _rules(skip_above, close_below, max_frames)
+        P = _pose12(pose)
+        if n_submap > 0:
+            FP, LP = _pose12(first_pose, "first_pose"), _pose12(last_pose, "last_pose")
+            fp, lp = FP.ctypes.data, LP.ctypes.data
+        else:
+            fp = lp = None
+        d, of, ol = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check_srv(_lib.vgicp_server_submap_step(self._h, ctypes.byref(r), int(frame), P.ctypes.data,
+                                                 int(first), fp, int(last), lp, int(n_submap),
+                                                 ctypes.byref(d), ctypes.byref(of),
+                                                 ctypes.byref(ol)), self)
+        return SUBMAP[d.value], of.value, ol.value
 
     def stats(self):
         v = [ctypes.c_int64() for _ in range(4)]

@@ -5,7 +5,21 @@ import numpy as np
 
 import oracle
 
-TOL = 1e-5      # relative Frobenius tolerance on H, b, e per factor (FP32 path vs FP64)
+TOL = 1e-5      # relative tolerance on every block of H and b, and on e, per factor (FP32 path vs FP64)
+
+# Sub-blocks of the 12x12 Hessian factor and the 12-vector b in the order
+# [omega_i, rho_i, omega_j, rho_j]: each 6x6 block of H split into its
+# rotation (w) and translation (r) parts.  The (w, w) blocks scale with |mu|^2
+# (10^2 - 10^3 m^2 at 10 - 40 m), so a norm over the whole factor would hide
+# an error confined to the (r, r) or cross blocks.
+_W_I, _R_I, _W_J, _R_J = slice(0, 3), slice(3, 6), slice(6, 9), slice(9, 12)
+H_BLOCKS = {
+    "Hii_ww": (_W_I, _W_I), "Hii_wr": (_W_I, _R_I), "Hii_rr": (_R_I, _R_I),
+    "Hij_ww": (_W_I, _W_J), "Hij_wr": (_W_I, _R_J), "Hij_rw": (_R_I, _W_J), "Hij_rr": (_R_I, _R_J),
+    "Hjj_ww": (_W_J, _W_J), "Hjj_wr": (_W_J, _R_J), "Hjj_rr": (_R_J, _R_J),
+}
+B_BLOCKS = {"bi_w": _W_I, "bi_r": _R_I, "bj_w": _W_J, "bj_r": _R_J}
+ELEM_FLOOR = 1e-3   # elementwise metric |d| / (|ref| + ELEM_FLOOR * max|ref|)
 
 
 def rel_fro(got, ref):
@@ -16,6 +30,46 @@ def rel_fro(got, ref):
     if den == 0.0:
         return float(num)
     return float(num / den)
+
+
+def elementwise(got, ref):
+    """max |got - ref| / (|ref| + ELEM_FLOOR * max|ref|) over the entries."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.abs(ref).max()
+    if scale == 0.0:
+        return float(np.abs(got - ref).max()) if got.size else 0.0
+    return float((np.abs(got - ref) / (np.abs(ref) + ELEM_FLOOR * scale)).max())
+
+
+def factor_errors(H, b, e, Hr, br, er):
+    """Every error metric of one factor against its reference: relative
+    Frobenius error of each H and b sub-block, the elementwise metric of H
+    and of b, the whole-factor norms and the relative error of e."""
+    out = {k: rel_fro(H[r, c], Hr[r, c]) for k, (r, c) in H_BLOCKS.items()}
+    out.update({k: rel_fro(b[r], br[r]) for k, r in B_BLOCKS.items()})
+    out["H_elem"] = elementwise(H, Hr)
+    out["b_elem"] = elementwise(b, br)
+    out["H"] = rel_fro(H, Hr)
+    out["b"] = rel_fro(b, br)
+    out["e"] = abs(float(e) - float(er)) / abs(float(er)) if er != 0 else abs(float(e))
+    return out
+
+
+def worst_errors(got, ref, factors=None):
+    """Worst of every metric over the factors with inliers, and the factor
+    where it occurs: {metric: (error, factor)}."""
+    idx = range(ref["H"].shape[0]) if factors is None else factors
+    worst = {}
+    for f in idx:
+        if ref["inliers"][f] == 0:
+            continue
+        errs = factor_errors(got["H"][f], got["b"][f], got["e"][f], ref["H"][f], ref["b"][f],
+                             ref["e"][f])
+        for k, v in errs.items():
+            if k not in worst or v > worst[k][0]:
+                worst[k] = (v, int(f))
+    return worst
 
 
 class GpuWorkload:
@@ -54,16 +108,22 @@ def oracle_results(w, factors=None, with_corr=True):
 
 
 def assert_linearize_parity(got, ref, tol=TOL, factors=None):
-    """Inliers bit-exact, H/b/e within `tol` relative Frobenius per factor."""
+    """Inliers bit-exact; factors without inliers exactly zero; every H and b
+    sub-block, the elementwise metric and e within `tol` of the FP64 oracle
+    per factor.  Returns {metric: (worst error, factor)} and prints the
+    worst block."""
     F = ref["H"].shape[0]
-    assert np.array_equal(got["inliers"], ref["inliers"]), \
-        np.flatnonzero(got["inliers"] != ref["inliers"])[:10]
-    worst = {"H": 0.0, "b": 0.0, "e": 0.0}
-    for f in range(F):
+    idx = range(F) if factors is None else factors
+    assert np.array_equal(np.asarray(got["inliers"])[list(idx)], np.asarray(ref["inliers"])[list(idx)]), \
+        np.flatnonzero(np.asarray(got["inliers"])[list(idx)] != np.asarray(ref["inliers"])[list(idx)])[:10]
+    for f in idx:
         if ref["inliers"][f] == 0:
             assert not np.any(got["H"][f]) and not np.any(got["b"][f]) and got["e"][f] == 0.0
-            continue
-        for k in ("H", "b", "e"):
-            worst[k] = max(worst[k], rel_fro(got[k][f], ref[k][f]))
-    assert worst["H"] <= tol and worst["b"] <= tol and worst["e"] <= tol, worst
+    worst = worst_errors(got, ref, idx)
+    if worst:
+        k = max(worst, key=lambda m: worst[m][0])
+        print(f"worst metric {k} = {worst[k][0]:.3e} (factor {worst[k][1]}); "
+              f"H {worst['H'][0]:.2e}, b {worst['b'][0]:.2e}, e {worst['e'][0]:.2e}")
+    bad = {k: v for k, v in worst.items() if not v[0] <= tol}
+    assert not bad, bad
     return worst

@@ -25,7 +25,7 @@ def test_every_header_symbol_is_exported():
 
 def test_version_and_last_error_never_null():
     lib = vg.lib()
-    assert lib.vgicp_version() >= 100
+    assert lib.vgicp_version() >= 200
     assert lib.vgicp_last_error(None) is not None
 
 
@@ -116,3 +116,60 @@ def test_server_rejects_bad_config_and_null_handles():
     assert lib.vgicp_server_wait(None, 1, None) == vg.EINVAL
     assert lib.vgicp_server_remove_frame(None, 0) == vg.EINVAL
     assert lib.vgicp_server_stats(None, None, None, None, None) == vg.EINVAL
+
+
+def test_bad_output_tensors_raise_before_any_library_call():
+    """Caller-supplied outputs of linearize / evaluate / overlap are checked
+    (dtype, shape, contiguity, device) before anything reaches the library:
+    with a context and factor set whose handles are NULL, reaching the
+    library would raise VgicpError, so a ValueError proves nothing ran."""
+    from types import SimpleNamespace
+
+    import torch
+
+    from paper_2109_07073_amd import vgicp as vg
+    ctx = SimpleNamespace(handle=None, device=0)
+    fs = SimpleNamespace(handle=None, n_factors=3, n_poses=2, total_points=10)
+    poses = torch.zeros((2, 12), dtype=torch.float64)
+    good = {"H": torch.zeros((3, 12, 12), dtype=torch.float64),
+            "b": torch.zeros((3, 12), dtype=torch.float64),
+            "e": torch.zeros(3, dtype=torch.float64),
+            "inliers": torch.zeros(3, dtype=torch.int64)}
+    cases = [
+        (vg.linearize_factors, dict(good, H=torch.zeros((2, 12, 12), dtype=torch.float64)), "shape"),
+        (vg.linearize_factors, dict(good, e=torch.zeros(3, dtype=torch.float32)), "float64"),
+        (vg.linearize_factors, {"H": good["H"]}, "missing"),
+        (vg.evaluate_errors, {"e": good["e"], "inliers": good["e"]}, "int64"),
+        (vg.evaluate_errors, {"e": torch.zeros(4, dtype=torch.float64)[::1][:3].clone()[:2],
+                              "inliers": good["inliers"]}, "shape"),
+        (vg.evaluate_errors, {"e": torch.zeros((3, 2), dtype=torch.float64)[:, 0],
+                              "inliers": good["inliers"]}, "contiguous"),
+        (vg.overlap, {"hits": good["inliers"], "overlap": good["inliers"]}, "float64"),
+        (vg.overlap, {"hits": good["inliers"][:2], "overlap": good["e"]}, "shape"),
+        # right dtype and shape, but host memory
+        (vg.overlap, {"hits": good["inliers"], "overlap": good["e"]}, "CUDA"),
+        (vg.evaluate_errors, {"e": good["e"], "inliers": good["inliers"]}, "CUDA"),
+    ]
+    for fn, out, what in cases:
+        with pytest.raises(ValueError, match=what):
+            fn(ctx, fs, poses, out=out)
+    # graph replay needs caller-owned outputs
+    with pytest.raises(ValueError, match="use_graph"):
+        vg.linearize_factors(ctx, fs, poses, use_graph=True)
+    with pytest.raises(ValueError, match="use_graph"):
+        vg.evaluate_errors(ctx, fs, poses, use_graph=True)
+
+
+def test_keyframe_calls_reject_null_handles_without_a_device():
+    lib = vg.lib()
+    r = vg._rules()
+    d = ctypes.c_int32()
+    c = vg.CCloud(None, None, 0)
+    assert lib.vgicp_connect(None, ctypes.byref(c), None, None, None, 0, 0.025, 0, None, None,
+                             None, None) == vg.EINVAL
+    assert lib.vgicp_submap_step(None, ctypes.byref(r), ctypes.byref(c), None, None, None, None,
+                                 None, 0, ctypes.byref(d), None, None) == vg.EINVAL
+    assert lib.vgicp_server_connect(None, 0, None, None, None, 0, 0.025, 0, None, None, None,
+                                    None) == vg.EINVAL
+    assert lib.vgicp_server_submap_step(None, ctypes.byref(r), 0, None, 0, None, 0, None, 0,
+                                        ctypes.byref(d), None, None) == vg.EINVAL

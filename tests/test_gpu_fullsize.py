@@ -4,7 +4,8 @@ tile, HIP graph replay on a side stream).
 
 The oracle cannot linearize every factor in a test's time, so
   * a seeded sample of 40 factors is compared with the oracle (inliers and
-    correspondences bit-exact, H, b, e within 1e-5);
+    correspondences bit-exact, every block of H and b, the elementwise
+    metric and e within 1e-5);
   * over all factors: the overlap hits equal the inliers bit for bit, the
     cost-only kernel gives the same e, H is exactly symmetric with no negative
     diagonal, e >= 0, and a factor without inliers is exactly zero;
@@ -15,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_helpers import TOL, rel_fro
+from tests.gpu_helpers import assert_linearize_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -39,11 +40,13 @@ def test_batched4500_round(full):
         fs = vg.FactorSet(ctx, src, maps, w.factors, w.poses.shape[0])
         poses = torch.from_numpy(np.ascontiguousarray(w.poses)).to("cuda")
         tile, _ = vg.tune_tiles(ctx, fs, poses)
-        out = vg.linearize_factors(ctx, fs, poses, use_graph=True)
+        out = vg.linearize_factors(ctx, fs, poses)
+        vg.linearize_factors(ctx, fs, poses, use_graph=True, out=out)
         first = {k: v.clone() for k, v in out.items()}
         for _ in range(3):
             vg.linearize_factors(ctx, fs, poses, use_graph=True, out=out)
-        ev = vg.evaluate_errors(ctx, fs, poses, use_graph=True)
+        ev = vg.evaluate_errors(ctx, fs, poses)
+        vg.evaluate_errors(ctx, fs, poses, use_graph=True, out=ev)
         ov = vg.overlap(ctx, fs, poses)
     stream.synchronize()
     print("tile", tile, "factors", fs.n_factors, "tiles", fs.n_tiles)
@@ -70,7 +73,7 @@ def test_batched4500_round(full):
     corr = outc["corr"].cpu().numpy()
     offs = np.concatenate([[0], np.cumsum(fs.source_sizes)])
     vmaps = {}
-    worst = {"H": 0.0, "b": 0.0, "e": 0.0}
+    refs = {"H": [], "b": [], "e": [], "inliers": []}
     for f in ids:
         s, t, pi, pj = w.factors[f]
         if t not in vmaps:
@@ -78,9 +81,9 @@ def test_batched4500_round(full):
         ref = oracle.linearize_factor(*w.sources[s], vmaps[t], w.poses[pi], w.poses[pj])
         assert inl[f] == ref["inliers"]
         assert np.array_equal(corr[offs[f]:offs[f + 1]], ref["corr"])
-        if ref["inliers"]:
-            worst["H"] = max(worst["H"], rel_fro(H[f], ref["H"]))
-            worst["b"] = max(worst["b"], rel_fro(b[f], ref["b"]))
-            worst["e"] = max(worst["e"], rel_fro(e[f], ref["e"]))
-    print("sampled worst relative error", worst)
-    assert max(worst.values()) <= TOL, worst
+        for k in refs:
+            refs[k].append(ref[k])
+    refs = {k: np.array(v) for k, v in refs.items()}
+    got = {"H": H[ids], "b": b[ids], "e": e[ids], "inliers": inl[ids]}
+    worst = assert_linearize_parity(got, refs)
+    print("sampled worst errors", {k: f"{v[0]:.2e}" for k, v in worst.items()})

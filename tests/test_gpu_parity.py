@@ -3,13 +3,16 @@
 Integer outputs (voxel keys and counts, correspondences, inliers, overlap
 hits) must be bit-exact; the FP32 voxel payload is compared bit-exactly too
 (both sides sum in FP64 in point order and round once).  H, b and e must lie
-within a relative 1e-5 (Frobenius norm per factor) of the FP64 oracle for
-every accumulation variant."""
+within a relative 1e-5 of the FP64 oracle for every accumulation variant,
+per factor and per block: each 6x6 block of H split into its rotation and
+translation parts, b_i and b_j split likewise, and the elementwise error
+|d| / (|ref| + 1e-3 max|ref|) of H and of b."""
 
 import numpy as np
 import pytest
 
-from synth import Workload, make_scan_workload, make_single_factor, make_tiny_workload, pose_rows
+from synth import (Workload, make_degenerate_workload, make_scan_workload, make_single_factor,
+                   make_tiny_workload, pose_rows)
 from tests.gpu_helpers import (TOL, GpuWorkload, assert_linearize_parity,
                                oracle_results, rel_fro)
 import oracle
@@ -48,6 +51,11 @@ def ragged():
 @pytest.fixture(scope="module")
 def scans():
     return make_scan_workload(cfg=2, n_frames=6, n_factors=8, n_target=20000, workers=4)
+
+
+@pytest.fixture(scope="module")
+def degenerate():
+    return make_degenerate_workload()
 
 
 @pytest.fixture(scope="module")
@@ -260,6 +268,31 @@ def test_schedules_graph_and_repeats_are_bitwise_identical(vg, ctx, ragged):
         _ = g.linearize(accum="f64")        # unrelated eager work between replays
 
 
+def test_graph_cache_stays_bounded(vg, ctx, ragged):
+    """Graph replay with a new set of output tensors on every call captures
+    a new graph each time; the factor set keeps at most 8 (least recently
+    replayed dropped), and every replay still writes the direct result."""
+    import torch
+    g = GpuWorkload(vg, ctx, ragged)
+    base = g.linearize()
+    side = torch.cuda.Stream()
+    gctx = vg.Context(0, stream=side)
+    fs = vg.FactorSet(gctx, g.src, g.maps, g.factors, g.poses.shape[0])
+    outs = []
+    with torch.cuda.stream(side):
+        for k in range(12):
+            out = vg.linearize_factors(gctx, fs, g.poses)
+            vg.linearize_factors(gctx, fs, g.poses, use_graph=True, out=out)
+            outs.append(out)
+            assert fs.graph_count() == min(k + 1, 8)
+        vg.linearize_factors(gctx, fs, g.poses, use_graph=True, out=outs[0])
+    gctx.synchronize()
+    assert fs.graph_count() == 8
+    for out in outs:
+        for k in ("H", "b", "e", "inliers"):
+            assert np.array_equal(out[k].cpu().numpy(), base[k]), k
+
+
 def test_results_do_not_depend_on_the_batch(vg, ctx, ragged):
     g = GpuWorkload(vg, ctx, ragged)
     full = g.linearize()
@@ -271,14 +304,54 @@ def test_results_do_not_depend_on_the_batch(vg, ctx, ragged):
 
 
 @pytest.mark.parametrize("accum", ACCS)
-def test_evaluate_matches_linearize(vg, ctx, scans, accum):
-    g = GpuWorkload(vg, ctx, scans)
-    lin = g.linearize(accum=accum)
-    ev = g.evaluate(accum=accum)
-    assert np.array_equal(ev["inliers"], lin["inliers"])
-    assert np.array_equal(ev["e"], lin["e"])
-    per = g.evaluate(accum=accum, schedule="per_factor")
-    assert np.array_equal(per["e"], lin["e"])
+def test_evaluate_matches_linearize_and_the_oracle(vg, ctx, scans, ragged, accum):
+    """The cost-only kernel (Eq. (3) for trial steps): e within 1e-5 of the
+    oracle's cost and inliers bit-exact, and bit-identical to the e of the
+    linearization with the same accumulation, in both schedules."""
+    for w in (scans, ragged):
+        _, ref = oracle_results(w, with_corr=False)
+        g = GpuWorkload(vg, ctx, w)
+        lin = g.linearize(accum=accum)
+        ev = g.evaluate(accum=accum)
+        assert np.array_equal(ev["inliers"], ref["inliers"])
+        worst = 0.0
+        for f in range(w.n_factors):
+            if ref["inliers"][f] == 0:
+                assert ev["e"][f] == 0.0
+            else:
+                worst = max(worst, abs(ev["e"][f] - ref["e"][f]) / ref["e"][f])
+        print(f"{w.name} evaluate {accum}: worst relative error of e {worst:.2e}")
+        assert worst <= TOL
+        assert np.array_equal(ev["inliers"], lin["inliers"])
+        assert np.array_equal(ev["e"], lin["e"])
+        per = g.evaluate(accum=accum, schedule="per_factor")
+        assert np.array_equal(per["e"], lin["e"])
+
+
+# --------------------------------------------- degenerate fused covariances
+
+@pytest.mark.parametrize("kappa", [0.0, 1e4])
+@pytest.mark.parametrize("accum", ACCS)
+def test_degenerate_fused_covariances(vg, ctx, degenerate, accum, kappa):
+    """Hits whose fused covariance is zero, rank one or two, indefinite or
+    has NaN or infinite entries: counted as inliers (correspondences
+    bit-exact), adding nothing; H, b, e match the oracle, a factor of such
+    hits alone is exactly zero, and the cost-only kernel agrees."""
+    w = degenerate
+    _, ref = oracle_results(w, with_corr=True)
+    g = GpuWorkload(vg, ctx, w)
+    got = g.linearize(accum=accum, fp64_kappa=kappa, with_corr=True)
+    assert np.array_equal(got["corr"], np.concatenate(ref["corr"]).astype(np.int32))
+    assert got["inliers"][2] == len(w.meta["kinds"][2])
+    assert not got["H"][2].any() and not got["b"][2].any() and got["e"][2] == 0.0
+    assert all(np.all(np.isfinite(got[k])) for k in ("H", "b", "e"))
+    assert_linearize_parity(got, ref)
+    # with and without the degenerate points (tiles and summation order differ)
+    for k in ("H", "b", "e"):
+        assert rel_fro(got[k][0], got[k][3]) <= TOL, k
+    ev = g.evaluate(accum=accum, fp64_kappa=kappa)
+    assert np.array_equal(ev["inliers"], ref["inliers"])
+    assert np.array_equal(ev["e"], got["e"])
 
 
 # ------------------------------------------------------------------ overlap
@@ -388,7 +461,8 @@ def test_tile_autotuning_keeps_parity(vg, ctx, scans, ragged):
     fs = vg.FactorSet(sctx, g.src, g.maps, ragged.factors, ragged.poses.shape[0])
     with torch.cuda.stream(stream):
         poses = g.poses.clone()
-        before = vg.linearize_factors(sctx, fs, poses, use_graph=True)
+        before = vg.linearize_factors(sctx, fs, poses)
+        vg.linearize_factors(sctx, fs, poses, use_graph=True, out=before)
         best, ms = vg.tune_tiles(sctx, fs, poses, candidates=[1536, 768, 2304])
         assert best in (1536, 768, 2304) and fs.tile_points == best and ms > 0
         direct = vg.linearize_factors(sctx, fs, poses)
@@ -422,8 +496,19 @@ def test_bad_arguments_raise(vg, ctx, cfg1):
         vg.linearize_factors(ctx, g.fs, g.poses.float())
     with pytest.raises(ValueError):
         vg.linearize_factors(ctx, g.fs, g.poses[:1])
+    out = vg.linearize_factors(ctx, g.fs, g.poses)
     with pytest.raises(vg.VgicpError):       # graph replay needs a side stream
+        vg.linearize_factors(ctx, g.fs, g.poses, use_graph=True, out=out)
+    with pytest.raises(ValueError):          # and caller-owned outputs
         vg.linearize_factors(ctx, g.fs, g.poses, use_graph=True)
+    bad = dict(out, e=out["e"].float())
+    with pytest.raises(ValueError):
+        vg.linearize_factors(ctx, g.fs, g.poses, out=bad)
+    with pytest.raises(ValueError):
+        vg.evaluate_errors(ctx, g.fs, g.poses, out={"e": out["e"], "inliers": out["e"]})
+    with pytest.raises(ValueError):
+        vg.overlap(ctx, g.fs, g.poses, out={"hits": out["inliers"], "overlap": out["e"][:0]})
+    ctx.synchronize()
 
 
 @pytest.mark.parametrize("n,extent,r", [(60000, 12.0, 0.25), (200000, 30.0, 0.3),
@@ -494,3 +579,63 @@ def test_point_order_changes_only_the_summation_order(vg, ctx, scans):
         if a["inliers"][f]:
             for k in ("H", "b", "e"):
                 assert rel_fro(b[k][f], a[k][f]) <= TOL, (f, k)
+
+
+def test_target_order_copies_keep_parity(vg, ctx, scans, ragged):
+    """vgicp_factorset_reorder gives every factor its own copy of its source
+    ordered by target voxel at the given poses: correspondences (in the
+    caller's point order) and inliers are unchanged, H, b, e stay within the
+    tolerance of the oracle at those poses and at poses moved afterwards, a
+    source shared by several factors is ordered per factor, and graph replay
+    after the reorder writes the direct result."""
+    import torch
+    from tests.oracle_pins import hom, rows
+    for w in (scans, ragged):
+        _, ref = oracle_results(w, with_corr=True)
+        g = GpuWorkload(vg, ctx, w)
+        before = g.linearize(with_corr=True)
+        vg.reorder_by_target(ctx, g.fs, g.poses)
+        after = g.linearize(with_corr=True)
+        assert np.array_equal(after["corr"], before["corr"])
+        assert np.array_equal(after["corr"], np.concatenate(ref["corr"]).astype(np.int32))
+        assert_linearize_parity(after, ref)
+        ov = g.overlap()
+        assert np.array_equal(ov["hits"], ref["inliers"])
+        # poses moved by 5 cm / 0.5 degrees after the reorder
+        rng = np.random.default_rng(3)
+        moved = np.array(w.poses, copy=True)
+        for p in range(moved.shape[0]):
+            T = hom(moved[p])
+            a = rng.normal(size=3)
+            a *= np.deg2rad(0.5) / np.linalg.norm(a)
+            K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+            dT = np.eye(4)
+            dT[:3, :3] = np.eye(3) + K + K @ K / 2
+            u, _, vt = np.linalg.svd(dT[:3, :3])
+            dT[:3, :3] = u @ vt
+            dT[:3, 3] = rng.normal(size=3) * 0.05 / np.sqrt(3)
+            moved[p] = rows(T @ dT)
+        wm = Workload(name=w.name + "_moved", resolution=w.resolution, sources=w.sources,
+                      targets=w.targets, poses=moved, factors=w.factors, meta={})
+        _, refm = oracle_results(wm, with_corr=True)
+        pm = torch.from_numpy(moved).to("cuda")
+        out = vg.linearize_factors(ctx, g.fs, pm, with_corr=True)
+        ctx.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        assert np.array_equal(got["corr"], np.concatenate(refm["corr"]).astype(np.int32))
+        assert_linearize_parity(got, refm)
+    # graph replay after a reorder on a side stream
+    side = torch.cuda.Stream()
+    gctx = vg.Context(0, stream=side)
+    g = GpuWorkload(vg, ctx, scans)
+    fs = vg.FactorSet(gctx, g.src, g.maps, g.factors, g.poses.shape[0])
+    with torch.cuda.stream(side):
+        out = vg.linearize_factors(gctx, fs, g.poses)
+        vg.linearize_factors(gctx, fs, g.poses, use_graph=True, out=out)
+        vg.reorder_by_target(gctx, fs, g.poses)
+        assert fs.graph_count() == 0
+        direct = vg.linearize_factors(gctx, fs, g.poses)
+        vg.linearize_factors(gctx, fs, g.poses, use_graph=True, out=out)
+    gctx.synchronize()
+    for k in ("H", "b", "e", "inliers"):
+        assert torch.equal(out[k], direct[k]), k

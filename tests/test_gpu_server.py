@@ -4,7 +4,9 @@
     split across batches, and through the factor-set path;
   * requests submitted while batches run are merged and overlap on the device;
   * the memory budget refuses frames (EFULL) and frees them on removal;
-  * requests from several host threads all complete.
+  * requests from several host threads all complete;
+  * linearize, evaluate and overlap results match the FP64 oracle alone,
+    mixed and split across batches.
 """
 
 import threading
@@ -12,7 +14,9 @@ import threading
 import numpy as np
 import pytest
 
+import oracle
 from synth import make_scan_workload
+from tests.gpu_helpers import TOL, assert_linearize_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -153,3 +157,39 @@ def test_unwaited_requests_finish_before_close(vg, scans):
         reqs = [srv.submit("linearize", fac, scans.poses) for _ in range(3)]
     for r in reqs:
         assert np.array_equal(r.H, ref.H) and np.array_equal(r.inliers, ref.inliers)
+
+
+def test_server_results_match_the_oracle(vg, scans):
+    """Each request kind against the oracle (the server's frames are the
+    workload's target clouds, used both as sources and as targets): alone,
+    then the three kinds in flight together with a second linearize request
+    over an overlapping range, every request split over 7-factor batches."""
+    maps = oracle.build_maps(scans.targets, scans.resolution)
+    ref = oracle.linearize_workload(scans.targets, maps, scans.poses, scans.factors)
+    hits, rate = oracle.overlap_workload(scans.targets, maps, scans.poses, scans.factors)
+    with vg.Server(max_batch_factors=7, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        alone = {k: srv.submit(k, fac, scans.poses).wait()
+                 for k in ("linearize", "evaluate", "overlap")}
+        mixed = {k: srv.submit(k, fac, scans.poses) for k in ("linearize", "evaluate", "overlap")}
+        part = srv.submit("linearize", fac[10:25], scans.poses)
+        for r in list(mixed.values()) + [part]:
+            r.wait()
+        st = srv.stats()
+    sub = {k: v[10:25] for k, v in ref.items()}
+    for run in (alone, mixed):
+        lin = run["linearize"]
+        assert_linearize_parity({"H": lin.H, "b": lin.b, "e": lin.e, "inliers": lin.inliers}, ref)
+        ev = run["evaluate"]
+        assert np.array_equal(ev.inliers, ref["inliers"])
+        for f in range(len(fac)):
+            if ref["inliers"][f]:
+                assert abs(ev.e[f] - ref["e"][f]) <= TOL * ref["e"][f], f
+        ov = run["overlap"]
+        assert np.array_equal(ov.inliers, hits) and np.array_equal(ov.overlap, rate)
+    assert_linearize_parity({"H": part.H, "b": part.b, "e": part.e, "inliers": part.inliers}, sub)
+    print("server stats", st)
+    assert st["max_requests_per_batch"] >= 2

@@ -369,6 +369,25 @@ def test_overlap_self_far_and_hits_equal_inliers(cfg1):
     assert hits == out["inliers"] and ov == hits / sx.shape[0]
 
 
+def test_keyframe_rules_on_hand_cases():
+    """Sec. III-B / III-C thresholds on hand-picked overlaps, including
+    equality with each threshold (strict rules do not fire on it)."""
+    rules = dict(skip_above=0.95, close_below=0.10, max_frames=15)
+    cases = [
+        ((0, 0.0, 0.0), "start"), ((0, 1.0, 1.0), "start"),
+        ((3, 0.951, 0.5), "skip"), ((3, 0.95, 0.5), "insert"), ((3, 0.95, 0.0999), "close"),
+        ((3, 0.5, 0.10), "insert"), ((14, 0.5, 0.5), "insert"), ((15, 0.5, 0.5), "close"),
+        ((15, 0.99, 0.01), "skip"), ((1, 0.2, 0.2), "insert"), ((1, 0.05, 0.05), "close"),
+    ]
+    for (n, ol, of), want in cases:
+        assert oracle.submap_decision(n, ol, of, **rules) == want, (n, ol, of)
+    assert oracle.factor_admitted(0.0251, 0.025) and not oracle.factor_admitted(0.025, 0.025)
+    assert oracle.factor_admitted(0.05, 0.05, at_least=True)
+    assert not oracle.factor_admitted(0.0499, 0.05, at_least=True)
+    # an exact rate: 1 hit in 40 points is 0.025 in FP64, on the threshold
+    assert 1 / 40 == 0.025 and not oracle.factor_admitted(1 / 40, 0.025)
+
+
 def test_workload_driver_matches_per_factor():
     w = make_tiny_workload(seed=3, n_src=[50, 80, 0], n_tgt=[90, 60, 70], resolution=0.5, n_factors=3)
     maps = oracle.build_maps(w.targets, w.resolution)
