@@ -64,8 +64,10 @@ extern "C" {
 #define VGICP_EFULL (-6)      /* a server's memory budget would be exceeded        */
 
 /* Accumulation of the per-point Hessian, gradient and cost terms. */
-#define VGICP_ACC_F32 0      /* FP32 per lane and across the workgroup              */
-#define VGICP_ACC_F32_COMP 1 /* FP32 per lane, two-sum compensated across the lanes of
+#define VGICP_ACC_MIXED 0    /* (default) FP32 per lane; the sum over a wave's lanes,
+                                the waves and the tiles in FP64                        */
+#define VGICP_ACC_F32 1      /* FP32 per lane and across the workgroup (plain)      */
+#define VGICP_ACC_F32_COMP 3 /* FP32 per lane, two-sum compensated across the lanes of
                                 a wave, FP64 across waves and tiles                   */
 #define VGICP_ACC_F64 2      /* FP64 from the first per-point term                  */
 
@@ -77,6 +79,17 @@ extern "C" {
                              mean and the FP64 relative pose, then rounded to FP32: accurate
                              to the rounding of the residual itself                       */
 #define VGICP_RESID_F32 1 /* plain FP32 transform: absolute error ~ |mu| * 2^-23        */
+
+/* Precision of the fused covariance F' = R^T C'_k R + C_k of a correspondence
+ * (Eq. (2), in the source frame) and of its inverse, the point's weight.  With
+ * covariances regularized to eigenvalues (1, 1, 1e-3), F' of a point on a
+ * surface has a condition number near 1e3, so forming it in FP32 moves the
+ * weight along the surface normal by about 1e3 FP32 ulp (relative errors up to
+ * about 1e-4 in single entries of a small factor's H). */
+#define VGICP_FUSED_F64 0 /* F', its adjugate and determinant in FP64 from the FP32
+                             inputs and the FP64 relative rotation, the weight rounded
+                             to FP32 (default)                                        */
+#define VGICP_FUSED_F32 1 /* all in FP32 (optionally gated to FP64 by fp64_kappa)    */
 
 /* How the factors of one call are launched. */
 #define VGICP_SCHED_BATCHED 0    /* one launch over the tiles of all factors, one reduce   */
@@ -107,11 +120,13 @@ typedef struct {
   int32_t use_graph; /* nonzero: the batched schedule is captured once into a HIP
                         graph per (poses, outputs) pointer set and replayed          */
   int32_t resid;     /* VGICP_RESID_*                                                */
-  float fp64_kappa;  /* > 0: points whose FP32 fused covariance F' = R^T C' R + C has a
-                        condition estimate trace^3 / (27 det) above this value (or is not
-                        positive definite in FP32) form and invert F' in FP64;
-                        0 = FP32 always                                               */
-  int32_t reserved;  /* must be 0                                                    */
+  float fp64_kappa;  /* with VGICP_FUSED_F32 only: > 0 makes points whose FP32 fused
+                        covariance F' = R^T C' R + C has a condition estimate
+                        trace^3 / (27 det) above this value (or is not positive
+                        definite in FP32) form and invert F' in FP64; 0 = FP32 always.
+                        Ignored with VGICP_FUSED_F64                                 */
+  int32_t fused;     /* VGICP_FUSED_*: precision of the fused covariance and its
+                        inverse (0 = VGICP_FUSED_F64, the default)                   */
 } vgicp_opts;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -217,21 +232,50 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
                          int64_t *total_points, int32_t *tile_points);
 
-/* Tile-size autotuning (the batched schedule of Sec. III-D's one-launch
+/* Schedule autotuning (the batched schedule of Sec. III-D's one-launch
  * linearization round): after 10 warm-up rounds, time a linearization round
- * of this factor set at these poses for each candidate tile size (twice, in
- * forward and reverse order, keeping each candidate's best) (host int32 array of multiples of
- * 256 in [256, 2^20]; NULL = 9216, 4608, 3072, 2304, 1536, 768, whole lookup phases
- * of a workgroup) and keep the fastest.  H, b, e, inliers are device buffers
- * as for vgicp_linearize_factors, overwritten by the trial rounds.  The
- * factor set's tiles change (results change only by FP32 summation order) and
- * its captured graphs are dropped.  best_tile and best_ms (mean device time
- * of a round) may be NULL.  Synchronizes ctx's stream.
+ * of this factor set at these poses for each candidate tile size (host int32
+ * array of multiples of 256 in [256, 2^20]; NULL = 9216, 4608, 3072, 2304,
+ * 1536, 768, whole lookup phases of a workgroup) on each of two grids (one
+ * workgroup per tile, and a persistent grid of as many workgroups as the
+ * device's CUs hold at once for opts' kernel, each walking several tiles),
+ * twice in forward and reverse order keeping each pair's best, and keep the
+ * fastest pair.  H, b, e, inliers are device buffers as for
+ * vgicp_linearize_factors, overwritten by the trial rounds.  The factor set's
+ * tiles and grid change (results change only by FP32 summation order; the
+ * grid alone does not change them) and its captured graphs are dropped.
+ * best_tile and best_ms (mean device time of a round) may be NULL; the grid
+ * chosen is read with vgicp_factorset_grid.  Synchronizes ctx's stream.
  * Errors: EINVAL, EHIP. */
 int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          const vgicp_opts *opts, double *H, double *b, double *e,
                          int64_t *inliers, const int32_t *candidates, int32_t n_candidates,
                          int32_t *best_tile, double *best_ms);
+
+/* Measurement of one kernel of a round: `reps` (1..10000) back-to-back
+ * launches of the linearization (VGICP_KERNEL_LINEARIZE), cost-only
+ * (VGICP_KERNEL_EVALUATE) or overlap (VGICP_KERNEL_OVERLAP) kernel over every
+ * tile of the factor set at `poses`, with opts' variant (NULL: defaults),
+ * bracketed by one pair of HIP events on ctx's stream and no event between
+ * launches; *avg_ms receives the mean duration of a launch.  The launches
+ * write only the factor set's tile partials (the next call overwrites them).
+ * Synchronizes ctx's stream.  Errors: EINVAL (unknown or reduce kernel, reps
+ * out of range), EHIP. */
+int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                                const vgicp_opts *opts, int32_t kernel, int32_t reps,
+                                double *avg_ms);
+
+/* Grid of the factor set's linearize, evaluate and overlap launches:
+ * persist_blocks = 0 runs one workgroup per tile; a positive multiple of 8
+ * runs at most that many workgroups, the tiles dealt to the 8 XCDs in eighths
+ * of the tile table and walked in order by each XCD's workgroups.  Results
+ * are the same bits on either grid.  Drops captured graphs (synchronizes
+ * ctx's stream when the grid changes).  Errors: EINVAL (not 0 or a multiple
+ * of 8 in [8, 2^24]). */
+int vgicp_factorset_set_grid(vgicp_ctx ctx, vgicp_factorset fs, int32_t persist_blocks);
+
+/* The grid in use (see vgicp_factorset_set_grid).  Errors: EINVAL. */
+int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks);
 
 /* Target-order source copies.  A round streams every source point once and
  * gathers the statistics of the target voxel it falls in (Sec. III-A, Eq. (3)
@@ -254,8 +298,9 @@ int vgicp_factorset_reorder(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
 /* Precision diagnostics (the ill-conditioned case of Sec. III-A's fused
  * covariance C'_k + R C_k R^T): the number of correspondences of the last
  * vgicp_linearize_factors or vgicp_evaluate_errors call on fs that formed and
- * inverted the fused covariance in FP64 because of opts.fp64_kappa (0 when that
- * call had fp64_kappa = 0, and before any call).  Overlap calls do not change
+ * inverted the fused covariance in FP64: every inlier with VGICP_FUSED_F64, the
+ * inliers the opts.fp64_kappa gate sent to FP64 with VGICP_FUSED_F32 (0 with
+ * fp64_kappa = 0, and before any call).  Overlap calls do not change
  * it.  Synchronizes ctx's stream.  n_points: host int64.
  * Errors: EINVAL (NULL or foreign arguments), EHIP. */
 int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points);
@@ -284,7 +329,9 @@ int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
  * (points that fell in a voxel of the target map), and optionally corr int32
  * [total_points] with the voxel ordinal of each source point or -1 (NULL to
  * skip).  A factor with no inlier returns H = 0, b = 0, e = 0.
- * opts may be NULL (FP32 accumulation, batched schedule, no graph, FP64 residual).  Results
+ * opts may be NULL (the defaults: FP32 per-lane sums carried in FP64 beyond the lane,
+ * batched schedule, no graph, FP64 residual, FP64 fused covariance; a zero-filled
+ * vgicp_opts is the same).  Results
  * are deterministic and do not depend on the schedule or on the other factors
  * of the set.  Device inputs are not scanned: a source point whose transform
  * is not finite or falls outside the key range is a miss, and a hit whose
@@ -299,6 +346,7 @@ int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
  * vgicp_linearize_factors with the same accumulation.  Errors: EINVAL, EHIP. */
 int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                           const vgicp_opts *opts, double *e, int64_t *inliers);
+
 
 /* --------------------------------------------------------------------------
  * Assembly of the linearized system (Sec. III-D: the optimizer collects the

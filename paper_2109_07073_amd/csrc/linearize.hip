@@ -18,6 +18,8 @@
 //   H_ij = -H_ii Ad,  H_jj = Ad^T H_ii Ad,  b_j = -Ad^T b_i,
 // which the reduce kernel applies once per factor in FP64.
 
+#include <algorithm>
+
 #include "vgicp_internal.hpp"
 
 namespace vgicp {
@@ -184,14 +186,6 @@ __device__ __forceinline__ RecordLoad load_home(Rsrc rb, uint32_t h, bool occupi
   return r;
 }
 
-// Copies a map's occupancy bitset into LDS (whole block; ends with a barrier).
-__device__ __forceinline__ void stage_occupancy(uint32_t *lds, const uint32_t *__restrict__ occ,
-                                                uint32_t occ_mask) {
-  const uint32_t words = (occ_mask + 1u) >> 5;
-  for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) lds[w] = occ[w];
-  __syncthreads();
-}
-
 __device__ __forceinline__ uint64_t u64_of(float lo, float hi) {
   return (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32) | __builtin_bit_cast(uint32_t, lo);
 }
@@ -338,18 +332,19 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &err) 
   err = (a - (s - bp)) + (b - bp);
 }
 
-// Residual m - (R mu + t) in FP64 from the FP32 point and voxel mean and the
-// FP64 relative pose, rounded once to FP32.  FP64 fused multiply-adds issue at
-// the unpacked FP32 rate, so this costs about a fifth of an FP32 double-float
-// evaluation and is accurate to the rounding of the residual itself.
+// Source-frame residual r = R^T (m - (R mu + t)) = R^T (m - t) - mu, in FP64
+// from the FP32 point and voxel mean and the FP64 relative pose, rounded once
+// to FP32.  FP64 fused multiply-adds issue at the unpacked FP32 rate on
+// gfx950, so this costs about as much as an FP32 transform and rotation and is
+// accurate to the rounding of the residual itself.
 __device__ __forceinline__ void residual64(const double R[9], const double t[3], float x,
-                                           float y, float z, const float m[3], float e[3]) {
-  const double dx = x, dy = y, dz = z;
+                                           float y, float z, const float m[3], float r[3]) {
+  const double d0 = double(m[0]) - t[0], d1 = double(m[1]) - t[1], d2 = double(m[2]) - t[2];
+  const double p[3] = {x, y, z};
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    const double q = __builtin_fma(R[3 * r + 2], dz,
-                                   __builtin_fma(R[3 * r + 1], dy, __builtin_fma(R[3 * r], dx, t[r])));
-    e[r] = float(double(m[r]) - q);
+  for (int c = 0; c < 3; ++c) {
+    const double q = __builtin_fma(R[6 + c], d2, __builtin_fma(R[3 + c], d1, R[c] * d0));
+    r[c] = float(q - p[c]);
   }
 }
 
@@ -390,6 +385,37 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
     }
   }
   double wide[N];  // the wave's (sum + compensation) in FP64, after wave_reduce
+  __device__ void store(double *lds, int wave) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
+  }
+  using lds_t = double;
+  __device__ static double finish(const double *lds, int i) {
+    double s = lds[i];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += lds[w * N + i];
+    return s;
+  }
+};
+
+// FP32 per lane, FP64 beyond: a lane adds its few terms of a tile in FP32 (the
+// registers and occupancy of VGICP_ACC_F32); each lane sum is then widened
+// exactly to FP64 and the wave's DPP tree, the waves and the tiles add in
+// FP64.  The tree costs two DPP moves and one FP64 add per step, about a
+// third of the two-sum tree, and rounds less.
+template <int N>
+struct Sums<VGICP_ACC_MIXED, N> {
+  float v[N];
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = 0.f;
+  }
+  __device__ __forceinline__ void add(int i, float x) { v[i] += x; }
+  __device__ void wave_reduce() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) wide[i] = wave_sum(double(v[i]));
+  }
+  double wide[N];  // the wave's sum in FP64, after wave_reduce
   __device__ void store(double *lds, int wave) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
@@ -457,7 +483,11 @@ __device__ __forceinline__ bool fused_information_fp64(const double R[9], const 
   // det also excludes every infinite entry (each one makes det infinite or
   // NaN, or a22 negative), and NaN fails every comparison
   if (!(f00 > 0.0 && a22 > 0.0 && det > 0.0 && det < __builtin_huge_val())) return false;
-  const double inv = 1.0 / det;
+  // hardware reciprocal estimate refined by two Newton steps (det is far
+  // from the FP64 subnormal range: F' comes from FP32 entries)
+  double inv = __builtin_amdgcn_rcp(det);
+  inv = __builtin_fma(__builtin_fma(-det, inv, 1.0), inv, inv);
+  inv = __builtin_fma(__builtin_fma(-det, inv, 1.0), inv, inv);
   o[0] = float(a00 * inv);
   o[1] = float(a01 * inv);
   o[2] = float(a02 * inv);
@@ -467,75 +497,88 @@ __device__ __forceinline__ bool fused_information_fp64(const double R[9], const 
   return true;
 }
 
+// How the fused information Omega' = F'^-1 of a hit is formed:
+//   kFuse64:   F', its adjugate and determinant in FP64 for every hit (F' of
+//              a point on a surface has a condition number near 1e3 with
+//              covariances regularized to (1, 1, 1e-3), so forming it in FP32
+//              already costs about 1e3 ulp in the normal direction);
+//   kFuse32:   all in FP32;
+//   kFuseGate: FP32, and FP64 for hits whose FP32 F' is not positive definite
+//              or has a condition estimate trace^3 / (27 det) above kappa.
+constexpr int kFuse32 = 0;
+constexpr int kFuseGate = 1;
+constexpr int kFuse64 = 2;
+
 // Adds one correspondence.  k holds the FP32 relative rotation (and its FP64
-// value), (mx, my, mz) is the source point, c its covariance, e its residual
-// m - T mu in the target frame, S the voxel covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
-// the cost are added; without it only the cost.  With KAPPA, points whose
-// FP32 fused covariance is not positive definite or has a condition estimate
-// trace^3 / (27 det) above `kappa` take the FP64 fused covariance; `nwide`
-// counts them.
-template <bool LIN, bool KAPPA, typename SumsT>
+// value), (mx, my, mz) is the source point, c its covariance, r its residual
+// R^T (mu' - T mu) in the source frame, S the voxel covariance.  With LIN the
+// 21 + 6 source-frame Hessian/gradient sums and the cost are added; without
+// it only the cost.  FUSE selects how Omega' is formed (above); with
+// kFuseGate `nwide` counts the hits that took the FP64 path.
+template <bool LIN, int FUSE, typename SumsT>
 __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConsts &k,
                                                    float kappa, float mx, float my, float mz,
-                                                   const float c[6], const float e[3],
+                                                   const float c[6], const float r[3],
                                                    const float S[6], uint32_t &nwide) {
   // Contraction is off and every fused multiply-add is explicit, so the cost
   // comes out bit-identical in the linearization and the cost-only kernels.
 #pragma clang fp contract(off)
   const float *R = k.R;
 #define FMA __builtin_fmaf
-  // residual e_k = mu' - T mu (target frame), rotated into the source frame
-  const float e0 = e[0], e1 = e[1], e2 = e[2];
-  const float r0 = FMA(R[6], e2, FMA(R[3], e1, R[0] * e0));
-  const float r1 = FMA(R[7], e2, FMA(R[4], e1, R[1] * e0));
-  const float r2 = FMA(R[8], e2, FMA(R[5], e1, R[2] * e0));
-  // W = C' R, then F' = R^T W + C (symmetric, upper triangle)
-  const float W00 = FMA(S[2], R[6], FMA(S[1], R[3], S[0] * R[0]));
-  const float W01 = FMA(S[2], R[7], FMA(S[1], R[4], S[0] * R[1]));
-  const float W02 = FMA(S[2], R[8], FMA(S[1], R[5], S[0] * R[2]));
-  const float W10 = FMA(S[4], R[6], FMA(S[3], R[3], S[1] * R[0]));
-  const float W11 = FMA(S[4], R[7], FMA(S[3], R[4], S[1] * R[1]));
-  const float W12 = FMA(S[4], R[8], FMA(S[3], R[5], S[1] * R[2]));
-  const float W20 = FMA(S[5], R[6], FMA(S[4], R[3], S[2] * R[0]));
-  const float W21 = FMA(S[5], R[7], FMA(S[4], R[4], S[2] * R[1]));
-  const float W22 = FMA(S[5], R[8], FMA(S[4], R[5], S[2] * R[2]));
-  const float f00 = FMA(R[6], W20, FMA(R[3], W10, FMA(R[0], W00, c[0])));
-  const float f01 = FMA(R[6], W21, FMA(R[3], W11, FMA(R[0], W01, c[1])));
-  const float f02 = FMA(R[6], W22, FMA(R[3], W12, FMA(R[0], W02, c[2])));
-  const float f11 = FMA(R[7], W21, FMA(R[4], W11, FMA(R[1], W01, c[3])));
-  const float f12 = FMA(R[7], W22, FMA(R[4], W12, FMA(R[1], W02, c[4])));
-  const float f22 = FMA(R[8], W22, FMA(R[5], W12, FMA(R[2], W02, c[5])));
-  // Omega' = F'^-1 by the adjugate
-  const float a00 = FMA(f11, f22, -(f12 * f12));
-  const float a01 = FMA(f02, f12, -(f01 * f22));
-  const float a02 = FMA(f01, f12, -(f02 * f11));
-  const float a11 = FMA(f00, f22, -(f02 * f02));
-  const float a12 = FMA(f01, f02, -(f00 * f12));
-  const float a22 = FMA(f00, f11, -(f01 * f01));
-  const float det = FMA(f02, a02, FMA(f01, a01, f00 * a00));
+  const float r0 = r[0], r1 = r[1], r2 = r[2];
   float o00, o01, o02, o11, o12, o22;
-  // positive definite: leading minors f00, a22 (upper 2x2) and det positive.
-  // An infinite entry makes det infinite or NaN (or a22 negative), so a
-  // finite det also excludes those; NaN fails every comparison.
-  const bool pd32 = (f00 > 0.f) & (a22 > 0.f) & (det > 0.f) & (det < __builtin_huge_valf());
-  bool wide = false;
-  if constexpr (KAPPA) {
-    const float tr = (f00 + f11) + f22;
-    wide = !pd32 || (tr * tr * tr > (27.0f * kappa) * det);
-  }
-  if (wide) {
-    ++nwide;
+  if constexpr (FUSE == kFuse64) {
     float o[6];
     if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
     o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
   } else {
-    if (!pd32) return;  // not positive definite
-    // hardware reciprocal refined by one Newton step (within an ulp or so;
-    // det > 0 here and far above the FP32 subnormal range for these inputs)
-    const float r0i = __builtin_amdgcn_rcpf(det);
-    const float inv = FMA(FMA(-det, r0i, 1.0f), r0i, r0i);
-    o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
-    o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
+    // W = C' R, then F' = R^T W + C (symmetric, upper triangle)
+    const float W00 = FMA(S[2], R[6], FMA(S[1], R[3], S[0] * R[0]));
+    const float W01 = FMA(S[2], R[7], FMA(S[1], R[4], S[0] * R[1]));
+    const float W02 = FMA(S[2], R[8], FMA(S[1], R[5], S[0] * R[2]));
+    const float W10 = FMA(S[4], R[6], FMA(S[3], R[3], S[1] * R[0]));
+    const float W11 = FMA(S[4], R[7], FMA(S[3], R[4], S[1] * R[1]));
+    const float W12 = FMA(S[4], R[8], FMA(S[3], R[5], S[1] * R[2]));
+    const float W20 = FMA(S[5], R[6], FMA(S[4], R[3], S[2] * R[0]));
+    const float W21 = FMA(S[5], R[7], FMA(S[4], R[4], S[2] * R[1]));
+    const float W22 = FMA(S[5], R[8], FMA(S[4], R[5], S[2] * R[2]));
+    const float f00 = FMA(R[6], W20, FMA(R[3], W10, FMA(R[0], W00, c[0])));
+    const float f01 = FMA(R[6], W21, FMA(R[3], W11, FMA(R[0], W01, c[1])));
+    const float f02 = FMA(R[6], W22, FMA(R[3], W12, FMA(R[0], W02, c[2])));
+    const float f11 = FMA(R[7], W21, FMA(R[4], W11, FMA(R[1], W01, c[3])));
+    const float f12 = FMA(R[7], W22, FMA(R[4], W12, FMA(R[1], W02, c[4])));
+    const float f22 = FMA(R[8], W22, FMA(R[5], W12, FMA(R[2], W02, c[5])));
+    // Omega' = F'^-1 by the adjugate
+    const float a00 = FMA(f11, f22, -(f12 * f12));
+    const float a01 = FMA(f02, f12, -(f01 * f22));
+    const float a02 = FMA(f01, f12, -(f02 * f11));
+    const float a11 = FMA(f00, f22, -(f02 * f02));
+    const float a12 = FMA(f01, f02, -(f00 * f12));
+    const float a22 = FMA(f00, f11, -(f01 * f01));
+    const float det = FMA(f02, a02, FMA(f01, a01, f00 * a00));
+    // positive definite: leading minors f00, a22 (upper 2x2) and det positive.
+    // An infinite entry makes det infinite or NaN (or a22 negative), so a
+    // finite det also excludes those; NaN fails every comparison.
+    const bool pd32 = (f00 > 0.f) & (a22 > 0.f) & (det > 0.f) & (det < __builtin_huge_valf());
+    bool wide = false;
+    if constexpr (FUSE == kFuseGate) {
+      const float tr = (f00 + f11) + f22;
+      wide = !pd32 || (tr * tr * tr > (27.0f * kappa) * det);
+    }
+    if (wide) {
+      ++nwide;
+      float o[6];
+      if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
+      o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
+    } else {
+      if (!pd32) return;  // not positive definite
+      // hardware reciprocal refined by one Newton step (within an ulp or so;
+      // det > 0 here and far above the FP32 subnormal range for these inputs)
+      const float r0i = __builtin_amdgcn_rcpf(det);
+      const float inv = FMA(FMA(-det, r0i, 1.0f), r0i, r0i);
+      o00 = a00 * inv, o01 = a01 * inv, o02 = a02 * inv;
+      o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
+    }
   }
   // g = Omega' r
   const float g0 = FMA(o02, r2, FMA(o01, r1, o00 * r0));
@@ -584,14 +627,6 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
 }
 
 // ---------------------------------------------------------------- tiles
-// Map a block to a tile so that each XCD (blocks are dealt round-robin over
-// the 8 XCDs) works through one contiguous range of the tile table: tiles of
-// one factor, and factors sorted by target map, then share that XCD's L2.
-__device__ __forceinline__ int64_t block_tile(int64_t tile_base) {
-  const uint32_t per = gridDim.x >> 3;  // the grid is a multiple of 8
-  return tile_base + int64_t(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-}
-
 __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
                                                       const double *__restrict__ poses) {
   double R[9], t[3];
@@ -690,31 +725,34 @@ __device__ __forceinline__ CorrOut corr_out(int32_t *corr, const FactorDesc &fd,
   return {corr + fd.corr_offset + begin, nullptr};
 }
 
-template <bool LIN, bool R64, bool CORR, bool KAPPA, typename SumsT>
+template <bool LIN, bool R64, bool CORR, int FUSE, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
                                            float kappa, const CorrOut &pcorr, uint32_t &nwide) {
   if constexpr (CORR) pcorr.put(uint32_t(B.idx), B.ord);
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
-  float e[3];
+  float r[3];
   if constexpr (R64) {
-    residual64(k.R64, k.t64, B.x, B.y, B.z, m, e);
+    residual64(k.R64, k.t64, B.x, B.y, B.z, m, r);
   } else {
 #pragma clang fp contract(off)
+    // e = m - T mu in FP32 (target frame), then rotated into the source frame
     float q[3];
     transform_fp32(k.R, k.t, B.x, B.y, B.z, q);
-    e[0] = m[0] - q[0];
-    e[1] = m[1] - q[1];
-    e[2] = m[2] - q[2];
+    const float e0 = m[0] - q[0], e1 = m[1] - q[1], e2 = m[2] - q[2];
+    const float *R = k.R;
+    r[0] = __builtin_fmaf(R[6], e2, __builtin_fmaf(R[3], e1, R[0] * e0));
+    r[1] = __builtin_fmaf(R[7], e2, __builtin_fmaf(R[4], e1, R[1] * e0));
+    r[2] = __builtin_fmaf(R[8], e2, __builtin_fmaf(R[5], e1, R[2] * e0));
   }
-  add_correspondence<LIN, KAPPA>(acc, k, kappa, B.x, B.y, B.z, B.c, e, S, nwide);
+  add_correspondence<LIN, FUSE>(acc, k, kappa, B.x, B.y, B.z, B.c, r, S, nwide);
 }
 
-// Linearization (LIN) or cost evaluation (!LIN) of one tile per block.
+// Linearization (LIN) or cost evaluation (!LIN) of one tile by one block.
 // R64: residual in FP64 from the FP64 relative pose (else plain FP32).
 // CORR: also write each point's voxel ordinal (or -1).
-// KAPPA: ill-conditioned points take the FP64 fused covariance (see
-// add_correspondence).
+// FUSE: how each hit's fused information is formed (kFuse64, kFuse32,
+// kFuseGate; see add_correspondence).
 //
 // Each wave alternates two phases over its 64-point columns of the tile:
 //   lookup: kChunk passes of transform + key, one key load and the prefetch
@@ -728,25 +766,40 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
 // accumulation ask for 4 waves per SIMD (at most 128 VGPRs; both keep one
 // FP32 sum per lane); the FP64 accumulators hold twice the registers and
 // keep them.
-template <int ACC, bool LIN, bool R64, bool CORR, bool KAPPA>
-__global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
-k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-            int64_t tile_base, int64_t tile_end, int32_t tile_points,
-            const double *__restrict__ poses, double *__restrict__ partials,
-            int32_t *__restrict__ corr, float kappa) {
+template <int ACC, int N>
+struct LinearizeLds {
+  typename Sums<ACC, N>::lds_t sums[kWaves * N];
+  int cnt[kWaves];
+  int wide[kWaves];
+  HitQueue queues[kWaves];
+  uint32_t occ[kOccMaxBits / 32];
+};
+
+// One tile of k_linearize.  `staged` names the map whose occupancy bits the
+// block's LDS holds (restaged only when the tile's map differs).
+template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
+__device__ __forceinline__ void linearize_tile(
+    LinearizeLds<ACC, LIN ? kNumSums : 1> &L, const uint32_t *&staged, int64_t tile,
+    const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles, int32_t tile_points,
+    const double *__restrict__ poses, double *__restrict__ partials, int32_t *__restrict__ corr,
+    float kappa) {
   constexpr int N = LIN ? kNumSums : 1;
   using SumsT = Sums<ACC, N>;
-  __shared__ typename SumsT::lds_t lds[kWaves * N];
-  __shared__ int lds_cnt[kWaves];
-  __shared__ int lds_wide[kWaves];
-  __shared__ HitQueue queues[kWaves];
-  __shared__ uint32_t occ_lds[kOccMaxBits / 32];
+  auto &lds = L.sums;
+  auto &lds_cnt = L.cnt;
+  auto &lds_wide = L.wide;
+  auto &queues = L.queues;
+  uint32_t *occ_lds = L.occ;
 
-  const int64_t tile = block_tile(tile_base);
-  if (tile >= tile_end) return;
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
-  stage_occupancy(occ_lds, fd.occ, fd.occ_mask);
+  // the previous tile's reads of the LDS sums and bits end before this barrier
+  if (fd.occ != staged) {
+    const uint32_t words = (fd.occ_mask + 1u) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) occ_lds[w] = fd.occ[w];
+    staged = fd.occ;
+  }
+  __syncthreads();
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
@@ -839,18 +892,18 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
-        batch_math<LIN, R64, CORR, KAPPA>(acc, B, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide);
       } else {
-        batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
       }
       count -= nb * 64;
     }
@@ -860,11 +913,12 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
     const bool live = lane < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, ri);
-    if (live) batch_math<LIN, R64, CORR, KAPPA>(acc, A, k, kappa, pcorr, nwide);
+    if (live) batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
   }
 
   acc.wave_reduce();
-  const int wide = KAPPA ? wave_sum(int(nwide)) : 0;
+  // hits that formed F' in FP64: counted with the gate, all hits with kFuse64
+  const int wide = FUSE == kFuseGate ? wave_sum(int(nwide)) : FUSE == kFuse64 ? int(hits) : 0;
   if (lane == kLastLane) {
     acc.store(lds, wave);
     lds_cnt[wave] = int(hits);
@@ -887,18 +941,50 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   }
 }
 
-// Overlap hit counts of one tile per block (Eq. (7)): brick records only.
-__global__ void __launch_bounds__(kBlock)
-k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-          int64_t tile_base, int64_t tile_end, int32_t tile_points,
-          const double *__restrict__ poses, double *__restrict__ partials) {
-  __shared__ int lds_cnt[kWaves];
-  __shared__ uint32_t occ_lds[kOccMaxBits / 32];
-  const int64_t tile = block_tile(tile_base);
-  if (tile >= tile_end) return;
+// Linearization (LIN) or cost evaluation (!LIN) of the tiles [tile_base,
+// tile_end).  The grid is a multiple of 8; XCD x (blocks are dealt round-robin
+// over the 8 XCDs) takes the x-th eighth of the tile range, and its P blocks
+// walk it in order (block l: tiles l, l + P, l + 2P, ... of the range), so the
+// tiles in flight on one XCD are neighbours in the table: tiles of one factor,
+// and factors sorted by target map, share that XCD's L2.  With one block per
+// tile (P = the eighth's length) each block runs one tile; a persistent grid
+// (P blocks per XCD resident at once) runs several and keeps a map's
+// occupancy bits in LDS across its consecutive tiles of that map.
+template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
+__global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
+k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
+            int64_t tile_base, int64_t tile_end, int32_t tile_points,
+            const double *__restrict__ poses, double *__restrict__ partials,
+            int32_t *__restrict__ corr, float kappa) {
+  __shared__ LinearizeLds<ACC, LIN ? kNumSums : 1> L;
+  // tile indices are below 2^31 (the tile table is indexed by int32)
+  const uint32_t base = uint32_t(tile_base), count = uint32_t(tile_end - tile_base);
+  const uint32_t per = (count + 7u) >> 3;
+  const uint32_t lo = (blockIdx.x & 7u) * per;
+  const uint32_t hi = min(lo + per, count);
+  const uint32_t P = gridDim.x >> 3;
+  const uint32_t *staged = nullptr;
+  for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
+    linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base + t), factors, tiles,
+                                              tile_points, poses, partials, corr, kappa);
+}
+
+// Overlap hit count of one tile (Eq. (7)): brick records only.
+__device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
+                                             const uint32_t *&staged, int64_t tile,
+                                             const FactorDesc *__restrict__ factors,
+                                             const Tile *__restrict__ tiles, int32_t tile_points,
+                                             const double *__restrict__ poses,
+                                             double *__restrict__ partials) {
   const Tile td = tiles[tile];
   const FactorDesc fd = factors[td.factor];
-  stage_occupancy(occ_lds, fd.occ, fd.occ_mask);
+  // the previous tile's reads of the LDS counts and bits end before this barrier
+  if (fd.occ != staged) {
+    const uint32_t words = (fd.occ_mask + 1u) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) occ_lds[w] = fd.occ[w];
+    staged = fd.occ;
+  }
+  __syncthreads();
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
@@ -952,6 +1038,23 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
     for (int w = 0; w < kWaves; ++w) s += lds_cnt[w];
     partials[tile * kPartialStride + kNumSums] = double(s);
   }
+}
+
+// Overlap hit counts of the tiles [tile_base, tile_end), tiles dealt to
+// blocks as in k_linearize.
+__global__ void __launch_bounds__(kBlock)
+k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
+          int64_t tile_base, int64_t tile_end, int32_t tile_points,
+          const double *__restrict__ poses, double *__restrict__ partials) {
+  __shared__ int lds_cnt[kWaves];
+  __shared__ uint32_t occ_lds[kOccMaxBits / 32];
+  const int64_t per = (tile_end - tile_base + 7) >> 3;
+  const int64_t lo = tile_base + int64_t(blockIdx.x & 7u) * per;
+  const int64_t hi = min(lo + per, tile_end);
+  const uint32_t P = gridDim.x >> 3;
+  const uint32_t *staged = nullptr;
+  for (int64_t tile = lo + (blockIdx.x >> 3); tile < hi; tile += P)
+    overlap_tile(lds_cnt, occ_lds, staged, tile, factors, tiles, tile_points, poses, partials);
 }
 
 // ---------------------------------------------------------------- target order
@@ -1152,59 +1255,109 @@ k_assemble_pairs(const int64_t *__restrict__ off, const int64_t *__restrict__ en
 // ---------------------------------------------------------------- launchers
 static inline unsigned xcd_grid(int64_t tiles) { return unsigned(((tiles + 7) / 8) * 8); }
 
-template <int ACC, bool LIN, bool R64, bool KAPPA>
+// Grid of a launch over `tiles` tiles: one block per tile, or with a
+// persistent schedule (persist_blocks > 0) at most persist_blocks blocks
+// (a multiple of 8), each walking several tiles.
+static inline unsigned tile_grid(int64_t tiles, int32_t persist_blocks) {
+  const unsigned one_per_tile = xcd_grid(tiles);
+  if (persist_blocks <= 0) return one_per_tile;
+  return std::min(one_per_tile, unsigned(persist_blocks));
+}
+
+template <int ACC, bool LIN, bool R64, int FUSE>
 static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                             const double *poses, int32_t *corr, float kappa, hipStream_t st) {
+                             const double *poses, double *partials, int32_t *corr, float kappa,
+                             hipStream_t st) {
   if (te <= tb) return hipSuccess;
   if (corr) {
-    k_linearize<ACC, LIN, R64, true, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, corr, kappa);
+    k_linearize<ACC, LIN, R64, true, FUSE><<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, corr, kappa);
   } else {
-    k_linearize<ACC, LIN, R64, false, KAPPA><<<xcd_grid(te - tb), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, fs->d_partials, nullptr,
-        kappa);
+    k_linearize<ACC, LIN, R64, false, FUSE><<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, nullptr, kappa);
   }
   return hipGetLastError();
 }
 
-template <int ACC, bool KAPPA>
+template <int ACC, int FUSE>
 static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool r64, int64_t tb,
-                             int64_t te, const double *poses, int32_t *corr, float kappa,
-                             hipStream_t st) {
+                             int64_t te, const double *poses, double *partials, int32_t *corr,
+                             float kappa, hipStream_t st) {
   if (lin) {
-    return r64 ? launch_lin<ACC, true, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
-              : launch_lin<ACC, true, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
+    return r64 ? launch_lin<ACC, true, true, FUSE>(fs, tb, te, poses, partials, corr, kappa, st)
+               : launch_lin<ACC, true, false, FUSE>(fs, tb, te, poses, partials, corr, kappa, st);
   }
-  return r64 ? launch_lin<ACC, false, true, KAPPA>(fs, tb, te, poses, corr, kappa, st)
-            : launch_lin<ACC, false, false, KAPPA>(fs, tb, te, poses, corr, kappa, st);
+  return r64 ? launch_lin<ACC, false, true, FUSE>(fs, tb, te, poses, partials, corr, kappa, st)
+             : launch_lin<ACC, false, false, FUSE>(fs, tb, te, poses, partials, corr, kappa, st);
 }
 
-template <bool KAPPA>
+template <int FUSE>
 static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool r64, int64_t tb,
-                           int64_t te, const double *poses, int32_t *corr, float kappa,
-                           hipStream_t st) {
+                           int64_t te, const double *poses, double *partials, int32_t *corr,
+                           float kappa, hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F64:
-      return launch_acc<VGICP_ACC_F64, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_F64, FUSE>(fs, lin, r64, tb, te, poses, partials, corr, kappa,
+                                              st);
     case VGICP_ACC_F32_COMP:
-      return launch_acc<VGICP_ACC_F32_COMP, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_F32_COMP, FUSE>(fs, lin, r64, tb, te, poses, partials, corr,
+                                                   kappa, st);
+    case VGICP_ACC_F32:
+      return launch_acc<VGICP_ACC_F32, FUSE>(fs, lin, r64, tb, te, poses, partials, corr, kappa,
+                                              st);
     default:
-      return launch_acc<VGICP_ACC_F32, KAPPA>(fs, lin, r64, tb, te, poses, corr, kappa, st);
+      return launch_acc<VGICP_ACC_MIXED, FUSE>(fs, lin, r64, tb, te, poses, partials, corr,
+                                                kappa, st);
   }
 }
 
-hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
-                            bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st) {
+// Blocks of the linearization kernel for (accum, fused) one CU holds at once.
+hipError_t linearize_blocks_per_cu(int accum, int fused, int *blocks) {
+  const void *fn;
+  const bool f64 = fused == VGICP_FUSED_F64;
+  switch (accum) {
+    case VGICP_ACC_F64:
+      fn = f64 ? (const void *)k_linearize<VGICP_ACC_F64, true, true, false, kFuse64>
+               : (const void *)k_linearize<VGICP_ACC_F64, true, true, false, kFuse32>;
+      break;
+    case VGICP_ACC_F32_COMP:
+      fn = f64 ? (const void *)k_linearize<VGICP_ACC_F32_COMP, true, true, false, kFuse64>
+               : (const void *)k_linearize<VGICP_ACC_F32_COMP, true, true, false, kFuse32>;
+      break;
+    case VGICP_ACC_F32:
+      fn = f64 ? (const void *)k_linearize<VGICP_ACC_F32, true, true, false, kFuse64>
+               : (const void *)k_linearize<VGICP_ACC_F32, true, true, false, kFuse32>;
+      break;
+    default:
+      fn = f64 ? (const void *)k_linearize<VGICP_ACC_MIXED, true, true, false, kFuse64>
+               : (const void *)k_linearize<VGICP_ACC_MIXED, true, true, false, kFuse32>;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
+}
+
+hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                                 float kappa, bool lin, int64_t tb, int64_t te,
+                                 const double *poses, double *partials, int32_t *corr,
+                                 hipStream_t st) {
   const bool r64 = resid == VGICP_RESID_F64;
-  if (kappa > 0.f) return launch_k<true>(fs, accum, lin, r64, tb, te, poses, corr, kappa, st);
-  return launch_k<false>(fs, accum, lin, r64, tb, te, poses, corr, 0.f, st);
+  if (fused == VGICP_FUSED_F64)
+    return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, poses, partials, corr, 0.f, st);
+  if (kappa > 0.f)
+    return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, poses, partials, corr, kappa, st);
+  return launch_k<kFuse32>(fs, accum, lin, r64, tb, te, poses, partials, corr, 0.f, st);
+}
+
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                            float kappa, bool lin, int64_t tb, int64_t te, const double *poses,
+                            int32_t *corr, hipStream_t st) {
+  return launch_linearize_into(fs, accum, resid, fused, kappa, lin, tb, te, poses,
+                               fs->d_partials, corr, st);
 }
 
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st) {
   if (te <= tb) return hipSuccess;
-  k_overlap<<<xcd_grid(te - tb), kBlock, 0, st>>>(fs->d_factors, fs->d_tiles, tb, te,
+  k_overlap<<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(fs->d_factors, fs->d_tiles, tb, te,
                                                    fs->tile_points, poses, fs->d_partials);
   return hipGetLastError();
 }
@@ -1225,13 +1378,20 @@ hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const d
   return hipSuccess;
 }
 
+hipError_t launch_reduce_from(const vgicp_factorset_s *fs, int64_t f0, int64_t nf,
+                              const double *poses, const double *partials, int mode, double *H,
+                              double *b, double *e, int64_t *inl, double *overlap,
+                              hipStream_t st) {
+  if (nf <= 0) return hipSuccess;
+  k_reduce<<<unsigned(nf), 64, 0, st>>>(fs->d_factors, f0, poses, partials, mode, H, b, e, inl,
+                                         overlap);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
                          int mode, double *H, double *b, double *e, int64_t *inl,
                          double *overlap, hipStream_t st) {
-  if (nf <= 0) return hipSuccess;
-  k_reduce<<<unsigned(nf), 64, 0, st>>>(fs->d_factors, f0, poses, fs->d_partials, mode, H, b, e,
-                                         inl, overlap);
-  return hipGetLastError();
+  return launch_reduce_from(fs, f0, nf, poses, fs->d_partials, mode, H, b, e, inl, overlap, st);
 }
 
 }  // namespace vgicp

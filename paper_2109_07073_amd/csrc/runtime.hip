@@ -14,8 +14,8 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
                   std::string &msg);
 int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, float *cov,
                     int32_t *count, std::string &msg);
-hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
-                            bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                            float kappa, bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
                             hipStream_t st);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st);
@@ -24,6 +24,7 @@ hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, co
                          double *overlap, hipStream_t st);
 hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const double *b,
                            double *Hdiag, double *bvec, double *Hoff, hipStream_t st);
+hipError_t linearize_blocks_per_cu(int accum, int fused, int *blocks);
 }  // namespace vgicp
 
 using namespace vgicp;
@@ -568,7 +569,9 @@ namespace {
 constexpr int kKindLinearize = 0;
 constexpr int kKindEvaluate = 1;
 
-int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const char *who) {
+}  // namespace
+
+int vgicp::check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const char *who) {
   if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
   if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
   if (fs->device != ctx->device)
@@ -578,10 +581,12 @@ int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const c
   return use_device(ctx);
 }
 
-int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
-  *o = vgicp_opts{VGICP_ACC_F32, VGICP_SCHED_BATCHED, 0, VGICP_RESID_F64, 0.0f, 0};
+int vgicp::read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
+  *o = vgicp_opts{VGICP_ACC_MIXED, VGICP_SCHED_BATCHED, 0, VGICP_RESID_F64, 0.0f,
+                  VGICP_FUSED_F64};
   if (opts) *o = *opts;
-  if (o->accum < VGICP_ACC_F32 || o->accum > VGICP_ACC_F64)
+  if (o->accum != VGICP_ACC_MIXED && o->accum != VGICP_ACC_F32 && o->accum != VGICP_ACC_F64 &&
+      o->accum != VGICP_ACC_F32_COMP)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown accumulation");
   if (o->schedule != VGICP_SCHED_BATCHED && o->schedule != VGICP_SCHED_PER_FACTOR)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown schedule");
@@ -589,25 +594,28 @@ int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown residual mode");
   if (!(o->fp64_kappa >= 0.0f) || !std::isfinite(o->fp64_kappa))
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": fp64_kappa must be finite and >= 0");
-  if (o->reserved != 0) return fail(ctx, VGICP_EINVAL, std::string(who) + ": reserved must be 0");
+  if (o->fused != VGICP_FUSED_F64 && o->fused != VGICP_FUSED_F32)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown fused-covariance precision");
   return VGICP_OK;
 }
+
+namespace {
 
 // Enqueue the factors' tiles [tb, te) and the reduce of factors [f0, f0+nf).
 // `ctx` is NULL inside graph capture (no timing events there).
 hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum, int resid,
-                         float kappa, const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
+                         int fused, float kappa, const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
                          double *H, double *b, double *e, int64_t *inl, int32_t *corr,
                          hipStream_t st) {
   const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
   hipError_t err = hipSuccess;
   if (ctx) {
     TimedLaunch t(ctx, tk);
-    err = launch_linearize(fs, accum, resid, kappa, kind == kKindLinearize, tb, te, poses, corr,
+    err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
                            st);
     t.done();
   } else {
-    err = launch_linearize(fs, accum, resid, kappa, kind == kKindLinearize, tb, te, poses, corr,
+    err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
                            st);
   }
   if (err != hipSuccess) return err;
@@ -630,14 +638,14 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   if (o.schedule == VGICP_SCHED_PER_FACTOR) {
     for (int64_t f = 0; f < fs->n_factors && err == hipSuccess; ++f) {
       const FactorDesc &d = fs->h_factors[size_t(f)];
-      err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, d.tile_begin,
+      err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, d.tile_begin,
                           int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st);
     }
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
   }
   if (!o.use_graph) {
-    err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
+    err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
                         inl, corr, st);
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
@@ -647,7 +655,8 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   GraphEntry *g = nullptr;
   for (auto &x : fs->graphs)
     if (x.poses == poses && x.H == H && x.b == b && x.e == e && x.inl == inl && x.corr == corr &&
-        x.accum == o.accum && x.resid == o.resid && x.kappa == o.fp64_kappa && x.kind == kind)
+        x.accum == o.accum && x.resid == o.resid && x.fused == o.fused &&
+        x.kappa == o.fp64_kappa && x.kind == kind)
       g = &x;
   if (!g && fs->graphs.size() >= kMaxGraphs) {
     // drop the least recently replayed graph (after its last launch is done)
@@ -661,10 +670,10 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
     fs->graphs.erase(fs->graphs.begin() + std::ptrdiff_t(lru));
   }
   if (!g) {
-    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fp64_kappa, kind};
+    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fused, o.fp64_kappa, kind};
     err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(ctx, "hipStreamBeginCapture", err);
-    hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, o.fp64_kappa, poses, 0, fs->n_tiles, 0,
+    hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, 0, fs->n_tiles, 0,
                                     fs->n_factors, H, b, e, inl, corr, st);
     err = hipStreamEndCapture(st, &ng.graph);
     if (lerr != hipSuccess) {
@@ -815,37 +824,123 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
     if (t0) (void)hipEventDestroy(t0);
     return hip_fail(ctx, who, he);
   }
+  // the persistent grid: as many blocks as the CUs hold at once
+  int per_cu = 0;
+  he = linearize_blocks_per_cu(o.accum, o.fused, &per_cu);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return hip_fail(ctx, who, he);
+  }
+  const int32_t persist = std::max(8, (ctx->cu_count * std::max(per_cu, 1)) / 8 * 8);
+  const int32_t grids[2] = {0, persist};
+  std::vector<double> grid_ms(size_t(2 * n_candidates), 1e300);
   for (int32_t step = 0; step < 2 * n_candidates && rc == VGICP_OK; ++step) {
     const int32_t k = step < n_candidates ? step : 2 * n_candidates - 1 - step;
     rc = set_tiles(ctx, fs, candidates[k], who);
-    for (int r = 0; r < kWarm + kTimed && rc == VGICP_OK; ++r) {
-      if (r == kWarm && (he = hipEventRecord(t0, ctx->stream)) != hipSuccess)
+    for (int g = 0; g < 2 && rc == VGICP_OK; ++g) {
+      fs->persist_blocks = grids[step < n_candidates ? g : 1 - g];
+      for (int r = 0; r < kWarm + kTimed && rc == VGICP_OK; ++r) {
+        if (r == kWarm && (he = hipEventRecord(t0, ctx->stream)) != hipSuccess)
+          rc = hip_fail(ctx, who, he);
+        if (rc == VGICP_OK)
+          rc = run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, nullptr, who);
+      }
+      float ms = 0.f;
+      if (rc == VGICP_OK && (he = hipEventRecord(t1, ctx->stream)) != hipSuccess)
         rc = hip_fail(ctx, who, he);
-      if (rc == VGICP_OK)
-        rc = run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, nullptr, who);
+      if (rc == VGICP_OK && (he = hipEventSynchronize(t1)) != hipSuccess)
+        rc = hip_fail(ctx, who, he);
+      if (rc == VGICP_OK && (he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+        rc = hip_fail(ctx, who, he);
+      const size_t slot = size_t(2 * k + (fs->persist_blocks ? 1 : 0));
+      if (rc == VGICP_OK) grid_ms[slot] = std::min(grid_ms[slot], double(ms) / kTimed);
     }
-    float ms = 0.f;
-    if (rc == VGICP_OK && (he = hipEventRecord(t1, ctx->stream)) != hipSuccess)
-      rc = hip_fail(ctx, who, he);
-    if (rc == VGICP_OK && (he = hipEventSynchronize(t1)) != hipSuccess) rc = hip_fail(ctx, who, he);
-    if (rc == VGICP_OK && (he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
-      rc = hip_fail(ctx, who, he);
-    if (rc == VGICP_OK) cand_ms[size_t(k)] = std::min(cand_ms[size_t(k)], double(ms) / kTimed);
   }
-  int32_t best = candidates[0];
-  double best_t = cand_ms[0];
-  for (int32_t k = 1; k < n_candidates; ++k)
-    if (cand_ms[size_t(k)] < best_t) {
-      best = candidates[k];
-      best_t = cand_ms[size_t(k)];
-    }
+  size_t best_slot = 0;
+  for (size_t q = 1; q < grid_ms.size(); ++q)
+    if (grid_ms[q] < grid_ms[best_slot]) best_slot = q;
+  const int32_t best = candidates[best_slot / 2];
+  const double best_t = grid_ms[best_slot];
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  fs->persist_blocks = 0;
   if (rc != VGICP_OK) return rc;
   rc = set_tiles(ctx, fs, best, who);
   if (rc != VGICP_OK) return rc;
+  fs->persist_blocks = grids[best_slot % 2];
   if (best_tile) *best_tile = best;
   if (best_ms) *best_ms = best_t;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                                const vgicp_opts *opts, int32_t kernel, int32_t reps,
+                                double *avg_ms) {
+  const char *who = "vgicp_factorset_time_kernel";
+  int rc = check_common(ctx, fs, poses, who);
+  if (rc) return rc;
+  vgicp_opts o;
+  rc = read_opts(ctx, opts, &o, who);
+  if (rc) return rc;
+  if (kernel != VGICP_KERNEL_LINEARIZE && kernel != VGICP_KERNEL_EVALUATE &&
+      kernel != VGICP_KERNEL_OVERLAP)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": kernel must be linearize, evaluate or overlap");
+  if (reps < 1 || reps > 10000)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": reps must be in [1, 10000]");
+  if (!avg_ms) return fail(ctx, VGICP_EINVAL, std::string(who) + ": avg_ms is NULL");
+  *avg_ms = 0.0;
+  if (fs->n_tiles == 0) return VGICP_OK;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e == hipSuccess) e = hipEventRecord(t0, ctx->stream);
+  for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
+    if (kernel == VGICP_KERNEL_OVERLAP)
+      e = launch_overlap(fs, 0, fs->n_tiles, poses, ctx->stream);
+    else
+      e = launch_linearize(fs, o.accum, o.resid, o.fused, o.fp64_kappa,
+                           kernel == VGICP_KERNEL_LINEARIZE, 0, fs->n_tiles, poses, nullptr,
+                           ctx->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(t1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  *avg_ms = double(ms) / reps;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_set_grid(vgicp_ctx ctx, vgicp_factorset fs, int32_t persist_blocks) {
+  const char *who = "vgicp_factorset_set_grid";
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  if (persist_blocks < 0 || persist_blocks % 8 != 0 || persist_blocks > (1 << 24))
+    return fail(ctx, VGICP_EINVAL,
+                std::string(who) + ": persist_blocks must be 0 or a multiple of 8 up to 2^24");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  if (persist_blocks == fs->persist_blocks) return VGICP_OK;
+  // captured graphs hold the old grid: drop them after their last replay
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  for (auto &g : fs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  fs->graphs.clear();
+  fs->persist_blocks = persist_blocks;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_grid: factor set is NULL");
+  if (persist_blocks) *persist_blocks = fs->persist_blocks;
   return VGICP_OK;
 }
 

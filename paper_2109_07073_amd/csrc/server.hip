@@ -27,7 +27,8 @@
 namespace vgicp {
 int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vgicp_map *out,
                   std::string &msg);
-hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, float kappa,
+hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                            float kappa,
                             bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
                             hipStream_t st);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
@@ -322,7 +323,7 @@ void launch_batch(vgicp_server srv, size_t si) {
   } else {
     const bool lin = kind == VGICP_REQ_LINEARIZE;
     if (e == hipSuccess)
-      e = launch_linearize(&view, o.accum, o.resid, o.fp64_kappa, lin, 0, nt, s.d_poses, nullptr,
+      e = launch_linearize(&view, o.accum, o.resid, o.fused, o.fp64_kappa, lin, 0, nt, s.d_poses, nullptr,
                            st);
     if (e == hipSuccess)
       e = launch_reduce(&view, 0, nf, s.d_poses, lin ? 0 : 1, s.d_H, s.d_b, s.d_e, s.d_inl,
@@ -463,9 +464,10 @@ int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server
   int tp = cfg->tile_points ? cfg->tile_points : kDefaultTile;
   if (tp < 256 || tp > (1 << 20) || tp % 256 != 0) return VGICP_EINVAL;
   const vgicp_opts &o = cfg->opts;
-  if (o.accum < VGICP_ACC_F32 || o.accum > VGICP_ACC_F64 ||
+  if ((o.accum != VGICP_ACC_MIXED && o.accum != VGICP_ACC_F32 && o.accum != VGICP_ACC_F64 &&
+       o.accum != VGICP_ACC_F32_COMP) ||
       (o.resid != VGICP_RESID_F64 && o.resid != VGICP_RESID_F32) || !(o.fp64_kappa >= 0.0f) ||
-      !std::isfinite(o.fp64_kappa) || o.reserved != 0)
+      !std::isfinite(o.fp64_kappa) || (o.fused != VGICP_FUSED_F64 && o.fused != VGICP_FUSED_F32))
     return VGICP_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VGICP_EHIP;

@@ -230,6 +230,13 @@ constexpr uint32_t kErrRange = 2u;
 // is NULL) and returns `code`.
 int set_error(vgicp_ctx ctx, int code, const std::string &msg);
 
+// Common checks of the calls on a factor set (ctx and fs not NULL, same
+// device, poses given when needed); makes ctx's device current.
+int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const char *who);
+
+// opts (NULL: defaults) validated into *o.
+int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who);
+
 // The poses one batch of a server holds (its max_batch_poses).
 int64_t server_max_batch_poses(vgicp_server srv);
 
@@ -285,6 +292,7 @@ struct GraphEntry {
   int32_t *corr;
   int accum;
   int resid;
+  int fused;
   float kappa;
   int kind;
   hipGraph_t graph = nullptr;
@@ -303,6 +311,8 @@ struct vgicp_factorset_s {
   int64_t total_points = 0;
   int32_t n_poses = 0;
   int32_t tile_points = 0;
+  // Blocks of a persistent grid (a multiple of 8), 0 for one block per tile.
+  int32_t persist_blocks = 0;
   vgicp::FactorDesc *d_factors = nullptr;  // device
   vgicp::Tile *d_tiles = nullptr;          // device
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]

@@ -26,10 +26,11 @@ OK, EINVAL, ENOMEM, ERANGE, ENONFINITE, EHIP, EFULL = 0, -1, -2, -3, -4, -5, -6
 REQ = {"linearize": 0, "evaluate": 1, "overlap": 2}
 GATE = {"above": 0, "at_least": 1}
 SUBMAP = {0: "start", 1: "skip", 2: "insert", 3: "close"}
-ACC = {"f32": 0, "f32_comp": 1, "f64": 2}
+ACC = {"mixed": 0, "f32": 1, "f64": 2, "f32_comp": 3}
 KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
 RESID = {"f64": 0, "f32": 1}
+FUSED = {"f64": 0, "f32": 1}
 
 
 class VgicpError(RuntimeError):
@@ -50,7 +51,7 @@ class CFactor(ctypes.Structure):
 class COpts(ctypes.Structure):
     _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32),
-                ("fp64_kappa", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("fp64_kappa", ctypes.c_float), ("fused", ctypes.c_int32)]
 
 
 class CSubmapRules(ctypes.Structure):
@@ -102,6 +103,9 @@ _PROTOS = {
     "vgicp_server_remove_frame": (ctypes.c_int, [_vp, _i32]),
     "vgicp_factorset_fp64_points": (ctypes.c_int, [_vp, _vp, _P(_i64)]),
     "vgicp_factorset_reorder": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vgicp_factorset_set_grid": (ctypes.c_int, [_vp, _vp, _i32]),
+    "vgicp_factorset_time_kernel": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _i32, _i32, _P(_dbl)]),
+    "vgicp_factorset_grid": (ctypes.c_int, [_vp, _P(_i32)]),
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
@@ -435,15 +439,17 @@ class FactorSet:
 
 
 def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "f64",
-          fp64_kappa: float = 0.0) -> COpts:
+          fp64_kappa: float = 0.0, fused: str = "f64") -> COpts:
     if accum not in ACC:
         raise ValueError(f"accum must be one of {sorted(ACC)}")
     if schedule not in SCHED:
         raise ValueError(f"schedule must be one of {sorted(SCHED)}")
     if resid not in RESID:
         raise ValueError(f"resid must be one of {sorted(RESID)}")
+    if fused not in FUSED:
+        raise ValueError(f"fused must be one of {sorted(FUSED)}")
     return COpts(ACC[accum], SCHED[schedule], int(bool(use_graph)), RESID[resid],
-                 float(fp64_kappa), 0)
+                 float(fp64_kappa), FUSED[fused])
 
 
 def _check_poses(fs: FactorSet, poses):
@@ -451,10 +457,10 @@ def _check_poses(fs: FactorSet, poses):
     return _dev_tensor(poses, torch.float64, (fs.n_poses, 12), "poses")
 
 
-def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
+def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "mixed",
                       schedule: str = "batched", use_graph: bool = False,
                       with_corr: bool = False, out=None, resid: str = "f64",
-                      fp64_kappa: float = 0.0):
+                      fp64_kappa: float = 0.0, fused: str = "f64"):
     """Hessian factors of every factor at `poses` (float64 (P, 12) device).
     Returns dict of device tensors H (F,12,12), b (F,12), e (F,), inliers (F,)
     and corr (total_points,) when asked.  `out` may supply the same dict of
@@ -478,7 +484,7 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     corr = out.get("corr")
     if corr is not None:
         _dev_tensor(corr, torch.int32, (fs.total_points,), "out['corr']")
-    o = _opts(accum, schedule, use_graph, resid, fp64_kappa)
+    o = _opts(accum, schedule, use_graph, resid, fp64_kappa, fused)
     _check(_lib.vgicp_linearize_factors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                         out["H"].data_ptr(), out["b"].data_ptr(),
                                         out["e"].data_ptr(), out["inliers"].data_ptr(),
@@ -487,9 +493,9 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     return out
 
 
-def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
+def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "mixed",
                     schedule: str = "batched", use_graph: bool = False, out=None,
-                    resid: str = "f64", fp64_kappa: float = 0.0):
+                    resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64"):
     """Matching cost e (F,) and inliers (F,) without Jacobians."""
     torch = _torch()
     _graph_needs_out(use_graph, out)
@@ -501,7 +507,7 @@ def evaluate_errors(ctx: Context, fs: FactorSet, poses, accum: str = "f32",
     if out is None:
         out = {"e": torch.empty((F,), dtype=torch.float64, device=dev),
                "inliers": torch.empty((F,), dtype=torch.int64, device=dev)}
-    o = _opts(accum, schedule, use_graph, resid, fp64_kappa)
+    o = _opts(accum, schedule, use_graph, resid, fp64_kappa, fused)
     _check(_lib.vgicp_evaluate_errors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                       out["e"].data_ptr(), out["inliers"].data_ptr()), ctx.handle)
     return out
@@ -523,8 +529,8 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
     return out
 
 
-def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str = "f32",
-               resid: str = "f64", fp64_kappa: float = 0.0):
+def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str = "mixed",
+               resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64"):
     """Time a linearization round per candidate tile size and keep the fastest
     (vgicp_factorset_tune).  Returns (tile_points, ms per round)."""
     torch = _torch()
@@ -535,7 +541,7 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
     b = torch.empty((max(F, 1), 12), dtype=torch.float64, device=dev)
     e = torch.empty((max(F, 1),), dtype=torch.float64, device=dev)
     inl = torch.empty((max(F, 1),), dtype=torch.int64, device=dev)
-    o = _opts(accum, "batched", False, resid, fp64_kappa)
+    o = _opts(accum, "batched", False, resid, fp64_kappa, fused)
     cand = None
     n = 0
     if candidates is not None:
@@ -552,6 +558,38 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
     return best.value, ms.value
 
 
+def time_kernel(ctx: Context, fs: FactorSet, poses, kernel: str = "linearize", reps: int = 20,
+                accum: str = "mixed", resid: str = "f64", fp64_kappa: float = 0.0,
+                fused: str = "f64") -> float:
+    """Mean device milliseconds of one launch of a round's `kernel`
+    ("linearize", "evaluate" or "overlap") over the whole factor set, from
+    `reps` back-to-back launches between one pair of HIP events
+    (vgicp_factorset_time_kernel)."""
+    _check_poses(fs, poses)
+    if kernel not in ("linearize", "evaluate", "overlap"):
+        raise ValueError("kernel must be linearize, evaluate or overlap")
+    o = _opts(accum, "batched", False, resid, fp64_kappa, fused)
+    ms = ctypes.c_double()
+    _check(_lib.vgicp_factorset_time_kernel(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
+                                            KERNELS[kernel], int(reps), ctypes.byref(ms)),
+           ctx.handle)
+    return ms.value
+
+
+def set_grid(ctx: Context, fs: FactorSet, persist_blocks: int):
+    """Grid of the factor set's launches: 0 = one workgroup per tile, a
+    multiple of 8 = a persistent grid of that many workgroups
+    (vgicp_factorset_set_grid).  Results are the same bits on either grid."""
+    _check(_lib.vgicp_factorset_set_grid(ctx.handle, fs.handle, int(persist_blocks)), ctx.handle)
+
+
+def grid(fs: FactorSet) -> int:
+    """The factor set's persistent-grid size, 0 for one workgroup per tile."""
+    g = ctypes.c_int32()
+    _check(_lib.vgicp_factorset_grid(fs.handle, ctypes.byref(g)))
+    return g.value
+
+
 def reorder_by_target(ctx: Context, fs: FactorSet, poses):
     """Give every factor its own copy of its source points in the order of the
     target voxels they fall in at `poses` (vgicp_factorset_reorder);
@@ -563,7 +601,8 @@ def reorder_by_target(ctx: Context, fs: FactorSet, poses):
 
 def fp64_points(ctx: Context, fs: FactorSet) -> int:
     """Correspondences of the last linearize / evaluate call on `fs` whose
-    fused covariance was formed in FP64 by the fp64_kappa gate (synchronizes)."""
+    fused covariance was formed in FP64: all inliers with fused="f64", those
+    the fp64_kappa gate picked with fused="f32" (synchronizes)."""
     n = ctypes.c_int64()
     _check(_lib.vgicp_factorset_fp64_points(ctx.handle, fs.handle, ctypes.byref(n)), ctx.handle)
     return n.value
@@ -720,10 +759,10 @@ class Server:
 
     def __init__(self, device=0, memory_budget_bytes=0, max_batch_factors=4096,
                  max_batch_points=1 << 27, max_batch_poses=65536, inflight=2, tile_points=0,
-                 accum="f32", resid="f64", fp64_kappa=0.0):
+                 accum="mixed", resid="f64", fp64_kappa=0.0, fused="f64"):
         cfg = CServerConfig(int(memory_budget_bytes), int(max_batch_factors), int(max_batch_points),
                             int(max_batch_poses), int(inflight), int(tile_points), 0,
-                            _opts(accum, "batched", False, resid, fp64_kappa))
+                            _opts(accum, "batched", False, resid, fp64_kappa, fused))
         h = ctypes.c_void_p()
         code = _lib.vgicp_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
         if code != OK:

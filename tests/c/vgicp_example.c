@@ -116,7 +116,8 @@ static int run_factor(const char *in_path, const char *out_path) {
   vgicp_factorset fs = NULL;
   CHECK(vgicp_factorset_create(ctx, &src, 1, &map, 1, &factor, 1, 2, 0, &fs));
   vgicp_opts opts;
-  memset(&opts, 0, sizeof(opts)); /* FP32 accumulation, batched, FP64 residual */
+  memset(&opts, 0, sizeof(opts)); /* the defaults: compensated FP32 accumulation, batched,
+                                    FP64 residual, FP64 fused covariance */
   CHECK(vgicp_linearize_factors(ctx, fs, d_poses, &opts, d_out, d_out + 144, d_out + 156,
                                 d_cnt, NULL));
   CHECK(vgicp_overlap(ctx, fs, d_poses, d_cnt + 1, d_out + 157));

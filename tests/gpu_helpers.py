@@ -7,6 +7,27 @@ import oracle
 
 TOL = 1e-5      # relative tolerance on every block of H and b, and on e, per factor (FP32 path vs FP64)
 
+# Tolerance of the opt-in all-FP32 fused covariance (fused="f32").  With
+# covariances regularized to (1, 1, 1e-3), F' of a surface point has
+# eigenvalues near (2, 2, 2e-3); forming it in FP32 perturbs its entries by
+# about 2^-24 * |F'| ~ 1.2e-7, the small eigenvalue by ~6e-5 of itself, and so
+# the weight along the normal by up to ~1e-4 relative, point by point.  Block
+# and elementwise errors of a small factor reach a few 1e-5; 2e-4 bounds them.
+FUSED32_TOL = 2e-4
+
+# Elementwise tolerance of the plain FP32 accumulation (accum="f32"): a tile's
+# 256 lane sums pass through a six-level FP32 DPP tree and an FP32 sum over 4
+# waves, each level rounding at 2^-24 of the partial sum.  An entry whose
+# terms cancel down to the metric's floor (1e-3 of the factor's largest entry)
+# carries that rounding amplified up to 1e3 times: about sqrt(8) * 6e-8 * 1e3
+# = 1.7e-4 at worst.  The compensated and FP64 accumulations stay at TOL.
+ACC32_ELEM_TOL = 1e-4
+
+
+def elem_tol_for(accum):
+    """Elementwise tolerance for an accumulation variant (None: TOL)."""
+    return ACC32_ELEM_TOL if accum == "f32" else None
+
 # Sub-blocks of the 12x12 Hessian factor and the 12-vector b in the order
 # [omega_i, rho_i, omega_j, rho_j]: each 6x6 block of H split into its
 # rotation (w) and translation (r) parts.  The (w, w) blocks scale with |mu|^2
@@ -107,11 +128,11 @@ def oracle_results(w, factors=None, with_corr=True):
     return maps, oracle.linearize_workload(w.sources, maps, w.poses, f, with_corr=with_corr)
 
 
-def assert_linearize_parity(got, ref, tol=TOL, factors=None):
+def assert_linearize_parity(got, ref, tol=TOL, factors=None, elem_tol=None):
     """Inliers bit-exact; factors without inliers exactly zero; every H and b
     sub-block, the elementwise metric and e within `tol` of the FP64 oracle
-    per factor.  Returns {metric: (worst error, factor)} and prints the
-    worst block."""
+    per factor (the elementwise metric within `elem_tol` when given).
+    Returns {metric: (worst error, factor)} and prints the worst block."""
     F = ref["H"].shape[0]
     idx = range(F) if factors is None else factors
     assert np.array_equal(np.asarray(got["inliers"])[list(idx)], np.asarray(ref["inliers"])[list(idx)]), \
@@ -124,6 +145,7 @@ def assert_linearize_parity(got, ref, tol=TOL, factors=None):
         k = max(worst, key=lambda m: worst[m][0])
         print(f"worst metric {k} = {worst[k][0]:.3e} (factor {worst[k][1]}); "
               f"H {worst['H'][0]:.2e}, b {worst['b'][0]:.2e}, e {worst['e'][0]:.2e}")
-    bad = {k: v for k, v in worst.items() if not v[0] <= tol}
+    lim = {k: (elem_tol if elem_tol is not None and k.endswith("_elem") else tol) for k in worst}
+    bad = {k: v for k, v in worst.items() if not v[0] <= lim[k]}
     assert not bad, bad
     return worst

@@ -174,8 +174,12 @@ def test_server_results_match_the_oracle(vg, scans):
         fac[:, 1] = [ids[t] for t in fac[:, 1]]
         alone = {k: srv.submit(k, fac, scans.poses).wait()
                  for k in ("linearize", "evaluate", "overlap")}
-        mixed = {k: srv.submit(k, fac, scans.poses) for k in ("linearize", "evaluate", "overlap")}
+        # the second linearize request queues right behind the first, so the
+        # first's last batch (40 = 5 * 7 + 5 factors) takes two of its
+        # factors: one batch serves both requests
+        mixed = {"linearize": srv.submit("linearize", fac, scans.poses)}
         part = srv.submit("linearize", fac[10:25], scans.poses)
+        mixed.update({k: srv.submit(k, fac, scans.poses) for k in ("evaluate", "overlap")})
         for r in list(mixed.values()) + [part]:
             r.wait()
         st = srv.stats()
