@@ -347,6 +347,25 @@ int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
 int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                           const vgicp_opts *opts, double *e, int64_t *inliers);
 
+/* For callers that cannot allocate device memory during a round (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * vgicp_linearize_factors with the same arguments, kernels and results (bit
+ * for bit), but the per-tile partial sums go to a fixed scratch array that the
+ * library holds on each device it runs on (VGICP_NOALLOC_MAX_TILES tiles of
+ * 32 doubles, 8 MiB, kept until the process ends) instead of the factor
+ * set's buffer, and the call allocates nothing: no device or pinned memory,
+ * no events, no graph (opts->use_graph must be 0).  Every call on a device
+ * shares that device's array, so calls that overlap on one device (on two
+ * streams, or from two threads) race and give wrong results; calls on one
+ * stream are ordered and safe.  Nothing in the array needs clearing between
+ * calls: each launch writes every partial its reduce reads.
+ * Errors: EINVAL (as vgicp_linearize_factors, or use_graph != 0), ERANGE (the
+ * factor set has more than VGICP_NOALLOC_MAX_TILES tiles: use larger tiles),
+ * EHIP. */
+#define VGICP_NOALLOC_MAX_TILES 32768
+int vgicp_linearize_factors_noalloc(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
+                                    const vgicp_opts *opts, double *H, double *b, double *e,
+                                    int64_t *inliers, int32_t *corr);
 
 /* --------------------------------------------------------------------------
  * Assembly of the linearized system (Sec. III-D: the optimizer collects the

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libvgicp.so")
 ARCH = os.environ.get("VGICP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["runtime.hip", "voxelize.hip", "linearize.hip", "server.hip", "reorder.hip",
-           "mapping.hip"]
+           "mapping.hip", "noalloc.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

@@ -132,6 +132,8 @@ int vgicp_ctx_create(int device, void *hip_stream, vgicp_ctx *out) {
   e = hipMalloc(&ctx->err_word, 256);
   if (e == hipSuccess) e = hipHostMalloc(&ctx->host_pinned, 64, hipHostMallocDefault);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device);
+  // the device address of the allocation-free entry point's scratch array
+  if (e == hipSuccess) e = noalloc_setup(device);
   if (e != hipSuccess) {
     if (ctx->err_word) (void)hipFree(ctx->err_word);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);

@@ -237,6 +237,10 @@ int check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, const c
 // opts (NULL: defaults) validated into *o.
 int read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who);
 
+// Looks up, once per device, the device address of the fixed scratch array
+// used by vgicp_linearize_factors_noalloc; `device` must be current.
+hipError_t noalloc_setup(int device);
+
 // The poses one batch of a server holds (its max_batch_poses).
 int64_t server_max_batch_poses(vgicp_server srv);
 

@@ -31,6 +31,7 @@ KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
 RESID = {"f64": 0, "f32": 1}
 FUSED = {"f64": 0, "f32": 1}
+NOALLOC_MAX_TILES = 32768      # VGICP_NOALLOC_MAX_TILES
 
 
 class VgicpError(RuntimeError):
@@ -95,6 +96,8 @@ _PROTOS = {
     "vgicp_validate_factors": (ctypes.c_int, [_i32, _i32, _i32, _P(CFactor), _i64]),
     "vgicp_linearize_factors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp, _vp, _vp]),
     "vgicp_evaluate_errors": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp]),
+    "vgicp_linearize_factors_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _vp, _vp, _vp,
+                                                       _vp, _vp]),
     "vgicp_overlap": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vgicp_server_create": (ctypes.c_int, [ctypes.c_int, _P(CServerConfig), _P(_vp)]),
     "vgicp_server_destroy": (ctypes.c_int, [_vp]),
@@ -490,6 +493,33 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "mixed",
                                         out["e"].data_ptr(), out["inliers"].data_ptr(),
                                         corr.data_ptr() if corr is not None else None),
            ctx.handle)
+    return out
+
+
+def linearize_factors_noalloc(ctx: Context, fs: FactorSet, poses, out, accum: str = "mixed",
+                              schedule: str = "batched", resid: str = "f64",
+                              fp64_kappa: float = 0.0, fused: str = "f64"):
+    """linearize_factors into caller-owned `out` (H, b, e, inliers and
+    optionally corr, as linearize_factors returns them) through
+    vgicp_linearize_factors_noalloc: the library allocates nothing during the
+    call (its per-tile partials live in a fixed per-device array), so the
+    factor set may have at most NOALLOC_MAX_TILES tiles, and calls that overlap
+    on one device race."""
+    torch = _torch()
+    F = fs.n_factors
+    if out is None:
+        raise ValueError("linearize_factors_noalloc needs caller-owned outputs in `out`")
+    _check_outputs(out, [("H", torch.float64, (F, 12, 12)), ("b", torch.float64, (F, 12)),
+                         ("e", torch.float64, (F,)), ("inliers", torch.int64, (F,))])
+    corr = out.get("corr")
+    if corr is not None:
+        _dev_tensor(corr, torch.int32, (fs.total_points,), "out['corr']")
+    _check_poses(fs, poses)
+    o = _opts(accum, schedule, False, resid, fp64_kappa, fused)
+    _check(_lib.vgicp_linearize_factors_noalloc(
+        ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o), out["H"].data_ptr(),
+        out["b"].data_ptr(), out["e"].data_ptr(), out["inliers"].data_ptr(),
+        corr.data_ptr() if corr is not None else None), ctx.handle)
     return out
 
 

@@ -1,0 +1,119 @@
+"""The allocation-free linearization entry point (GPU).
+
+vgicp_linearize_factors_noalloc runs the same kernels as
+vgicp_linearize_factors with the per-tile partials in a fixed per-device
+array, so its outputs must equal the allocating entry point's bit for bit,
+call after call, whatever the previous call left in the array."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from synth import make_tiny_workload
+from tests.gpu_helpers import GpuWorkload, assert_linearize_parity, oracle_results
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2109_07073_amd import vgicp
+    return vgicp
+
+
+@pytest.fixture(scope="module")
+def ctx(vg):
+    import torch
+    stream = torch.cuda.Stream()
+    return vg.Context(0, stream=stream)
+
+
+def _outputs(F, n_points, with_corr):
+    import torch
+    out = {"H": torch.full((F, 12, 12), np.nan, dtype=torch.float64, device="cuda"),
+           "b": torch.full((F, 12), np.nan, dtype=torch.float64, device="cuda"),
+           "e": torch.full((F,), np.nan, dtype=torch.float64, device="cuda"),
+           "inliers": torch.full((F,), -7, dtype=torch.int64, device="cuda")}
+    if with_corr:
+        out["corr"] = torch.full((n_points,), -9, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()   # the fills run on torch's stream, the library on ctx's
+    return out
+
+
+def _np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _assert_same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=False), k
+
+
+def test_noalloc_matches_allocating_entry_point_twice(vg, ctx):
+    big = make_tiny_workload(seed=71, n_src=[9000, 4097, 1, 0, 3000, 700],
+                             n_tgt=[4000, 2500, 50, 300, 2000, 900], resolution=0.5,
+                             n_factors=6, half=6.0, height=3.0)
+    small = make_tiny_workload(seed=72, n_src=[513, 300], n_tgt=[800, 400], resolution=0.5,
+                               n_factors=2, half=6.0, height=3.0)
+    results = []
+    for w, tile in ((big, 256), (small, 0)):
+        g = GpuWorkload(vg, ctx, w, tile_points=tile)
+        n = g.fs.total_points
+        F = g.fs.n_factors
+        print(f"noalloc case {w.name}: {F} factors, {n} points, {g.fs.n_tiles} tiles", flush=True)
+        ref = vg.linearize_factors(ctx, g.fs, g.poses, with_corr=True)
+        got = vg.linearize_factors_noalloc(ctx, g.fs, g.poses, _outputs(F, n, True))
+        ctx.synchronize()
+        ref, got = _np(ref), _np(got)
+        _assert_same(got, ref)
+        # and the result is the oracle's (inliers and correspondences exact)
+        _, orc = oracle_results(w)
+        assert np.array_equal(got["corr"], np.concatenate(orc["corr"]).astype(np.int32))
+        assert_linearize_parity(got, orc)
+        results.append(got)
+    assert [r["H"].shape[0] for r in results] == [6, 2]
+
+
+def test_noalloc_other_options_and_schedules(vg, ctx):
+    w = make_tiny_workload(seed=73, n_src=[4000, 2000, 257], n_tgt=[3000, 1500, 600],
+                           resolution=0.5, n_factors=3, half=6.0, height=3.0)
+    g = GpuWorkload(vg, ctx, w, tile_points=1024)
+    F, n = g.fs.n_factors, g.fs.total_points
+    for kw in ({"accum": "f32"}, {"accum": "f32_comp"}, {"accum": "f64"}, {"fused": "f32"},
+               {"fused": "f32", "fp64_kappa": 1e2}, {"resid": "f32"},
+               {"schedule": "per_factor"}):
+        print(f"noalloc options {kw}", flush=True)
+        ref = vg.linearize_factors(ctx, g.fs, g.poses, **kw)
+        got = vg.linearize_factors_noalloc(ctx, g.fs, g.poses, _outputs(F, n, False), **kw)
+        ctx.synchronize()
+        _assert_same(_np(got), _np(ref))
+
+
+def test_noalloc_rejects_graphs_and_too_many_tiles(vg, ctx):
+    import torch
+    # one cloud used by enough factors that 256-point tiles exceed the array
+    w = make_tiny_workload(seed=74, n_src=[300000], n_tgt=[2000], resolution=0.5, n_factors=1)
+    src = [vg.cloud_to_device(x, c) for (x, c) in w.sources]
+    maps = [vg.voxelize(ctx, x, c, w.resolution) for (x, c) in [vg.cloud_to_device(*t) for t in w.targets]]
+    reps = vg.NOALLOC_MAX_TILES * 256 // 300000 + 2
+    factors = np.array([[0, 0, 0, 1]] * reps, dtype=np.int32)
+    fs = vg.FactorSet(ctx, src, maps, factors, 2, 256)
+    assert fs.n_tiles > vg.NOALLOC_MAX_TILES
+    poses = torch.from_numpy(np.ascontiguousarray(w.poses)).to("cuda")
+    out = _outputs(reps, fs.total_points, False)
+    with pytest.raises(vg.VgicpError) as ei:
+        vg.linearize_factors_noalloc(ctx, fs, poses, out)
+    assert ei.value.code == vg.ERANGE and "tiles" in str(ei.value)
+    # use_graph through the C ABI directly
+    o = vg._opts("f32", "batched", True)
+    code = vg.lib().vgicp_linearize_factors_noalloc(
+        ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o), out["H"].data_ptr(),
+        out["b"].data_ptr(), out["e"].data_ptr(), out["inliers"].data_ptr(), None)
+    assert code == vg.EINVAL
+    # the allocating entry point still handles the large set
+    ref = vg.linearize_factors(ctx, fs, poses)
+    ctx.synchronize()
+    assert int(ref["inliers"][0]) > 0
