@@ -899,17 +899,6 @@ def main():
     n_corr = int(inliers.sum())
     n_pts = int(fs.total_points)
 
-    # ---- warmup + timed rounds (graph replay of [linearize, reduce])
-    for _ in range(args.warmup):
-        vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt * 1e3 / args.steps
-
     # ---- round latency: device time (events) and host-visible (incl. D2H)
     dev_ms, host_ms = [], []
     host_H = torch.empty((F, 12, 12), dtype=torch.float64, pin_memory=True)
@@ -924,6 +913,18 @@ def main():
         stream.synchronize()
         host_ms.append((time.perf_counter() - h0) * 1e3)
         dev_ms.append(a.elapsed_time(b))
+
+    # ---- warmup + timed rounds (graph replay of [linearize, reduce]), right
+    # after the latency rounds so that the GPU clocks are up when timing starts
+    for _ in range(args.warmup):
+        vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
 
     # ---- kernel timing for the roofline: the linearize kernel launched
     # args.steps times back to back between one pair of HIP events on its

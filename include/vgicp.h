@@ -235,8 +235,8 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
 /* Schedule autotuning (the batched schedule of Sec. III-D's one-launch
  * linearization round): after 10 warm-up rounds, time a linearization round
  * of this factor set at these poses for each candidate tile size (host int32
- * array of multiples of 256 in [256, 2^20]; NULL = 9216, 4608, 3072, 2304,
- * 1536, 768, whole lookup phases of a workgroup) on each of two grids (one
+ * array of multiples of 256 in [256, 2^20]; NULL = 18432, 13824, 9216, 4608,
+ * 3072, 2304, 1536, 768, whole lookup phases of a workgroup) on each of two grids (one
  * workgroup per tile, and a persistent grid of as many workgroups as the
  * device's CUs hold at once for opts' kernel, each walking several tiles),
  * twice in forward and reverse order keeping each pair's best, and keep the
@@ -305,6 +305,25 @@ int vgicp_factorset_reorder(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
  * Errors: EINVAL (NULL or foreign arguments), EHIP. */
 int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points);
 
+/* Input checks.  The rounds do not scan their inputs (a source point whose
+ * transform is not finite is a miss, a hit whose fused covariance is not
+ * positive definite adds nothing), so that a round reads each input once.
+ * The checks come from passes that read the inputs anyway:
+ *   nonfinite_points, nonfinite_covs: points of the source clouds the set uses
+ *     with a non-finite coordinate, and with a non-finite covariance entry,
+ *     counted when the set was created (making its ordered copies reads every
+ *     point; the set keeps no pointer to the caller's clouds, so later changes
+ *     of those clouds are not seen);
+ *   degenerate_hits: correspondences of the last vgicp_linearize_factors or
+ *     vgicp_evaluate_errors call whose fused covariance C'_k + R C_k R^T
+ *     (Eq. (2)) was not positive definite or not finite, and so added nothing
+ *     though counted as inliers (0 before any call; synchronizes ctx's stream).
+ * Target clouds are checked by vgicp_voxelize (ENONFINITE for a non-finite
+ * point; a non-finite covariance makes its voxel's hits degenerate).  Any
+ * output may be NULL.  Errors: EINVAL, EHIP. */
+int vgicp_factorset_check(vgicp_ctx ctx, vgicp_factorset fs, int64_t *nonfinite_points,
+                          int64_t *nonfinite_covs, int64_t *degenerate_hits);
+
 /* Number of HIP graphs the factor set holds.  Graph replay (opts.use_graph)
  * captures one graph per (poses, outputs, options) set and keeps at most 8:
  * capturing another first waits for the context's stream and drops the least
@@ -333,10 +352,11 @@ int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
  * batched schedule, no graph, FP64 residual, FP64 fused covariance; a zero-filled
  * vgicp_opts is the same).  Results
  * are deterministic and do not depend on the schedule or on the other factors
- * of the set.  Device inputs are not scanned: a source point whose transform
- * is not finite or falls outside the key range is a miss, and a hit whose
- * fused covariance is not positive definite (including non-finite) adds
- * nothing but counts as an inlier.  Errors: EINVAL, EHIP. */
+ * of the set.  Device inputs are not scanned here: a source point whose
+ * transform is not finite or falls outside the key range is a miss, and a hit
+ * whose fused covariance is not positive definite (including non-finite) adds
+ * nothing but counts as an inlier; vgicp_factorset_check reports both kinds of
+ * bad input.  Errors: EINVAL, EHIP. */
 int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                             const vgicp_opts *opts, double *H, double *b, double *e,
                             int64_t *inliers, int32_t *corr);

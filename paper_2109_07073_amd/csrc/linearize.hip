@@ -290,6 +290,14 @@ struct Sums<VGICP_ACC_F32, N> {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
   }
+  // The wave's sums into lds[wave * N + i] (the wave's hit ring, `ring`, is
+  // free at this point; these forms do not use it).
+  template <typename T>
+  __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
+    (void)ring;
+    wave_reduce();
+    if (lane == kLastLane) store(lds, wave);
+  }
   using lds_t = float;
   __device__ static double finish(const float *lds, int i) {
     float s = lds[i];
@@ -314,6 +322,14 @@ struct Sums<VGICP_ACC_F64, N> {
   __device__ void store(double *lds, int wave) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
+  }
+  // The wave's sums into lds[wave * N + i] (the wave's hit ring, `ring`, is
+  // free at this point; these forms do not use it).
+  template <typename T>
+  __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
+    (void)ring;
+    wave_reduce();
+    if (lane == kLastLane) store(lds, wave);
   }
   using lds_t = double;
   __device__ static double finish(const double *lds, int i) {
@@ -389,6 +405,14 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
   }
+  // The wave's sums into lds[wave * N + i] (the wave's hit ring, `ring`, is
+  // free at this point; these forms do not use it).
+  template <typename T>
+  __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
+    (void)ring;
+    wave_reduce();
+    if (lane == kLastLane) store(lds, wave);
+  }
   using lds_t = double;
   __device__ static double finish(const double *lds, int i) {
     double s = lds[i];
@@ -400,9 +424,8 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
 
 // FP32 per lane, FP64 beyond: a lane adds its few terms of a tile in FP32 (the
 // registers and occupancy of VGICP_ACC_F32); each lane sum is then widened
-// exactly to FP64 and the wave's DPP tree, the waves and the tiles add in
-// FP64.  The tree costs two DPP moves and one FP64 add per step, about a
-// third of the two-sum tree, and rounds less.
+// exactly to FP64, and the sum over the wave's lanes, the waves and the tiles
+// are FP64.
 template <int N>
 struct Sums<VGICP_ACC_MIXED, N> {
   float v[N];
@@ -411,14 +434,44 @@ struct Sums<VGICP_ACC_MIXED, N> {
     for (int i = 0; i < N; ++i) v[i] = 0.f;
   }
   __device__ __forceinline__ void add(int i, float x) { v[i] += x; }
-  __device__ void wave_reduce() {
+  // The wave's sums in FP64 into lds[wave * N + i].  A single sum goes through
+  // the DPP tree.  The 28 sums of a linearization are transposed through the
+  // wave's hit ring instead (free at the end of a tile; 5,120 bytes): 14 sums
+  // at a time, every lane writes its 14 FP32 sums as one row (stride 15 words),
+  // then four lanes per sum each add a quarter of that sum's column, 16 values,
+  // in FP64 (exact for FP32 inputs of like magnitude), and a quad DPP step
+  // pair adds the four quarters: about 80 VALU instructions for all 28 sums
+  // against 530 for 28 DPP trees in FP64.
+  static constexpr int kGroup = 14;  // sums per pass
+  static constexpr int kStride = kGroup + 1;
+  template <typename T>
+  __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
+    if constexpr (N % kGroup != 0) {
+      (void)ring;
 #pragma unroll
-    for (int i = 0; i < N; ++i) wide[i] = wave_sum(double(v[i]));
-  }
-  double wide[N];  // the wave's sum in FP64, after wave_reduce
-  __device__ void store(double *lds, int wave) const {
+      for (int i = 0; i < N; ++i) {
+        const double w = wave_sum(double(v[i]));
+        if (lane == kLastLane) lds[wave * N + i] = w;
+      }
+    } else {
+      const uint32_t c = lane >> 2, q = lane & 3;
 #pragma unroll
-    for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
+      for (int g = 0; g < N; g += kGroup) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) ring[lane * kStride + i] = v[g + i];
+        __builtin_amdgcn_wave_barrier();
+        double sum = 0.0;
+        if (c < uint32_t(kGroup)) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sum += double(ring[(4 * r + q) * kStride + c]);
+        }
+        sum += dpp_d<0xb1>(sum);  // quad lanes (1, 0, 3, 2)
+        sum += dpp_d<0x4e>(sum);  // quad lanes (2, 3, 0, 1)
+        if (c < uint32_t(kGroup) && q == 0) lds[wave * N + g + int(c)] = sum;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
   }
   using lds_t = double;
   __device__ static double finish(const double *lds, int i) {
@@ -514,9 +567,10 @@ constexpr int kFuse64 = 2;
 // R^T (mu' - T mu) in the source frame, S the voxel covariance.  With LIN the
 // 21 + 6 source-frame Hessian/gradient sums and the cost are added; without
 // it only the cost.  FUSE selects how Omega' is formed (above); with
-// kFuseGate `nwide` counts the hits that took the FP64 path.
+// kFuseGate `nwide` counts the hits that took the FP64 path.  Returns false,
+// adding nothing, for a hit whose fused covariance is not positive definite.
 template <bool LIN, int FUSE, typename SumsT>
-__device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConsts &k,
+__device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConsts &k,
                                                    float kappa, float mx, float my, float mz,
                                                    const float c[6], const float r[3],
                                                    const float S[6], uint32_t &nwide) {
@@ -529,7 +583,7 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
   float o00, o01, o02, o11, o12, o22;
   if constexpr (FUSE == kFuse64) {
     float o[6];
-    if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
+    if (!fused_information_fp64(k.R64, S, c, o)) return false;  // not positive definite
     o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
   } else {
     // W = C' R, then F' = R^T W + C (symmetric, upper triangle)
@@ -568,10 +622,10 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
     if (wide) {
       ++nwide;
       float o[6];
-      if (!fused_information_fp64(k.R64, S, c, o)) return;  // not positive definite
+      if (!fused_information_fp64(k.R64, S, c, o)) return false;  // not positive definite
       o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
     } else {
-      if (!pd32) return;  // not positive definite
+      if (!pd32) return false;  // not positive definite
       // hardware reciprocal refined by one Newton step (within an ulp or so;
       // det > 0 here and far above the FP32 subnormal range for these inputs)
       const float r0i = __builtin_amdgcn_rcpf(det);
@@ -624,6 +678,7 @@ __device__ __forceinline__ void add_correspondence(SumsT &acc, const FactorConst
     acc.add(26, -g2);
   }
 #undef FMA
+  return true;
 }
 
 // ---------------------------------------------------------------- tiles
@@ -660,6 +715,9 @@ struct HitQueue {
   int32_t idx[kRing];   // point index in the tile
   int32_t pidx[kRing];  // index of its voxel in the target map's dense arrays
 };
+
+static_assert(64 * Sums<VGICP_ACC_MIXED, kNumSums>::kStride * sizeof(float) <= sizeof(HitQueue),
+              "the transposed wave sums fit a wave's hit ring");
 
 __device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
   e += d;  // e < kRing and d < kRing, so one wrap suffices
@@ -727,7 +785,8 @@ __device__ __forceinline__ CorrOut corr_out(int32_t *corr, const FactorDesc &fd,
 
 template <bool LIN, bool R64, bool CORR, int FUSE, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
-                                           float kappa, const CorrOut &pcorr, uint32_t &nwide) {
+                                           float kappa, const CorrOut &pcorr, uint32_t &nwide,
+                                           uint32_t &ndeg) {
   if constexpr (CORR) pcorr.put(uint32_t(B.idx), B.ord);
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
@@ -745,7 +804,9 @@ __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const Fac
     r[1] = __builtin_fmaf(R[7], e2, __builtin_fmaf(R[4], e1, R[1] * e0));
     r[2] = __builtin_fmaf(R[8], e2, __builtin_fmaf(R[5], e1, R[2] * e0));
   }
-  add_correspondence<LIN, FUSE>(acc, k, kappa, B.x, B.y, B.z, B.c, r, S, nwide);
+  const bool ok = add_correspondence<LIN, FUSE>(acc, k, kappa, B.x, B.y, B.z, B.c, r, S, nwide);
+  // hits of this batch whose fused covariance was degenerate (wave-uniform)
+  ndeg += uint32_t(__popcll(__ballot(!ok)));
 }
 
 // Linearization (LIN) or cost evaluation (!LIN) of one tile by one block.
@@ -771,6 +832,7 @@ struct LinearizeLds {
   typename Sums<ACC, N>::lds_t sums[kWaves * N];
   int cnt[kWaves];
   int wide[kWaves];
+  int deg[kWaves];
   HitQueue queues[kWaves];
   uint32_t occ[kOccMaxBits / 32];
 };
@@ -788,6 +850,7 @@ __device__ __forceinline__ void linearize_tile(
   auto &lds = L.sums;
   auto &lds_cnt = L.cnt;
   auto &lds_wide = L.wide;
+  auto &lds_deg = L.deg;
   auto &queues = L.queues;
   uint32_t *occ_lds = L.occ;
 
@@ -819,6 +882,7 @@ __device__ __forceinline__ void linearize_tile(
   uint32_t head = 0, count = 0;  // wave-uniform ring state
   uint32_t hits = 0;             // wave-uniform hit count
   uint32_t nwide = 0;            // per lane: hits with the FP64 fused covariance
+  uint32_t ndeg = 0;  // hits with a degenerate fused covariance (complete in lane 0)
 
   // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead;
   // past the tile's end the loads return zeros and the lanes are invalid).
@@ -892,18 +956,18 @@ __device__ __forceinline__ void linearize_tile(
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide, ndeg);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
-        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide, ndeg);
       } else {
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
+        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
       }
       count -= nb * 64;
     }
@@ -913,17 +977,19 @@ __device__ __forceinline__ void linearize_tile(
     const bool live = lane < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, ri);
-    if (live) batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide);
+    if (live) batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
   }
 
-  acc.wave_reduce();
+  // the ring is empty: its LDS holds the transposed sums now
+  acc.reduce_to(lds, wave, lane, reinterpret_cast<float *>(&Q));
   // hits that formed F' in FP64: counted with the gate, all hits with kFuse64
   const int wide = FUSE == kFuseGate ? wave_sum(int(nwide)) : FUSE == kFuse64 ? int(hits) : 0;
   if (lane == kLastLane) {
-    acc.store(lds, wave);
     lds_cnt[wave] = int(hits);
     lds_wide[wave] = wide;
   }
+  // lane 0 took part in every batch (the last, partial one included)
+  if (lane == 0) lds_deg[wave] = int(ndeg);
   __syncthreads();
   double *__restrict__ out = partials + tile * kPartialStride;
   if (threadIdx.x < N) {
@@ -938,6 +1004,11 @@ __device__ __forceinline__ void linearize_tile(
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += lds_wide[w];
     out[kWideSlot] = double(s);
+  } else if (threadIdx.x == 34) {
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += lds_deg[w];
+    out[kDegenerateSlot] = double(s);
   }
 }
 

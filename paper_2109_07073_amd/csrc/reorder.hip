@@ -57,22 +57,31 @@ k_morton_keys(const float *__restrict__ xyz, uint32_t n, float inv_cell,
 }
 
 // Copy point perm[i] of the cloud to position i of the ordered copy
-// (coordinates as three planes, covariances as six floats per point).
+// (coordinates as three planes, covariances as six floats per point), and
+// count the points with a non-finite coordinate (nonfinite[0]) or covariance
+// entry (nonfinite[1]): the only full pass over a factor set's inputs.
 __global__ void __launch_bounds__(kThreads)
 k_gather_points(const float *__restrict__ xyz, const float *__restrict__ cov, uint32_t n,
                 const int32_t *__restrict__ perm, float *__restrict__ xyz_out,
-                float *__restrict__ cov_out) {
+                float *__restrict__ cov_out, unsigned long long *__restrict__ nonfinite) {
   const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const uint64_t j = uint32_t(perm[i]);
-  xyz_out[i] = xyz[j];
-  xyz_out[uint64_t(n) + i] = xyz[uint64_t(n) + j];
-  xyz_out[2ull * n + i] = xyz[2ull * n + j];
+  const float x = xyz[j], y = xyz[uint64_t(n) + j], z = xyz[2ull * n + j];
+  xyz_out[i] = x;
+  xyz_out[uint64_t(n) + i] = y;
+  xyz_out[2ull * n + i] = z;
   const float2 *src = reinterpret_cast<const float2 *>(cov + 6 * j);
   float2 *dst = reinterpret_cast<float2 *>(cov_out + 6ull * i);
-  dst[0] = src[0];
-  dst[1] = src[1];
-  dst[2] = src[2];
+  const float2 c0 = src[0], c1 = src[1], c2 = src[2];
+  dst[0] = c0;
+  dst[1] = c1;
+  dst[2] = c2;
+  const bool bad_p = !(isfinite(x) && isfinite(y) && isfinite(z));
+  const bool bad_c = !(isfinite(c0.x) && isfinite(c0.y) && isfinite(c1.x) && isfinite(c1.y) &&
+                       isfinite(c2.x) && isfinite(c2.y));
+  if (bad_p) atomicAdd(&nonfinite[0], 1ull);
+  if (bad_c) atomicAdd(&nonfinite[1], 1ull);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -185,8 +194,10 @@ hipError_t reorder_by_target(vgicp_factorset_s *fs, const double *poses, hipStre
 
 hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
                                const std::vector<double> &cell, void **buffer,
-                               std::vector<SortedSource> &out, hipStream_t st) {
+                               std::vector<SortedSource> &out, hipStream_t st,
+                               int64_t *nonfinite) {
   *buffer = nullptr;
+  if (nonfinite) nonfinite[0] = nonfinite[1] = 0;
   out.assign(size_t(n_sources), SortedSource{});
   // layout: per used cloud, covariances [n][6], coordinates [3][n], permutation [n]
   size_t total = 0;
@@ -217,7 +228,7 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
   const size_t ibytes = align256(4 * size_t(nmax));
   char *tmp = nullptr;
   hipError_t e = hipMalloc(buffer, total);
-  if (e == hipSuccess) e = hipMalloc(&tmp, 2 * kbytes + ibytes + align256(sort_bytes));
+  if (e == hipSuccess) e = hipMalloc(&tmp, 2 * kbytes + ibytes + align256(sort_bytes) + 256);
   if (e != hipSuccess) {
     if (*buffer) (void)hipFree(*buffer);
     *buffer = nullptr;
@@ -227,6 +238,9 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
   uint64_t *keys_out = reinterpret_cast<uint64_t *>(tmp + kbytes);
   uint32_t *idx_in = reinterpret_cast<uint32_t *>(tmp + 2 * kbytes);
   void *sort_tmp = tmp + 2 * kbytes + ibytes;
+  unsigned long long *d_bad =
+      reinterpret_cast<unsigned long long *>(tmp + 2 * kbytes + ibytes + align256(sort_bytes));
+  e = hipMemsetAsync(d_bad, 0, 2 * sizeof(unsigned long long), st);
 
   char *base = static_cast<char *>(*buffer);
   for (int32_t s = 0; s < n_sources && e == hipSuccess; ++s) {
@@ -245,15 +259,22 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
       e = rocprim::radix_sort_pairs(sort_tmp, b, keys_in, keys_out, idx_in,
                                     reinterpret_cast<uint32_t *>(perm), n, 0, 63, st);
     if (e == hipSuccess) {
-      k_gather_points<<<grid, kThreads, 0, st>>>(c.xyz, c.cov, n, perm, xyz_s, cov_s);
+      k_gather_points<<<grid, kThreads, 0, st>>>(c.xyz, c.cov, n, perm, xyz_s, cov_s, d_bad);
       e = hipGetLastError();
     }
     out[size_t(s)] = SortedSource{xyz_s, cov_s, perm};
   }
   // the temporaries are reused cloud after cloud on the stream; free them
   // once the last gather has run
+  unsigned long long bad[2] = {0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, st);
   const hipError_t se = hipStreamSynchronize(st);
   if (e == hipSuccess) e = se;
+  if (e == hipSuccess && nonfinite) {
+    nonfinite[0] = int64_t(bad[0]);
+    nonfinite[1] = int64_t(bad[1]);
+  }
   (void)hipFree(tmp);
   if (e != hipSuccess) {
     (void)hipFree(*buffer);

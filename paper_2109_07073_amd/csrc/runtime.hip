@@ -351,8 +351,11 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
       const double r = maps[factors[f].tgt]->resolution;
       c = (c == 0.0) ? r : std::min(c, r);
     }
-    const hipError_t se =
-        make_sorted_sources(sources, n_sources, cell, &fs->d_sorted, sorted, ctx->stream);
+    int64_t nonfinite[2] = {0, 0};
+    const hipError_t se = make_sorted_sources(sources, n_sources, cell, &fs->d_sorted, sorted,
+                                              ctx->stream, nonfinite);
+    fs->nonfinite_points = nonfinite[0];
+    fs->nonfinite_covs = nonfinite[1];
     if (se != hipSuccess) {
       vgicp_factorset_destroy(fs);
       return hip_fail(ctx, "vgicp_factorset_create", se);
@@ -797,7 +800,8 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc) return rc;
   if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": an output pointer is NULL");
-  static const int32_t kDefaultCandidates[] = {12 * kTileQuantum, 6 * kTileQuantum,
+  static const int32_t kDefaultCandidates[] = {24 * kTileQuantum, 18 * kTileQuantum,
+                                               12 * kTileQuantum, 6 * kTileQuantum,
                                                4 * kTileQuantum,  3 * kTileQuantum,
                                                2 * kTileQuantum,  kTileQuantum};
   if (!candidates) {
@@ -965,28 +969,53 @@ int vgicp_factorset_reorder(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
   return VGICP_OK;
 }
 
-int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points) {
-  const char *who = "vgicp_factorset_fp64_points";
-  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
-  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
-  if (fs->device != ctx->device)
-    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
-  int rc = use_device(ctx);
-  if (rc) return rc;
-  if (!n_points) return fail(ctx, VGICP_EINVAL, std::string(who) + ": n_points is NULL");
-  *n_points = 0;
+namespace {
+
+// Sum over the factor set's tiles of one slot of the tile partials (a count
+// written by the last linearize or evaluate call); synchronizes.
+int partial_column_sum(vgicp_ctx ctx, vgicp_factorset fs, int slot, int64_t *total,
+                       const char *who) {
+  *total = 0;
   if (fs->n_tiles == 0) return VGICP_OK;
-  // one double per tile partial, strided
   std::vector<double> col(size_t(fs->n_tiles));
-  hipError_t e = hipMemcpy2DAsync(col.data(), sizeof(double), fs->d_partials + kWideSlot,
+  hipError_t e = hipMemcpy2DAsync(col.data(), sizeof(double), fs->d_partials + slot,
                                   kPartialStride * sizeof(double), sizeof(double),
                                   size_t(fs->n_tiles), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess)
     return fail(ctx, VGICP_EHIP, std::string(who) + ": " + hipGetErrorString(e));
-  int64_t total = 0;
-  for (double v : col) total += int64_t(v);
-  *n_points = total;
+  int64_t sum = 0;
+  for (double v : col) sum += int64_t(v);
+  *total = sum;
+  return VGICP_OK;
+}
+
+int check_fs(vgicp_ctx ctx, vgicp_factorset fs, const char *who) {
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  return use_device(ctx);
+}
+
+}  // namespace
+
+int vgicp_factorset_fp64_points(vgicp_ctx ctx, vgicp_factorset fs, int64_t *n_points) {
+  const char *who = "vgicp_factorset_fp64_points";
+  int rc = check_fs(ctx, fs, who);
+  if (rc) return rc;
+  if (!n_points) return fail(ctx, VGICP_EINVAL, std::string(who) + ": n_points is NULL");
+  return partial_column_sum(ctx, fs, kWideSlot, n_points, who);
+}
+
+int vgicp_factorset_check(vgicp_ctx ctx, vgicp_factorset fs, int64_t *nonfinite_points,
+                          int64_t *nonfinite_covs, int64_t *degenerate_hits) {
+  const char *who = "vgicp_factorset_check";
+  int rc = check_fs(ctx, fs, who);
+  if (rc) return rc;
+  if (nonfinite_points) *nonfinite_points = fs->nonfinite_points;
+  if (nonfinite_covs) *nonfinite_covs = fs->nonfinite_covs;
+  if (degenerate_hits) return partial_column_sum(ctx, fs, kDegenerateSlot, degenerate_hits, who);
   return VGICP_OK;
 }
 

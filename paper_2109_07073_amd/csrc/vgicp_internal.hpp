@@ -194,10 +194,13 @@ struct SortedSource {
 
 // Ordered copies of the clouds s with cell[s] > 0 and n > 0, in one device
 // allocation returned in *buffer (NULL when there is none); out[s] points into
-// it.  Enqueued on st and synchronized before returning.
+// it.  nonfinite (may be NULL) receives the number of copied points with a
+// non-finite coordinate and with a non-finite covariance entry.  Enqueued on
+// st and synchronized before returning.
 hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
                                const std::vector<double> &cell, void **buffer,
-                               std::vector<SortedSource> &out, hipStream_t st);
+                               std::vector<SortedSource> &out, hipStream_t st,
+                               int64_t *nonfinite = nullptr);
 
 // Replace the source copies of fs by per-factor copies with each factor's
 // points in the order of the target voxels they fall in at `poses` (device)
@@ -217,10 +220,13 @@ struct Tile {
 //   27       cost
 //   28       inliers
 //   29       inliers whose fused covariance was formed in FP64 (linearize and
-//            cost kernels; 0 without the condition gate)
+//            cost kernels)
+//   30       inliers whose fused covariance was not positive definite (they
+//            add nothing; linearize and cost kernels)
 constexpr int kPartialStride = 32;
 constexpr int kNumSums = 28;
 constexpr int kWideSlot = 29;
+constexpr int kDegenerateSlot = 30;
 
 // Error bits of the device error word.
 constexpr uint32_t kErrNonFinite = 1u;
@@ -323,6 +329,9 @@ struct vgicp_factorset_s {
   std::vector<vgicp::FactorDesc> h_factors;
   std::vector<int64_t> tile_order;  // factors in tile order (grouped by target map)
   void *d_sorted = nullptr;  // device: ordered copies of the source clouds
+  // Source points with a non-finite coordinate / covariance entry, counted
+  // when the ordered copies were made.
+  int64_t nonfinite_points = 0, nonfinite_covs = 0;
   int64_t tiles_capacity = 0;       // tiles d_tiles and d_partials have room for
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;

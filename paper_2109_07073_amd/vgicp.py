@@ -105,6 +105,7 @@ _PROTOS = {
     "vgicp_server_add_frame": (ctypes.c_int, [_vp, _vp, _vp, _i64, _dbl, _P(_i32)]),
     "vgicp_server_remove_frame": (ctypes.c_int, [_vp, _i32]),
     "vgicp_factorset_fp64_points": (ctypes.c_int, [_vp, _vp, _P(_i64)]),
+    "vgicp_factorset_check": (ctypes.c_int, [_vp, _vp, _P(_i64), _P(_i64), _P(_i64)]),
     "vgicp_factorset_reorder": (ctypes.c_int, [_vp, _vp, _vp]),
     "vgicp_factorset_set_grid": (ctypes.c_int, [_vp, _vp, _i32]),
     "vgicp_factorset_time_kernel": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _i32, _i32, _P(_dbl)]),
@@ -636,6 +637,16 @@ def fp64_points(ctx: Context, fs: FactorSet) -> int:
     n = ctypes.c_int64()
     _check(_lib.vgicp_factorset_fp64_points(ctx.handle, fs.handle, ctypes.byref(n)), ctx.handle)
     return n.value
+
+
+def check_inputs(ctx: Context, fs: FactorSet) -> dict:
+    """vgicp_factorset_check: source points with a non-finite coordinate or
+    covariance entry (counted at creation) and the degenerate correspondences
+    of the last linearize / evaluate call (synchronizes)."""
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.vgicp_factorset_check(ctx.handle, fs.handle, ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(c)), ctx.handle)
+    return {"nonfinite_points": a.value, "nonfinite_covs": b.value, "degenerate_hits": c.value}
 
 
 def assemble_system(ctx: Context, fs: FactorSet, H, b, out=None, with_offdiag: bool = True):

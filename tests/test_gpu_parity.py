@@ -371,6 +371,22 @@ def test_evaluate_matches_linearize_and_the_oracle(vg, ctx, scans, ragged, accum
 
 # --------------------------------------------- degenerate fused covariances
 
+def _oracle_degenerate_hits(w):
+    """Hits of every factor whose fused covariance the oracle finds not
+    positive definite."""
+    from oracle.vgicp_oracle import _unpack_cov
+    maps = oracle.build_maps(w.targets, w.resolution)
+    n = 0
+    for s, t, pi, pj in w.factors:
+        x, c = w.sources[s]
+        R, tt = oracle.relative_pose(w.poses[pi], w.poses[pj])
+        corr = oracle.lookup(maps[t], x, R, tt)
+        hit = corr >= 0
+        F = oracle.fused_covariance(_unpack_cov(maps[t].cov[corr[hit]]), _unpack_cov(c[hit]), R)
+        n += int((~oracle.positive_definite(F)).sum())
+    return n
+
+
 @pytest.mark.parametrize("fused,kappa", [("f64", 0.0), ("f32", 0.0), ("f32", 1e4)])
 @pytest.mark.parametrize("accum", ACCS)
 def test_degenerate_fused_covariances(vg, ctx, degenerate, accum, fused, kappa):
@@ -393,6 +409,13 @@ def test_degenerate_fused_covariances(vg, ctx, degenerate, accum, fused, kappa):
     # with and without the degenerate points (tiles and summation order differ)
     for k in ("H", "b", "e"):
         assert rel_fro(got[k][0], got[k][3]) <= TOL, k
+    # the counts of bad inputs: non-finite covariances of the clouds the set
+    # copied, and the hits the oracle finds degenerate (as inliers adding nothing)
+    chk = vg.check_inputs(ctx, g.fs)
+    n_nonfinite = sum(int((~np.isfinite(c)).any(axis=1).sum()) for _, c in w.sources)
+    assert chk["nonfinite_points"] == 0 and chk["nonfinite_covs"] == n_nonfinite
+    if fused == "f64":   # FP32 positive-definiteness tests may round the other way
+        assert chk["degenerate_hits"] == _oracle_degenerate_hits(w)
     ev = g.evaluate(accum=accum, fused=fused, fp64_kappa=kappa)
     assert np.array_equal(ev["inliers"], ref["inliers"])
     assert np.array_equal(ev["e"], got["e"])
@@ -470,11 +493,15 @@ def test_non_finite_source_points_miss(vg, ctx, cfg1):
     w_far = Workload(name="far", resolution=cfg1.resolution, sources=[(xyz_far, cov)],
                      targets=cfg1.targets, poses=cfg1.poses, factors=cfg1.factors, meta={})
     _, ref = oracle_results(w_far, with_corr=True)
-    got = GpuWorkload(vg, ctx, w_bad).linearize(with_corr=True)
+    g = GpuWorkload(vg, ctx, w_bad)
+    got = g.linearize(with_corr=True)
     assert np.all(got["corr"][bad] == -1)
     assert np.array_equal(got["corr"], ref["corr"][0])
     assert_linearize_parity(got, ref)
     assert np.all(np.isfinite(got["H"])) and np.all(np.isfinite(got["b"]))
+    # the factor set counted the bad points when it copied the cloud
+    chk = vg.check_inputs(ctx, g.fs)
+    assert chk == {"nonfinite_points": bad.size, "nonfinite_covs": 0, "degenerate_hits": 0}
 
 
 def test_automatic_tile_size(vg, ctx, cfg1, ragged):
