@@ -909,10 +909,15 @@ def main():
     n_corr = int(inliers.sum())
     n_pts = int(fs.total_points)
 
-    # ---- round latency: device time (events) and host-visible (incl. D2H)
+    # ---- round latency: device time (events) and host-visible (incl. D2H),
+    # over at least 100 rounds, after three untimed rounds that capture and
+    # instantiate the round's graph
+    for _ in range(3):
+        vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
+    torch.cuda.synchronize()
     dev_ms, host_ms = [], []
     host_H = torch.empty((F, 12, 12), dtype=torch.float64, pin_memory=True)
-    for _ in range(args.steps):
+    for _ in range(max(args.steps, 100)):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         h0 = time.perf_counter()

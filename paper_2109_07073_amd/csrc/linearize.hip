@@ -138,19 +138,48 @@ __device__ __forceinline__ void load_xyz(const CloudRsrc &c, uint32_t i, float p
 struct VoxelKey {
   uint32_t klo, khi;  // packed brick key
   uint32_t h;         // home record
-  uint32_t bit;       // the voxel's bit in the brick's occupancy mask
+  uint32_t up;        // 63 - the voxel's bit in the brick's occupancy mask
 };
 
-__device__ __forceinline__ VoxelKey voxel_key(const float v[3], uint32_t log2cap) {
+// floor(x) as an integer, one v_cvt_flr_i32_f32 (the compiler emits a floor
+// and a conversion); x is finite and within [-2^20 - 4, 2^20] here.
+__device__ __forceinline__ int32_t floor_i32(float x) {
+  int32_t k;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(k) : "v"(x));
+  return k;
+}
+
+// Table of 63 - brick_bit over the low two key bits per axis, entry
+// 16 (kx & 3) + 4 (ky & 3) + (kz & 3): the index takes five instructions
+// against ten for the interleave.  `up_table_fill` writes it into a block's
+// LDS (the caller synchronizes before the first lookup).
+constexpr int kUpTable = 64;
+
+__device__ __forceinline__ void up_table_fill(uint8_t *t) {
+  const uint32_t i = threadIdx.x;
+  if (i < uint32_t(kUpTable))
+    t[i] = uint8_t(brick_bit(int32_t(i >> 4), int32_t(i >> 2) & 3, int32_t(i) & 3) ^ 63u);
+}
+
+// With kTable the voxel's bit comes from the table `up` in LDS, else it is
+// computed.
+template <bool kTable = false>
+__device__ __forceinline__ VoxelKey voxel_key(const float v[3], uint32_t log2cap,
+                                              const uint8_t *up = nullptr) {
   const float vx = fminf(fmaxf(v[0], kClampLoF), kClampHiF);
   const float vy = fminf(fmaxf(v[1], kClampLoF), kClampHiF);
   const float vz = fminf(fmaxf(v[2], kClampLoF), kClampHiF);
-  const int32_t kx = int32_t(floorf(vx)), ky = int32_t(floorf(vy)), kz = int32_t(floorf(vz));
+  const int32_t kx = floor_i32(vx), ky = floor_i32(vy), kz = floor_i32(vz);
   const uint32_t fx = brick_field(kx), fy = brick_field(ky), fz = brick_field(kz);
   VoxelKey r;
   r.klo = (fy << kBrickBits) | fz;
   r.khi = (fx << (2 * kBrickBits - 32)) | (fy >> (32 - kBrickBits));
-  r.bit = brick_bit(kx, ky, kz);
+  if constexpr (kTable) {
+    const uint32_t i = (uint32_t(kx & 3) << 4) | (uint32_t(ky & 3) << 2) | uint32_t(kz & 3);
+    r.up = up[i];
+  } else {
+    r.up = brick_bit(kx, ky, kz) ^ 63u;
+  }
   r.h = brick_slot(fx, fy, fz, log2cap);
   return r;
 }
@@ -169,9 +198,22 @@ __device__ __forceinline__ RecordLoad load_record(Rsrc rb, uint32_t h) {
   return r;
 }
 
-// Whether the table's occupancy bitset (staged in LDS) has record h's bit set.
-__device__ __forceinline__ bool home_occupied(const uint32_t *occ, uint32_t occ_mask, uint32_t h) {
-  return (occ[(h & occ_mask) >> 5] >> (h & 31u)) & 1u;
+// Byte mask of the occupancy word of record h: the word is at byte
+// (h >> 3) & occ_word_mask(occ_mask) of the bitset, ((h & occ_mask) >> 5) * 4.
+__device__ __forceinline__ uint32_t occ_word_mask(uint32_t occ_mask) {
+  uint32_t m = (occ_mask >> 3) & ~3u;
+  // opaque to the optimizer, which would otherwise expand (h >> 3) & m back
+  // into three operations per lookup
+  asm("" : "+s"(m));
+  return m;
+}
+
+// Whether the table's occupancy bitset (staged in LDS) has record h's bit set;
+// wmask = occ_word_mask(occ_mask).
+__device__ __forceinline__ bool home_occupied(const uint32_t *occ, uint32_t wmask, uint32_t h) {
+  const uint32_t w = *reinterpret_cast<const uint32_t *>(
+      reinterpret_cast<const char *>(occ) + ((h >> 3) & wmask));
+  return __builtin_amdgcn_ubfe(w, h, 1u) != 0u;  // bit h mod 32
 }
 
 // The home record of a lookup, read only when its bit is set: otherwise the
@@ -203,7 +245,7 @@ __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const Voxel
   uint64_t mask = u64_of(home.km.z, home.km.w);
   uint32_t base = home.base;
   const bool probe = occupied && rkey != key && rkey != kEmptyKey;
-  if (__ballot(probe) != 0) {
+  if (__builtin_amdgcn_ballot_w64(probe) != 0) {
     if (probe) {
       const uint32_t cm = (1u << log2cap) - 1u;
       uint32_t h = vk.h;
@@ -224,8 +266,11 @@ __device__ __forceinline__ int find_voxel(Rsrc rb, uint32_t log2cap, const Voxel
     // stay exact
     __builtin_amdgcn_s_waitcnt(0);
   }
-  if (!occupied || rkey != key || !((mask >> vk.bit) & 1ull)) return -1;
-  return int(base + uint32_t(__popcll(mask & ((1ull << vk.bit) - 1ull))));
+  // the voxel's bit moved to the top: set for a hit, and the bits of the mask
+  // at and below it count the voxel and the brick's voxels before it
+  const uint64_t top = mask << vk.up;
+  if (!occupied || rkey != key || int64_t(top) >= 0) return -1;
+  return int(base + uint32_t(__popcll(top)) - 1u);
 }
 
 // ---------------------------------------------------------------- sums
@@ -721,6 +766,7 @@ static_assert(64 * Sums<VGICP_ACC_MIXED, kNumSums>::kStride * sizeof(float) <= s
 
 __device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
   e += d;  // e < kRing and d < kRing, so one wrap suffices
+  if constexpr ((kRing & (kRing - 1)) == 0) return e & (kRing - 1);
   return e >= kRing ? e - kRing : e;
 }
 
@@ -835,6 +881,7 @@ struct LinearizeLds {
   int deg[kWaves];
   HitQueue queues[kWaves];
   uint32_t occ[kOccMaxBits / 32];
+  uint8_t up[kUpTable];
 };
 
 // One tile of k_linearize.  `staged` names the map whose occupancy bits the
@@ -904,8 +951,8 @@ __device__ __forceinline__ void linearize_tile(
     for (int p = 0; p < kChunk; ++p) {
       float v[3];
       lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
-      vk[p] = voxel_key(v, fd.log2cap);
-      occ[p] = home_occupied(occ_lds, fd.occ_mask, vk[p].h);
+      vk[p] = voxel_key<true>(v, fd.log2cap, L.up);
+      occ[p] = home_occupied(occ_lds, occ_word_mask(fd.occ_mask), vk[p].h);
     }
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) rec[p] = load_home(rb, vk[p].h, occ[p]);
@@ -918,13 +965,13 @@ __device__ __forceinline__ void linearize_tile(
 #pragma unroll
     for (int p = 0; p < kChunk; ++p) {
       const uint32_t i = base + p * kBlock + lane;
-      const int hs = find_voxel(rb, fd.log2cap, vk[p], rec[p], occ[p]);
-      const int h = i < end ? hs : -1;
+      const int h = find_voxel(rb, fd.log2cap, vk[p], rec[p], occ[p]);
+      const bool hit = h >= 0 && i < end;
       if constexpr (CORR) {
-        if (i < end && h < 0) pcorr.put(i - begin, -1);
+        if (i < end && !hit) pcorr.put(i - begin, -1);
       }
-      const uint64_t mask = __ballot(h >= 0);
-      if (h >= 0) {
+      const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
+      if (hit) {
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
             uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
         const uint32_t e = ring_add(ring_add(head, count), below);
@@ -1035,6 +1082,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const uint32_t hi = min(lo + per, count);
   const uint32_t P = gridDim.x >> 3;
   const uint32_t *staged = nullptr;
+  up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base + t), factors, tiles,
                                               tile_points, poses, partials, corr, kappa);
@@ -1042,6 +1090,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
 
 // Overlap hit count of one tile (Eq. (7)): brick records only.
 __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
+                                             const uint8_t *up_lds,
                                              const uint32_t *&staged, int64_t tile,
                                              const FactorDesc *__restrict__ factors,
                                              const Tile *__restrict__ tiles, int32_t tile_points,
@@ -1078,8 +1127,8 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
     for (int p = 0; p < kOvlChunk; ++p) {
       float v[3];
       lookup_coords(k.S, k.u, cur[p][0], cur[p][1], cur[p][2], v);
-      vk[p] = voxel_key(v, fd.log2cap);
-      occ[p] = home_occupied(occ_lds, fd.occ_mask, vk[p].h);
+      vk[p] = voxel_key<true>(v, fd.log2cap, up_lds);
+      occ[p] = home_occupied(occ_lds, occ_word_mask(fd.occ_mask), vk[p].h);
     }
 #pragma unroll
     for (int p = 0; p < kOvlChunk; ++p) rec[p] = load_home(rb, vk[p].h, occ[p]);
@@ -1119,13 +1168,16 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
           const double *__restrict__ poses, double *__restrict__ partials) {
   __shared__ int lds_cnt[kWaves];
   __shared__ uint32_t occ_lds[kOccMaxBits / 32];
+  __shared__ uint8_t up_lds[kUpTable];
   const int64_t per = (tile_end - tile_base + 7) >> 3;
   const int64_t lo = tile_base + int64_t(blockIdx.x & 7u) * per;
   const int64_t hi = min(lo + per, tile_end);
   const uint32_t P = gridDim.x >> 3;
   const uint32_t *staged = nullptr;
+  up_table_fill(up_lds);  // read after the first tile's barrier
   for (int64_t tile = lo + (blockIdx.x >> 3); tile < hi; tile += P)
-    overlap_tile(lds_cnt, occ_lds, staged, tile, factors, tiles, tile_points, poses, partials);
+    overlap_tile(lds_cnt, occ_lds, up_lds, staged, tile, factors, tiles, tile_points, poses,
+                 partials);
 }
 
 // ---------------------------------------------------------------- target order

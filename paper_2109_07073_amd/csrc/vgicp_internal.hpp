@@ -59,9 +59,18 @@ __host__ __device__ inline uint64_t brick_key(uint32_t fx, uint32_t fy, uint32_t
   return (uint64_t(fx) << (2 * kBrickBits)) | (uint64_t(fy) << kBrickBits) | uint64_t(fz);
 }
 
+// Bits of b taken where m is set, the others from a (one v_bfi_b32).
+__host__ __device__ inline uint32_t bit_select(uint32_t m, uint32_t b, uint32_t a) {
+  return (b & m) | (a & ~m);
+}
+
+// The two low bits of each key spread three apart by a multiply: (k & 3) * 5
+// holds bit 0 at bits 0 and 2 and bit 1 at bits 1 and 3, so (k & 3) * 20 has
+// x0, x1 at bits 2, 5 (mask 0x24), (k & 3) * 10 has y0, y1 at bits 1, 4 (mask
+// 0x12) and (k & 3) * 5 has z0, z1 at bits 0, 3 (mask 0x09).
 __host__ __device__ inline uint32_t brick_bit(int32_t kx, int32_t ky, int32_t kz) {
-  return (uint32_t(kx & 2) << 4) | (uint32_t(ky & 2) << 3) | (uint32_t(kz & 2) << 2) |
-         (uint32_t(kx & 1) << 2) | (uint32_t(ky & 1) << 1) | uint32_t(kz & 1);
+  const uint32_t x = uint32_t(kx & 3) * 20u, y = uint32_t(ky & 3) * 10u, z = uint32_t(kz & 3) * 5u;
+  return bit_select(0x24u, x, bit_select(0x12u, y, z & 0x0fu));
 }
 
 // Brick-major sort key of an in-range voxel: the brick fields less one (19
@@ -92,8 +101,9 @@ constexpr uint32_t kProbeStep = 4;
 __host__ __device__ inline uint32_t brick_slot(uint32_t fx, uint32_t fy, uint32_t fz,
                                                uint32_t log2cap) {
   const uint32_t k = fz + ((fy >> 1) & 0xffffffu) * 353u + ((fx >> 1) & 0xffffffu) * 294913u;
-  const uint32_t line = (k * 0x9E3779B9u) >> (34 - log2cap);
-  return (line << 2) | (fx & 1u) | ((fy & 1u) << 1);
+  // the line, (k * 0x9E3779B9) >> (34 - log2cap), shifted left by two
+  const uint32_t line4 = (k * 0x9E3779B9u) >> (32 - log2cap);
+  return bit_select(~3u, line4, bit_select(2u, fy << 1, fx));
 }
 
 __host__ __device__ inline uint32_t brick_slot_of_key(uint64_t bkey, uint32_t log2cap) {
