@@ -946,6 +946,12 @@ def main():
     # stream; the reduce kernel bracketed by events per launch
     k_ms = vg.time_kernel(ctx, fs, poses, "linearize", reps=args.steps, accum=args.accum,
                           fused=args.fused)
+    form = vg.form_of(fs)
+    # both forms of the per-correspondence terms, whichever the tuner kept
+    form_ms = {f"{f}_kernel_ms": round(vg.time_kernel(ctx, fs, poses, "linearize",
+                                                      reps=args.steps, accum=args.accum,
+                                                      fused=args.fused, form=f), 5)
+               for f in ("source", "pair")} if args.accum != "f64" else None
     ctx.reset_timing()
     ctx.set_timing(True)
     for _ in range(min(args.steps, 20)):
@@ -962,7 +968,7 @@ def main():
     all_cov_bytes = float(36 * sizes.sum() + 44 * U.sum() + 91 * 8 * F)
     achieved = needed_bytes / (k_ms * 1e-3) / 1e9
     traffic = (profiled_traffic(args.workload, fs.tile_points)
-               if (args.accum, args.fused) == ("mixed", "f64") else None)
+               if (args.accum, args.fused, form) == ("mixed", "f64", "source") else None)
     copy_gbs = measured_copy_gbs()
 
     # ---- plain per-factor launches on the same factors
@@ -1035,6 +1041,7 @@ def main():
             "schedule": "batched, HIP graph replay" + (", autotuned tile" if tuned else ""),
             "tile_points": int(fs.tile_points),
             "grid_blocks": vg.grid(fs),
+            "form": form,
             "source_order": "Morton cells" if args.no_reorder else "target voxel order",
             "seed": w.meta.get("seed"),
         },
@@ -1053,7 +1060,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-            "kernel": "k_linearize",
+            "kernel": "k_linearize" if form == "source" else "k_linearize_pair",
             "kernel_ms": round(k_ms, 5),
             "bytes_per_launch": needed_bytes,
             "bytes_model": "12 B per source point + 24 B per correspondence + 44 B per "
@@ -1066,6 +1073,7 @@ def main():
             "copy_GBs": round(copy_gbs, 1),
             "frac_vs_copy": round(achieved / copy_gbs, 4),
         },
+        "forms": form_ms,
         "stages": {
             "voxelize_all_maps_ms": round(t_vox * 1e3, 3),
             "factorset_create_ms": round(t_fs * 1e3, 3),

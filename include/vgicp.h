@@ -91,6 +91,20 @@ extern "C" {
                              to FP32 (default)                                        */
 #define VGICP_FUSED_F32 1 /* all in FP32 (optionally gated to FP64 by fp64_kappa)    */
 
+/* How a linearization forms and sums the per-correspondence terms.  Both give
+ * the same H, b, e (up to FP32 rounding) in the same layout. */
+#define VGICP_FORM_AUTO 0   /* (default) the factor set's form: the source-frame form
+                               unless vgicp_factorset_tune chose the pair form          */
+#define VGICP_FORM_SOURCE 1 /* 21 + 6 + 1 sums per correspondence in the source frame
+                               (Omega' = (R^T C' R + C)^-1, J' = [[mu]x, -I]), expanded
+                               exactly to the 12 x 12 H_ii, H_ij, H_jj once per factor  */
+#define VGICP_FORM_PAIR 2   /* Eqs. (5)-(6) term by term: each correspondence adds its
+                               J^T Omega J (78 upper-triangle entries of the 12 x 12),
+                               J^T Omega e (12) and e^T Omega e in the target frame, J =
+                               [A, B] with A = [R [mu]x, -R], B = [-[q]x, I]; accum
+                               VGICP_ACC_MIXED, _F32 or _F32_COMP, no corr output; about
+                               200 VGPRs per lane (2 waves per SIMD)                    */
+
 /* How the factors of one call are launched. */
 #define VGICP_SCHED_BATCHED 0    /* one launch over the tiles of all factors, one reduce   */
 #define VGICP_SCHED_PER_FACTOR 1 /* one linearize launch and one reduce launch per factor */
@@ -127,6 +141,7 @@ typedef struct {
                         Ignored with VGICP_FUSED_F64                                 */
   int32_t fused;     /* VGICP_FUSED_*: precision of the fused covariance and its
                         inverse (0 = VGICP_FUSED_F64, the default)                   */
+  int32_t form;      /* VGICP_FORM_*: 0 = VGICP_FORM_AUTO, the factor set's form     */
 } vgicp_opts;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -240,12 +255,17 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
  * workgroup per tile, and a persistent grid of as many workgroups as the
  * device's CUs hold at once for opts' kernel, each walking several tiles),
  * twice in forward and reverse order keeping each pair's best, and keep the
- * fastest pair.  H, b, e, inliers are device buffers as for
+ * fastest pair.  With opts' form VGICP_FORM_AUTO (the default) and an
+ * accumulation the pair form supports, every candidate is also timed in the
+ * pair form and the factor set keeps the faster form for VGICP_FORM_AUTO
+ * calls; with another form only that form is timed (and the kept form is not
+ * changed).  H, b, e, inliers are device buffers as for
  * vgicp_linearize_factors, overwritten by the trial rounds.  The factor set's
  * tiles and grid change (results change only by FP32 summation order; the
  * grid alone does not change them) and its captured graphs are dropped.
  * best_tile and best_ms (mean device time of a round) may be NULL; the grid
- * chosen is read with vgicp_factorset_grid.  Synchronizes ctx's stream.
+ * chosen is read with vgicp_factorset_grid and the form with
+ * vgicp_factorset_form.  Synchronizes ctx's stream.
  * Errors: EINVAL, EHIP. */
 int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          const vgicp_opts *opts, double *H, double *b, double *e,
@@ -276,6 +296,10 @@ int vgicp_factorset_set_grid(vgicp_ctx ctx, vgicp_factorset fs, int32_t persist_
 
 /* The grid in use (see vgicp_factorset_set_grid).  Errors: EINVAL. */
 int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks);
+
+/* The form VGICP_FORM_AUTO calls use (VGICP_FORM_SOURCE unless
+ * vgicp_factorset_tune chose VGICP_FORM_PAIR).  Errors: EINVAL. */
+int vgicp_factorset_form(vgicp_factorset fs, int32_t *form);
 
 /* Target-order source copies.  A round streams every source point once and
  * gathers the statistics of the target voxel it falls in (Sec. III-A, Eq. (3)
@@ -356,7 +380,11 @@ int vgicp_validate_factors(int32_t n_sources, int32_t n_maps, int32_t n_poses,
  * transform is not finite or falls outside the key range is a miss, and a hit
  * whose fused covariance is not positive definite (including non-finite) adds
  * nothing but counts as an inlier; vgicp_factorset_check reports both kinds of
- * bad input.  Errors: EINVAL, EHIP. */
+ * bad input.  The pair form (opts->form, or the factor set's tuned form under
+ * VGICP_FORM_AUTO) allocates its tile partials (96 doubles per tile) at its
+ * first call; VGICP_FORM_AUTO takes the source-frame form where the pair form
+ * does not apply (corr requested, VGICP_ACC_F64).  Errors: EINVAL (also for
+ * VGICP_FORM_PAIR with corr or with VGICP_ACC_F64), EHIP. */
 int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                             const vgicp_opts *opts, double *H, double *b, double *e,
                             int64_t *inliers, int32_t *corr);
@@ -374,8 +402,10 @@ int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses
  * library holds on each device it runs on (VGICP_NOALLOC_MAX_TILES tiles of
  * 32 doubles, 8 MiB, kept until the process ends) instead of the factor
  * set's buffer, and the call allocates nothing: no device or pinned memory,
- * no events, no graph (opts->use_graph must be 0).  Every call on a device
- * shares that device's array, so calls that overlap on one device (on two
+ * no events, no graph (opts->use_graph must be 0).  It linearizes in the
+ * source-frame form only: VGICP_FORM_PAIR is EINVAL and VGICP_FORM_AUTO means
+ * VGICP_FORM_SOURCE here, whatever form the factor set was tuned to.  Every
+ * call on a device shares that device's array, so calls that overlap on one device (on two
  * streams, or from two threads) race and give wrong results; calls on one
  * stream are ordered and safe.  Nothing in the array needs clearing between
  * calls: each launch writes every partial its reduce reads.
@@ -507,7 +537,9 @@ typedef struct {
   int32_t tile_points;         /* 0 = 4608 (whole lookup phases of a workgroup)     */
   int32_t reserved;            /* must be 0                                         */
   vgicp_opts opts;             /* accumulation, residual, kappa of every batch
-                                  (schedule and use_graph are ignored)              */
+                                  (schedule and use_graph are ignored; form must be
+                                  VGICP_FORM_AUTO or VGICP_FORM_SOURCE: batches are
+                                  linearized in the source-frame form)              */
 } vgicp_server_config;
 
 /* Create a server on HIP device `device` with its own streams and worker

@@ -450,13 +450,45 @@ struct Sums<VGICP_ACC_F32_COMP, N> {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wave * N + i] = wide[i];
   }
-  // The wave's sums into lds[wave * N + i] (the wave's hit ring, `ring`, is
-  // free at this point; these forms do not use it).
+  // The wave's (sum + compensation) values, in FP64, into lds[wave * N + i].
+  // A single sum goes through the DPP tree above.  The 28 sums of a
+  // linearization are transposed through the wave's hit ring (free at the end
+  // of a tile), 14 at a time as in the FP64-carried form: four lanes per sum
+  // each add 16 values of its column with two-sum, and two quad DPP steps add
+  // the four (sum, compensation) pairs with two-sum.
+  // sums per pass: 14 for the 28 source-frame sums, 13 for the pair form's 91
+  static constexpr int kGroup = N % 14 == 0 ? 14 : N % 13 == 0 ? 13 : 0;
+  static constexpr int kStride = kGroup + 1;
   template <typename T>
   __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
-    (void)ring;
-    wave_reduce();
-    if (lane == kLastLane) store(lds, wave);
+    if constexpr (kGroup == 0) {
+      (void)ring;
+      wave_reduce();
+      if (lane == kLastLane) store(lds, wave);
+    } else {
+      const uint32_t c = lane >> 2, q = lane & 3;
+#pragma unroll
+      for (int g = 0; g < N; g += kGroup) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) ring[lane * kStride + i] = v[g + i];
+        __builtin_amdgcn_wave_barrier();
+        float sum = 0.f, comp = 0.f;
+        if (c < uint32_t(kGroup)) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            float s, err;
+            two_sum(sum, ring[(4 * r + q) * kStride + c], s, err);
+            sum = s;
+            comp += err;
+          }
+        }
+        step<0xb1>(sum, comp);  // quad lanes (1, 0, 3, 2)
+        step<0x4e>(sum, comp);  // quad lanes (2, 3, 0, 1)
+        if (c < uint32_t(kGroup) && q == 0) lds[wave * N + g + int(c)] = double(sum) + double(comp);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
   }
   using lds_t = double;
   __device__ static double finish(const double *lds, int i) {
@@ -487,11 +519,12 @@ struct Sums<VGICP_ACC_MIXED, N> {
   // in FP64 (exact for FP32 inputs of like magnitude), and a quad DPP step
   // pair adds the four quarters: about 80 VALU instructions for all 28 sums
   // against 530 for 28 DPP trees in FP64.
-  static constexpr int kGroup = 14;  // sums per pass
+  // sums per pass: 14 for the 28 source-frame sums, 13 for the pair form's 91
+  static constexpr int kGroup = N % 14 == 0 ? 14 : N % 13 == 0 ? 13 : 0;
   static constexpr int kStride = kGroup + 1;
   template <typename T>
   __device__ void reduce_to(T *lds, int wave, uint32_t lane, float *ring) {
-    if constexpr (N % kGroup != 0) {
+    if constexpr (kGroup == 0) {
       (void)ring;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -549,14 +582,10 @@ __device__ __forceinline__ double uniform_d(double v) {
 }
 
 // ---------------------------------------------------------------- per point
-// Adds one correspondence.  R is the FP32 relative rotation, (mx, my, mz) the
-// source point, c its covariance, q its FP32 transform, m / S the voxel mean
-// and covariance.  With LIN the 21 + 6 source-frame Hessian/gradient sums and
-// the cost are added; without it only the cost.
-// Omega' = (R^T C' R + C)^-1 formed and inverted in FP64 from the FP32 inputs
-// and the FP64 relative rotation, rounded to FP32.  Used for ill-conditioned
-// points, where forming F' in FP32 already loses the small eigenvalue.
-// Returns false when F' is not positive definite.
+// (R^T S R + c)^-1 (for S = C', c = C the source-frame weight Omega') formed
+// and inverted in FP64 from the FP32 covariances and the FP64 rotation R,
+// rounded to FP32.  Used where forming the fused covariance in FP32 already
+// loses its small eigenvalue.  Returns false when it is not positive definite.
 __device__ __forceinline__ bool fused_information_fp64(const double R[9], const float S[6],
                                                     const float c[6], float o[6]) {
   const double s0 = S[0], s1 = S[1], s2 = S[2], s3 = S[3], s4 = S[4], s5 = S[5];
@@ -614,24 +643,26 @@ constexpr int kFuse64 = 2;
 // it only the cost.  FUSE selects how Omega' is formed (above); with
 // kFuseGate `nwide` counts the hits that took the FP64 path.  Returns false,
 // adding nothing, for a hit whose fused covariance is not positive definite.
-template <bool LIN, int FUSE, typename SumsT>
-__device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConsts &k,
-                                                   float kappa, float mx, float my, float mz,
-                                                   const float c[6], const float r[3],
-                                                   const float S[6], uint32_t &nwide) {
-  // Contraction is off and every fused multiply-add is explicit, so the cost
-  // comes out bit-identical in the linearization and the cost-only kernels.
+// The weight Omega = (R^T A R + B)^-1 of a correspondence (upper triangle
+// xx xy xz yy yz zz), formed as FUSE selects (above): R^T C' R + C with the
+// relative rotation R, the voxel covariance A = C' and the point covariance
+// B = C is the source-frame fused covariance F'; passing R^T, A = C and B = C'
+// gives the target-frame F = C' + R C R^T of Eq. (2).  R64 is R in FP64.
+// With kFuseGate `nwide` counts the FP64 formations.  Returns false, leaving
+// o unset, when the fused covariance is not positive definite.
+template <int FUSE>
+__device__ __forceinline__ bool fused_weight(const float R[9], const double R64[9],
+                                             const float S[6], const float c[6], float kappa,
+                                             uint32_t &nwide, float o[6]) {
 #pragma clang fp contract(off)
-  const float *R = k.R;
 #define FMA __builtin_fmaf
-  const float r0 = r[0], r1 = r[1], r2 = r[2];
   float o00, o01, o02, o11, o12, o22;
   if constexpr (FUSE == kFuse64) {
-    float o[6];
-    if (!fused_information_fp64(k.R64, S, c, o)) return false;  // not positive definite
-    o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
+    float w[6];
+    if (!fused_information_fp64(R64, S, c, w)) return false;  // not positive definite
+    o00 = w[0], o01 = w[1], o02 = w[2], o11 = w[3], o12 = w[4], o22 = w[5];
   } else {
-    // W = C' R, then F' = R^T W + C (symmetric, upper triangle)
+    // W = S R, then F = R^T W + c (symmetric, upper triangle)
     const float W00 = FMA(S[2], R[6], FMA(S[1], R[3], S[0] * R[0]));
     const float W01 = FMA(S[2], R[7], FMA(S[1], R[4], S[0] * R[1]));
     const float W02 = FMA(S[2], R[8], FMA(S[1], R[5], S[0] * R[2]));
@@ -647,7 +678,7 @@ __device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConst
     const float f11 = FMA(R[7], W21, FMA(R[4], W11, FMA(R[1], W01, c[3])));
     const float f12 = FMA(R[7], W22, FMA(R[4], W12, FMA(R[1], W02, c[4])));
     const float f22 = FMA(R[8], W22, FMA(R[5], W12, FMA(R[2], W02, c[5])));
-    // Omega' = F'^-1 by the adjugate
+    // Omega = F^-1 by the adjugate
     const float a00 = FMA(f11, f22, -(f12 * f12));
     const float a01 = FMA(f02, f12, -(f01 * f22));
     const float a02 = FMA(f01, f12, -(f02 * f11));
@@ -666,9 +697,9 @@ __device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConst
     }
     if (wide) {
       ++nwide;
-      float o[6];
-      if (!fused_information_fp64(k.R64, S, c, o)) return false;  // not positive definite
-      o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
+      float w[6];
+      if (!fused_information_fp64(R64, S, c, w)) return false;  // not positive definite
+      o00 = w[0], o01 = w[1], o02 = w[2], o11 = w[3], o12 = w[4], o22 = w[5];
     } else {
       if (!pd32) return false;  // not positive definite
       // hardware reciprocal refined by one Newton step (within an ulp or so;
@@ -679,6 +710,24 @@ __device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConst
       o11 = a11 * inv, o12 = a12 * inv, o22 = a22 * inv;
     }
   }
+  o[0] = o00, o[1] = o01, o[2] = o02, o[3] = o11, o[4] = o12, o[5] = o22;
+#undef FMA
+  return true;
+}
+
+template <bool LIN, int FUSE, typename SumsT>
+__device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConsts &k,
+                                                   float kappa, float mx, float my, float mz,
+                                                   const float c[6], const float r[3],
+                                                   const float S[6], uint32_t &nwide) {
+  // Contraction is off and every fused multiply-add is explicit, so the cost
+  // comes out bit-identical in the linearization and the cost-only kernels.
+#pragma clang fp contract(off)
+#define FMA __builtin_fmaf
+  const float r0 = r[0], r1 = r[1], r2 = r[2];
+  float o[6];
+  if (!fused_weight<FUSE>(k.R, k.R64, S, c, kappa, nwide, o)) return false;  // not PD
+  const float o00 = o[0], o01 = o[1], o02 = o[2], o11 = o[3], o12 = o[4], o22 = o[5];
   // g = Omega' r
   const float g0 = FMA(o02, r2, FMA(o01, r1, o00 * r0));
   const float g1 = FMA(o12, r2, FMA(o11, r1, o01 * r0));
@@ -726,6 +775,145 @@ __device__ __forceinline__ bool add_correspondence(SumsT &acc, const FactorConst
   return true;
 }
 
+// ---------------------------------------------------------------- pair form
+// The per-correspondence Hessian factor of Eqs. (5)-(6) in the target frame,
+// accumulated term by term: with q = R mu + t, the residual e = mu' - q, the
+// weight Omega = (C' + R C R^T)^-1 of Eq. (2) and the Jacobians under right
+// perturbations xi = (omega, rho) of T_i and T_j,
+//   A = de/dxi_i = [R [mu]x, -R],   B = de/dxi_j = [-[q]x, I],
+// a correspondence adds J^T Omega J to the 12 x 12 H (J = [A, B]; its 78
+// upper-triangle entries, row-major), J^T Omega e to b (12) and e^T Omega e
+// to the cost: 91 sums.  Intermediates: N = Omega R, P = Omega A =
+// [N [mu]x, -N], K = R [mu]x, Q = Omega [q]x, g = Omega e; then
+//   H_ii = [[K^T N [mu]x, -K^T N], [., R^T N]],
+//   H_ij = P^T B = [P^T (-[q]x), P^T],
+//   H_jj = [[-[q]x Q, -Q^T], [., Omega]],
+//   b = (K^T g, -R^T g, q x g, g).
+// Index of H entry (r, c), r <= c, in the row-major upper triangle of 12 x 12.
+__host__ __device__ constexpr int pair_index(int r, int c) {
+  return r * 12 - (r * (r - 1)) / 2 + (c - r);
+}
+static_assert(pair_index(11, 11) == 77, "78 upper-triangle entries");
+
+// Target-frame residual and transformed point: q = R mu + t and e = m - q in
+// FP64 from the FP32 point and voxel mean, each rounded once to FP32.
+__device__ __forceinline__ void residual64_target(const double R[9], const double t[3], float x,
+                                                  float y, float z, const float m[3], float e[3],
+                                                  float q[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double qq = __builtin_fma(R[3 * r + 2], double(z),
+                                    __builtin_fma(R[3 * r + 1], double(y),
+                                                  __builtin_fma(R[3 * r], double(x), t[r])));
+    q[r] = float(qq);
+    e[r] = float(double(m[r]) - qq);
+  }
+}
+
+// Adds one correspondence in the pair form: (mx, my, mz) is the source point,
+// c its covariance, e and q from residual64_target (or the FP32 transform),
+// S the voxel covariance.  Returns false, adding nothing, when the fused
+// covariance is not positive definite.
+template <int FUSE, typename SumsT>
+__device__ __forceinline__ bool add_pair_terms(SumsT &acc, const FactorConsts &k, float kappa,
+                                               float mx, float my, float mz, const float c[6],
+                                               const float e[3], const float q[3],
+                                               const float S[6], uint32_t &nwide) {
+#pragma clang fp contract(off)
+#define FMA __builtin_fmaf
+  const float *R = k.R;
+  // F = (R^T)^T C (R^T) + C' with the transposed rotation
+  const float RT[9] = {R[0], R[3], R[6], R[1], R[4], R[7], R[2], R[5], R[8]};
+  const double RT64[9] = {k.R64[0], k.R64[3], k.R64[6], k.R64[1], k.R64[4],
+                          k.R64[7], k.R64[2], k.R64[5], k.R64[8]};
+  float w[6];
+  if (!fused_weight<FUSE>(RT, RT64, c, S, kappa, nwide, w)) return false;  // not PD
+  const float O[9] = {w[0], w[1], w[2], w[1], w[3], w[4], w[2], w[4], w[5]};
+  float N[9];  // Omega R
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      N[3 * r + cc] = FMA(O[3 * r + 2], R[6 + cc], FMA(O[3 * r + 1], R[3 + cc], O[3 * r] * R[cc]));
+  // X [v]x for a 3 x 3 X: column 0 = vz X_1 - vy X_2, 1 = vx X_2 - vz X_0,
+  // 2 = vy X_0 - vx X_1 (X_c: column c)
+  auto cross_cols = [&](const float X[9], float vx, float vy, float vz, float Y[9]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float x0 = X[3 * r], x1 = X[3 * r + 1], x2 = X[3 * r + 2];
+      Y[3 * r] = FMA(vz, x1, -(vy * x2));
+      Y[3 * r + 1] = FMA(vx, x2, -(vz * x0));
+      Y[3 * r + 2] = FMA(vy, x0, -(vx * x1));
+    }
+  };
+  float Pw[9], K[9], Q[9];
+  cross_cols(N, mx, my, mz, Pw);  // Omega R [mu]x
+  cross_cols(R, mx, my, mz, K);   // R [mu]x
+  cross_cols(O, q[0], q[1], q[2], Q);  // Omega [q]x
+  // column a of P = Omega A (a < 3: Pw, else -N)
+  auto P = [&](int r, int a) { return a < 3 ? Pw[3 * r + a] : -N[3 * r + a - 3]; };
+  auto dot3 = [&](float a0, float a1, float a2, float b0, float b1, float b2) {
+    return FMA(a2, b2, FMA(a1, b1, a0 * b0));
+  };
+  // H_ii: A^T P, with A's columns (K, -R)
+  auto A = [&](int r, int a) { return a < 3 ? K[3 * r + a] : -R[3 * r + a - 3]; };
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b2 = a; b2 < 6; ++b2)
+      acc.add(pair_index(a, b2), dot3(A(0, a), A(1, a), A(2, a), P(0, b2), P(1, b2), P(2, b2)));
+  // H_ij = [P^T (-[q]x), P^T]
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const float p0 = P(0, a), p1 = P(1, a), p2 = P(2, a);
+    acc.add(pair_index(a, 6), FMA(p2, q[1], -(p1 * q[2])));
+    acc.add(pair_index(a, 7), FMA(p0, q[2], -(p2 * q[0])));
+    acc.add(pair_index(a, 8), FMA(p1, q[0], -(p0 * q[1])));
+    acc.add(pair_index(a, 9), p0);
+    acc.add(pair_index(a, 10), p1);
+    acc.add(pair_index(a, 11), p2);
+  }
+  // H_jj = [[-[q]x Q, -Q^T], [., Omega]]
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const float q0 = Q[cc], q1 = Q[3 + cc], q2 = Q[6 + cc];  // column cc of Q
+    const float t0 = FMA(q[2], q1, -(q[1] * q2));
+    const float t1 = FMA(q[0], q2, -(q[2] * q0));
+    const float t2 = FMA(q[1], q0, -(q[0] * q1));
+    acc.add(pair_index(6, 6 + cc), t0);
+    if (cc >= 1) acc.add(pair_index(7, 6 + cc), t1);
+    if (cc >= 2) acc.add(pair_index(8, 6 + cc), t2);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) acc.add(pair_index(6 + r, 9 + cc), -Q[3 * cc + r]);
+  acc.add(pair_index(9, 9), O[0]);
+  acc.add(pair_index(9, 10), O[1]);
+  acc.add(pair_index(9, 11), O[2]);
+  acc.add(pair_index(10, 10), O[4]);
+  acc.add(pair_index(10, 11), O[5]);
+  acc.add(pair_index(11, 11), O[8]);
+  // b and the cost
+  const float g0 = dot3(O[0], O[1], O[2], e[0], e[1], e[2]);
+  const float g1 = dot3(O[3], O[4], O[5], e[0], e[1], e[2]);
+  const float g2 = dot3(O[6], O[7], O[8], e[0], e[1], e[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc.add(78 + a, dot3(K[a], K[3 + a], K[6 + a], g0, g1, g2));
+    acc.add(81 + a, -dot3(R[a], R[3 + a], R[6 + a], g0, g1, g2));
+  }
+  acc.add(84, FMA(q[1], g2, -(q[2] * g1)));
+  acc.add(85, FMA(q[2], g0, -(q[0] * g2)));
+  acc.add(86, FMA(q[0], g1, -(q[1] * g0)));
+  acc.add(87, g0);
+  acc.add(88, g1);
+  acc.add(89, g2);
+  acc.add(90, dot3(e[0], e[1], e[2], g0, g1, g2));
+#undef FMA
+  return true;
+}
+
 // ---------------------------------------------------------------- tiles
 __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
                                                       const double *__restrict__ poses) {
@@ -762,6 +950,8 @@ struct HitQueue {
 };
 
 static_assert(64 * Sums<VGICP_ACC_MIXED, kNumSums>::kStride * sizeof(float) <= sizeof(HitQueue),
+              "the transposed wave sums fit a wave's hit ring");
+static_assert(64 * Sums<VGICP_ACC_F32_COMP, kNumSums>::kStride * sizeof(float) <= sizeof(HitQueue),
               "the transposed wave sums fit a wave's hit ring");
 
 __device__ __forceinline__ uint32_t ring_add(uint32_t e, uint32_t d) {
@@ -829,13 +1019,26 @@ __device__ __forceinline__ CorrOut corr_out(int32_t *corr, const FactorDesc &fd,
   return {corr + fd.corr_offset + begin, nullptr};
 }
 
-template <bool LIN, bool R64, bool CORR, int FUSE, typename SumsT>
+template <bool LIN, bool R64, bool CORR, int FUSE, bool PAIR, typename SumsT>
 __device__ __forceinline__ void batch_math(SumsT &acc, const Batch &B, const FactorConsts &k,
                                            float kappa, const CorrOut &pcorr, uint32_t &nwide,
                                            uint32_t &ndeg) {
   if constexpr (CORR) pcorr.put(uint32_t(B.idx), B.ord);
   const float m[3] = {B.w0.x, B.w0.y, B.w0.z};
   const float S[6] = {B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w, B.czz};
+  if constexpr (PAIR) {
+    float e[3], q[3];
+    if constexpr (R64) {
+      residual64_target(k.R64, k.t64, B.x, B.y, B.z, m, e, q);
+    } else {
+#pragma clang fp contract(off)
+      transform_fp32(k.R, k.t, B.x, B.y, B.z, q);
+      e[0] = m[0] - q[0], e[1] = m[1] - q[1], e[2] = m[2] - q[2];
+    }
+    const bool ok = add_pair_terms<FUSE>(acc, k, kappa, B.x, B.y, B.z, B.c, e, q, S, nwide);
+    ndeg += uint32_t(__popcll(__ballot(!ok)));
+    return;
+  }
   float r[3];
   if constexpr (R64) {
     residual64(k.R64, k.t64, B.x, B.y, B.z, m, r);
@@ -886,13 +1089,21 @@ struct LinearizeLds {
 
 // One tile of k_linearize.  `staged` names the map whose occupancy bits the
 // block's LDS holds (restaged only when the tile's map differs).
-template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
+template <bool LIN, bool PAIR>
+constexpr int tile_sums() {
+  return PAIR ? kNumPairSums : LIN ? kNumSums : 1;
+}
+
+// PAIR: the pair form's 91 sums of the tile go to partials_pair (stride
+// kPairStride), its counters to partials as in the source-frame form.
+template <int ACC, bool LIN, bool R64, bool CORR, int FUSE, bool PAIR = false>
 __device__ __forceinline__ void linearize_tile(
-    LinearizeLds<ACC, LIN ? kNumSums : 1> &L, const uint32_t *&staged, int64_t tile,
+    LinearizeLds<ACC, tile_sums<LIN, PAIR>()> &L, const uint32_t *&staged, int64_t tile,
     const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles, int32_t tile_points,
     const double *__restrict__ poses, double *__restrict__ partials, int32_t *__restrict__ corr,
-    float kappa) {
-  constexpr int N = LIN ? kNumSums : 1;
+    float kappa, double *__restrict__ partials_pair = nullptr) {
+  static_assert(!PAIR || (LIN && !CORR), "the pair form linearizes without correspondences");
+  constexpr int N = tile_sums<LIN, PAIR>();
   using SumsT = Sums<ACC, N>;
   auto &lds = L.sums;
   auto &lds_cnt = L.cnt;
@@ -1003,18 +1214,18 @@ __device__ __forceinline__ void linearize_tile(
       for (; bi + 1 < nb; bi += 2) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, A, k, kappa, pcorr, nwide, ndeg);
         batch_load<CORR>(A, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, B, k, kappa, pcorr, nwide, ndeg);
       }
       if (bi < nb) {
         batch_load<CORR>(B, Q, ring_add(head, lane), true, rc, rs, ri);
         head = ring_add(head, 64);
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
-        batch_math<LIN, R64, CORR, FUSE>(acc, B, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, A, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, B, k, kappa, pcorr, nwide, ndeg);
       } else {
-        batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
+        batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, A, k, kappa, pcorr, nwide, ndeg);
       }
       count -= nb * 64;
     }
@@ -1024,7 +1235,7 @@ __device__ __forceinline__ void linearize_tile(
     const bool live = lane < count;
     Batch A;
     batch_load<CORR>(A, Q, ring_add(head, live ? lane : 0), live, rc, rs, ri);
-    if (live) batch_math<LIN, R64, CORR, FUSE>(acc, A, k, kappa, pcorr, nwide, ndeg);
+    if (live) batch_math<LIN, R64, CORR, FUSE, PAIR>(acc, A, k, kappa, pcorr, nwide, ndeg);
   }
 
   // the ring is empty: its LDS holds the transposed sums now
@@ -1039,19 +1250,24 @@ __device__ __forceinline__ void linearize_tile(
   if (lane == 0) lds_deg[wave] = int(ndeg);
   __syncthreads();
   double *__restrict__ out = partials + tile * kPartialStride;
+  static_assert(N <= kBlock - 3, "the counters' threads hold no sum");
   if (threadIdx.x < N) {
-    out[LIN ? threadIdx.x : 27] = SumsT::finish(lds, threadIdx.x);
-  } else if (threadIdx.x == 32) {
+    const double v = SumsT::finish(lds, threadIdx.x);
+    if constexpr (PAIR)
+      partials_pair[tile * kPairStride + threadIdx.x] = v;
+    else
+      out[LIN ? threadIdx.x : 27] = v;
+  } else if (threadIdx.x == kBlock - 3) {
     int s = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += lds_cnt[w];
     out[kNumSums] = double(s);
-  } else if (threadIdx.x == 33) {
+  } else if (threadIdx.x == kBlock - 2) {
     int s = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += lds_wide[w];
     out[kWideSlot] = double(s);
-  } else if (threadIdx.x == 34) {
+  } else if (threadIdx.x == kBlock - 1) {
     int s = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += lds_deg[w];
@@ -1086,6 +1302,29 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base + t), factors, tiles,
                                               tile_points, poses, partials, corr, kappa);
+}
+
+// The pair form (Eqs. (5)-(6) term by term) over the tiles [tile_base,
+// tile_end), tiles dealt as in k_linearize.  Its 91 FP32 sums per lane take
+// about 200 VGPRs: 2 waves per SIMD.
+template <int ACC, bool R64, int FUSE>
+__global__ void __launch_bounds__(kBlock, 2)
+k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
+                 int64_t tile_base, int64_t tile_end, int32_t tile_points,
+                 const double *__restrict__ poses, double *__restrict__ partials,
+                 double *__restrict__ partials_pair, float kappa) {
+  __shared__ LinearizeLds<ACC, kNumPairSums> L;
+  const uint32_t base = uint32_t(tile_base), count = uint32_t(tile_end - tile_base);
+  const uint32_t per = (count + 7u) >> 3;
+  const uint32_t lo = (blockIdx.x & 7u) * per;
+  const uint32_t hi = min(lo + per, count);
+  const uint32_t P = gridDim.x >> 3;
+  const uint32_t *staged = nullptr;
+  up_table_fill(L.up);  // read after the first tile's barrier
+  for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
+    linearize_tile<ACC, true, R64, false, FUSE, true>(L, staged, int64_t(base + t), factors,
+                                                      tiles, tile_points, poses, partials,
+                                                      nullptr, kappa, partials_pair);
 }
 
 // Overlap hit count of one tile (Eq. (7)): brick records only.
@@ -1328,6 +1567,40 @@ k_reduce(const FactorDesc *__restrict__ factors, int64_t factor_base,
   }
 }
 
+// Pair form: one 64-lane block per factor adds the factor's tile partials in
+// tile order (FP64) and writes the 12 x 12 H from its upper triangle, b, e
+// and the inliers.
+__global__ void __launch_bounds__(64)
+k_reduce_pair(const FactorDesc *__restrict__ factors, int64_t factor_base,
+              const double *__restrict__ partials, const double *__restrict__ partials_pair,
+              double *__restrict__ H, double *__restrict__ b, double *__restrict__ e,
+              int64_t *__restrict__ inl) {
+  __shared__ double s[kPairStride];
+  const int64_t f = factor_base + blockIdx.x;
+  const FactorDesc fd = factors[f];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < kNumPairSums; i += 64) {
+    double acc = 0.0;
+    for (int32_t tt = 0; tt < fd.n_tiles; ++tt)
+      acc += partials_pair[int64_t(fd.tile_begin + tt) * kPairStride + i];
+    s[i] = acc;
+  }
+  if (lane == 0) {
+    double hits = 0.0;
+    for (int32_t tt = 0; tt < fd.n_tiles; ++tt)
+      hits += partials[int64_t(fd.tile_begin + tt) * kPartialStride + kNumSums];
+    inl[f] = int64_t(hits);
+  }
+  __syncthreads();
+  double *__restrict__ Hf = H + f * 144;
+  for (int idx = lane; idx < 144; idx += 64) {
+    const int r = idx / 12, c = idx % 12;
+    Hf[idx] = r <= c ? s[pair_index(r, c)] : s[pair_index(c, r)];
+  }
+  if (lane < 12) b[f * 12 + lane] = s[78 + lane];
+  if (lane == 0) e[f] = s[90];
+}
+
 // ---------------------------------------------------------------- assembly
 // One 64-lane block per pose: lanes 0..35 own an entry of the 6x6 diagonal
 // block, lanes 36..41 an entry of b.  Contributions are added in CSR order
@@ -1434,10 +1707,26 @@ static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, boo
   }
 }
 
-// Blocks of the linearization kernel for (accum, fused) one CU holds at once.
-hipError_t linearize_blocks_per_cu(int accum, int fused, int *blocks) {
+// Blocks of the linearization kernel for (accum, fused, form) one CU holds at once.
+hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks) {
   const void *fn;
   const bool f64 = fused == VGICP_FUSED_F64;
+  if (form == VGICP_FORM_PAIR) {
+    switch (accum) {
+      case VGICP_ACC_F32_COMP:
+        fn = f64 ? (const void *)k_linearize_pair<VGICP_ACC_F32_COMP, true, kFuse64>
+                 : (const void *)k_linearize_pair<VGICP_ACC_F32_COMP, true, kFuse32>;
+        break;
+      case VGICP_ACC_F32:
+        fn = f64 ? (const void *)k_linearize_pair<VGICP_ACC_F32, true, kFuse64>
+                 : (const void *)k_linearize_pair<VGICP_ACC_F32, true, kFuse32>;
+        break;
+      default:
+        fn = f64 ? (const void *)k_linearize_pair<VGICP_ACC_MIXED, true, kFuse64>
+                 : (const void *)k_linearize_pair<VGICP_ACC_MIXED, true, kFuse32>;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
+  }
   switch (accum) {
     case VGICP_ACC_F64:
       fn = f64 ? (const void *)k_linearize<VGICP_ACC_F64, true, true, false, kFuse64>
@@ -1475,6 +1764,62 @@ hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, i
                             int32_t *corr, hipStream_t st) {
   return launch_linearize_into(fs, accum, resid, fused, kappa, lin, tb, te, poses,
                                fs->d_partials, corr, st);
+}
+
+template <int ACC, int FUSE>
+static hipError_t launch_pair_acc(const vgicp_factorset_s *fs, bool r64, int64_t tb, int64_t te,
+                                  const double *poses, double *partials, double *partials_pair,
+                                  float kappa, hipStream_t st) {
+  const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
+  if (r64)
+    k_linearize_pair<ACC, true, FUSE><<<grid, kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, partials_pair,
+        kappa);
+  else
+    k_linearize_pair<ACC, false, FUSE><<<grid, kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, partials_pair,
+        kappa);
+  return hipGetLastError();
+}
+
+template <int FUSE>
+static hipError_t launch_pair_k(const vgicp_factorset_s *fs, int accum, bool r64, int64_t tb,
+                                int64_t te, const double *poses, double *partials,
+                                double *partials_pair, float kappa, hipStream_t st) {
+  switch (accum) {
+    case VGICP_ACC_F32_COMP:
+      return launch_pair_acc<VGICP_ACC_F32_COMP, FUSE>(fs, r64, tb, te, poses, partials,
+                                                        partials_pair, kappa, st);
+    case VGICP_ACC_F32:
+      return launch_pair_acc<VGICP_ACC_F32, FUSE>(fs, r64, tb, te, poses, partials,
+                                                   partials_pair, kappa, st);
+    default:
+      return launch_pair_acc<VGICP_ACC_MIXED, FUSE>(fs, r64, tb, te, poses, partials,
+                                                     partials_pair, kappa, st);
+  }
+}
+
+hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                                 float kappa, int64_t tb, int64_t te, const double *poses,
+                                 hipStream_t st) {
+  if (te <= tb) return hipSuccess;
+  if (accum == VGICP_ACC_F64) return hipErrorInvalidValue;  // rejected by the callers
+  const bool r64 = resid == VGICP_RESID_F64;
+  double *pp = fs->d_partials_pair;
+  if (fused == VGICP_FUSED_F64)
+    return launch_pair_k<kFuse64>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, 0.f, st);
+  if (kappa > 0.f)
+    return launch_pair_k<kFuseGate>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, kappa,
+                                    st);
+  return launch_pair_k<kFuse32>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, 0.f, st);
+}
+
+hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,
+                              double *b, double *e, int64_t *inl, hipStream_t st) {
+  if (nf <= 0) return hipSuccess;
+  k_reduce_pair<<<unsigned(nf), 64, 0, st>>>(fs->d_factors, f0, fs->d_partials,
+                                              fs->d_partials_pair, H, b, e, inl);
+  return hipGetLastError();
 }
 
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,

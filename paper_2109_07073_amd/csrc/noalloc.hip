@@ -69,6 +69,10 @@ int vgicp_linearize_factors_noalloc(vgicp_ctx ctx, vgicp_factorset fs, const dou
   if (o.use_graph)
     return set_error(ctx, VGICP_EINVAL,
                      std::string(who) + ": use_graph must be 0 (capturing a graph allocates)");
+  if (o.form == VGICP_FORM_PAIR)
+    return set_error(ctx, VGICP_EINVAL,
+                     std::string(who) + ": the scratch array holds source-frame partials only "
+                                        "(form must be VGICP_FORM_AUTO or VGICP_FORM_SOURCE)");
   if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
     return set_error(ctx, VGICP_EINVAL, std::string(who) + ": an output pointer is NULL");
   if (fs->n_tiles > kScratchTiles)

@@ -24,7 +24,12 @@ hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, co
                          double *overlap, hipStream_t st);
 hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const double *b,
                            double *Hdiag, double *bvec, double *Hoff, hipStream_t st);
-hipError_t linearize_blocks_per_cu(int accum, int fused, int *blocks);
+hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks);
+hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
+                                 float kappa, int64_t tb, int64_t te, const double *poses,
+                                 hipStream_t st);
+hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,
+                              double *b, double *e, int64_t *inl, hipStream_t st);
 }  // namespace vgicp
 
 using namespace vgicp;
@@ -558,6 +563,7 @@ int vgicp_factorset_destroy(vgicp_factorset fs) {
   if (fs->d_factors) (void)hipFree(fs->d_factors);
   if (fs->d_tiles) (void)hipFree(fs->d_tiles);
   if (fs->d_partials) (void)hipFree(fs->d_partials);
+  if (fs->d_partials_pair) (void)hipFree(fs->d_partials_pair);
   if (fs->d_sorted) (void)hipFree(fs->d_sorted);
   for (int64_t *p : {fs->d_pose_off, fs->d_pose_ent, fs->d_pair_off, fs->d_pair_ent})
     if (p) (void)hipFree(p);
@@ -588,7 +594,7 @@ int vgicp::check_common(vgicp_ctx ctx, vgicp_factorset fs, const double *poses, 
 
 int vgicp::read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const char *who) {
   *o = vgicp_opts{VGICP_ACC_MIXED, VGICP_SCHED_BATCHED, 0, VGICP_RESID_F64, 0.0f,
-                  VGICP_FUSED_F64};
+                  VGICP_FUSED_F64, VGICP_FORM_AUTO};
   if (opts) *o = *opts;
   if (o->accum != VGICP_ACC_MIXED && o->accum != VGICP_ACC_F32 && o->accum != VGICP_ACC_F64 &&
       o->accum != VGICP_ACC_F32_COMP)
@@ -601,19 +607,77 @@ int vgicp::read_opts(vgicp_ctx ctx, const vgicp_opts *opts, vgicp_opts *o, const
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": fp64_kappa must be finite and >= 0");
   if (o->fused != VGICP_FUSED_F64 && o->fused != VGICP_FUSED_F32)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown fused-covariance precision");
+  if (o->form != VGICP_FORM_AUTO && o->form != VGICP_FORM_SOURCE && o->form != VGICP_FORM_PAIR)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown form");
+  if (o->form == VGICP_FORM_PAIR && o->accum == VGICP_ACC_F64)
+    return fail(ctx, VGICP_EINVAL,
+                std::string(who) + ": the pair form accumulates in FP32 per lane (mixed, f32 "
+                                   "or f32_comp)");
   return VGICP_OK;
 }
 
 namespace {
+
+// The form a linearization runs in: opts' form, or under VGICP_FORM_AUTO the
+// factor set's where the pair form applies.
+int resolve_form(const vgicp_factorset_s *fs, const vgicp_opts &o, const int32_t *corr) {
+  if (o.form != VGICP_FORM_AUTO) return o.form;
+  if (fs->form == VGICP_FORM_PAIR && !corr && o.accum != VGICP_ACC_F64) return VGICP_FORM_PAIR;
+  return VGICP_FORM_SOURCE;
+}
+
+void drop_graphs(vgicp_factorset fs) {
+  for (auto &g : fs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  fs->graphs.clear();
+}
+
+// The pair form's tile partials, allocated at its first call and again when
+// the tiles have outgrown them (captured graphs hold the old buffer and are
+// dropped after the stream's pending work).
+int ensure_pair_partials(vgicp_ctx ctx, vgicp_factorset fs, const char *who) {
+  if (fs->d_partials_pair && fs->pair_capacity >= fs->n_tiles) return VGICP_OK;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  drop_graphs(fs);
+  if (fs->d_partials_pair) (void)hipFree(fs->d_partials_pair);
+  fs->d_partials_pair = nullptr;
+  fs->pair_capacity = 0;
+  const int64_t nt = std::max<int64_t>(std::max(fs->tiles_capacity, fs->n_tiles), 1);
+  e = hipMalloc(&fs->d_partials_pair, size_t(nt) * kPairStride * sizeof(double));
+  if (e != hipSuccess) return hip_fail(ctx, who, e);
+  fs->pair_capacity = nt;
+  return VGICP_OK;
+}
 
 // Enqueue the factors' tiles [tb, te) and the reduce of factors [f0, f0+nf).
 // `ctx` is NULL inside graph capture (no timing events there).
 hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum, int resid,
                          int fused, float kappa, const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
                          double *H, double *b, double *e, int64_t *inl, int32_t *corr,
-                         hipStream_t st) {
+                         hipStream_t st, int form = VGICP_FORM_SOURCE) {
   const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
   hipError_t err = hipSuccess;
+  if (form == VGICP_FORM_PAIR && kind == kKindLinearize) {
+    if (ctx) {
+      TimedLaunch t(ctx, tk);
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st);
+      t.done();
+    } else {
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st);
+    }
+    if (err != hipSuccess) return err;
+    if (ctx) {
+      TimedLaunch t(ctx, VGICP_KERNEL_REDUCE);
+      err = launch_reduce_pair(fs, f0, nf, H, b, e, inl, st);
+      t.done();
+    } else {
+      err = launch_reduce_pair(fs, f0, nf, H, b, e, inl, st);
+    }
+    return err;
+  }
   if (ctx) {
     TimedLaunch t(ctx, tk);
     err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
@@ -640,18 +704,25 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   if (fs->n_factors == 0) return VGICP_OK;
   hipStream_t st = ctx->stream;
   hipError_t err = hipSuccess;
+  if (o.form == VGICP_FORM_PAIR && corr && kind == kKindLinearize)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": the pair form writes no correspondences");
+  const int form = kind == kKindLinearize ? resolve_form(fs, o, corr) : VGICP_FORM_SOURCE;
+  if (form == VGICP_FORM_PAIR) {
+    const int rc = ensure_pair_partials(ctx, fs, who);
+    if (rc) return rc;
+  }
   if (o.schedule == VGICP_SCHED_PER_FACTOR) {
     for (int64_t f = 0; f < fs->n_factors && err == hipSuccess; ++f) {
       const FactorDesc &d = fs->h_factors[size_t(f)];
       err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, d.tile_begin,
-                          int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st);
+                          int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st, form);
     }
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
   }
   if (!o.use_graph) {
     err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, 0, fs->n_tiles, 0, fs->n_factors, H, b, e,
-                        inl, corr, st);
+                        inl, corr, st, form);
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
   }
@@ -661,7 +732,7 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
   for (auto &x : fs->graphs)
     if (x.poses == poses && x.H == H && x.b == b && x.e == e && x.inl == inl && x.corr == corr &&
         x.accum == o.accum && x.resid == o.resid && x.fused == o.fused &&
-        x.kappa == o.fp64_kappa && x.kind == kind)
+        x.kappa == o.fp64_kappa && x.kind == kind && x.form == form)
       g = &x;
   if (!g && fs->graphs.size() >= kMaxGraphs) {
     // drop the least recently replayed graph (after its last launch is done)
@@ -675,11 +746,11 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
     fs->graphs.erase(fs->graphs.begin() + std::ptrdiff_t(lru));
   }
   if (!g) {
-    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fused, o.fp64_kappa, kind};
+    GraphEntry ng{poses, H, b, e, inl, corr, o.accum, o.resid, o.fused, o.fp64_kappa, kind, form};
     err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(ctx, "hipStreamBeginCapture", err);
     hipError_t lerr = enqueue_range(nullptr, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, 0, fs->n_tiles, 0,
-                                    fs->n_factors, H, b, e, inl, corr, st);
+                                    fs->n_factors, H, b, e, inl, corr, st, form);
     err = hipStreamEndCapture(st, &ng.graph);
     if (lerr != hipSuccess) {
       if (ng.graph) (void)hipGraphDestroy(ng.graph);
@@ -830,27 +901,39 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
     if (t0) (void)hipEventDestroy(t0);
     return hip_fail(ctx, who, he);
   }
-  // the persistent grid: as many blocks as the CUs hold at once
-  int per_cu = 0;
-  he = linearize_blocks_per_cu(o.accum, o.fused, &per_cu);
-  if (he != hipSuccess) {
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    return hip_fail(ctx, who, he);
+  // forms to time: both under VGICP_FORM_AUTO where the pair form applies
+  int forms[2] = {o.form == VGICP_FORM_AUTO ? VGICP_FORM_SOURCE : o.form, VGICP_FORM_PAIR};
+  const int n_forms = (o.form == VGICP_FORM_AUTO && o.accum != VGICP_ACC_F64) ? 2 : 1;
+  // the persistent grid of each form: as many blocks as the CUs hold at once
+  int32_t persist[2] = {8, 8};
+  for (int fi = 0; fi < n_forms; ++fi) {
+    int per_cu = 0;
+    he = linearize_blocks_per_cu(o.accum, o.fused, forms[fi], &per_cu);
+    if (he != hipSuccess) {
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      return hip_fail(ctx, who, he);
+    }
+    persist[fi] = std::max(8, (ctx->cu_count * std::max(per_cu, 1)) / 8 * 8);
   }
-  const int32_t persist = std::max(8, (ctx->cu_count * std::max(per_cu, 1)) / 8 * 8);
-  const int32_t grids[2] = {0, persist};
-  std::vector<double> grid_ms(size_t(2 * n_candidates), 1e300);
+  // slot (form, candidate, grid) -> best mean round time
+  std::vector<double> grid_ms(size_t(2 * n_forms * n_candidates), 1e300);
+  auto slot_of = [&](int fi, int32_t k, int g) { return size_t((fi * n_candidates + k) * 2 + g); };
   for (int32_t step = 0; step < 2 * n_candidates && rc == VGICP_OK; ++step) {
-    const int32_t k = step < n_candidates ? step : 2 * n_candidates - 1 - step;
+    const bool fwd = step < n_candidates;
+    const int32_t k = fwd ? step : 2 * n_candidates - 1 - step;
     rc = set_tiles(ctx, fs, candidates[k], who);
-    for (int g = 0; g < 2 && rc == VGICP_OK; ++g) {
-      fs->persist_blocks = grids[step < n_candidates ? g : 1 - g];
+    for (int q = 0; q < 2 * n_forms && rc == VGICP_OK; ++q) {
+      const int qq = fwd ? q : 2 * n_forms - 1 - q;
+      const int fi = qq / 2, g = qq % 2;
+      vgicp_opts of = o;
+      of.form = forms[fi];
+      fs->persist_blocks = g ? persist[fi] : 0;
       for (int r = 0; r < kWarm + kTimed && rc == VGICP_OK; ++r) {
         if (r == kWarm && (he = hipEventRecord(t0, ctx->stream)) != hipSuccess)
           rc = hip_fail(ctx, who, he);
         if (rc == VGICP_OK)
-          rc = run_factors(ctx, fs, kKindLinearize, poses, o, H, b, e, inliers, nullptr, who);
+          rc = run_factors(ctx, fs, kKindLinearize, poses, of, H, b, e, inliers, nullptr, who);
       }
       float ms = 0.f;
       if (rc == VGICP_OK && (he = hipEventRecord(t1, ctx->stream)) != hipSuccess)
@@ -859,14 +942,16 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
         rc = hip_fail(ctx, who, he);
       if (rc == VGICP_OK && (he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
         rc = hip_fail(ctx, who, he);
-      const size_t slot = size_t(2 * k + (fs->persist_blocks ? 1 : 0));
+      const size_t slot = slot_of(fi, k, g);
       if (rc == VGICP_OK) grid_ms[slot] = std::min(grid_ms[slot], double(ms) / kTimed);
     }
   }
   size_t best_slot = 0;
   for (size_t q = 1; q < grid_ms.size(); ++q)
     if (grid_ms[q] < grid_ms[best_slot]) best_slot = q;
-  const int32_t best = candidates[best_slot / 2];
+  const int best_fi = int(best_slot / size_t(2 * n_candidates));
+  const int32_t best = candidates[(best_slot / 2) % size_t(n_candidates)];
+  const int best_g = int(best_slot % 2);
   const double best_t = grid_ms[best_slot];
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
@@ -874,7 +959,8 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc != VGICP_OK) return rc;
   rc = set_tiles(ctx, fs, best, who);
   if (rc != VGICP_OK) return rc;
-  fs->persist_blocks = grids[best_slot % 2];
+  fs->persist_blocks = best_g ? persist[best_fi] : 0;
+  if (o.form == VGICP_FORM_AUTO) fs->form = forms[best_fi];
   if (best_tile) *best_tile = best;
   if (best_ms) *best_ms = best_t;
   return VGICP_OK;
@@ -897,6 +983,12 @@ int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double 
   if (!avg_ms) return fail(ctx, VGICP_EINVAL, std::string(who) + ": avg_ms is NULL");
   *avg_ms = 0.0;
   if (fs->n_tiles == 0) return VGICP_OK;
+  const bool pair =
+      kernel == VGICP_KERNEL_LINEARIZE && resolve_form(fs, o, nullptr) == VGICP_FORM_PAIR;
+  if (pair) {
+    rc = ensure_pair_partials(ctx, fs, who);
+    if (rc) return rc;
+  }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -904,6 +996,9 @@ int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double 
   for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
     if (kernel == VGICP_KERNEL_OVERLAP)
       e = launch_overlap(fs, 0, fs->n_tiles, poses, ctx->stream);
+    else if (pair)
+      e = launch_linearize_pair(fs, o.accum, o.resid, o.fused, o.fp64_kappa, 0, fs->n_tiles, poses,
+                                ctx->stream);
     else
       e = launch_linearize(fs, o.accum, o.resid, o.fused, o.fp64_kappa,
                            kernel == VGICP_KERNEL_LINEARIZE, 0, fs->n_tiles, poses, nullptr,
@@ -947,6 +1042,12 @@ int vgicp_factorset_set_grid(vgicp_ctx ctx, vgicp_factorset fs, int32_t persist_
 int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks) {
   if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_grid: factor set is NULL");
   if (persist_blocks) *persist_blocks = fs->persist_blocks;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_form(vgicp_factorset fs, int32_t *form) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_form: factor set is NULL");
+  if (form) *form = fs->form;
   return VGICP_OK;
 }
 

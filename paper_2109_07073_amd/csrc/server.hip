@@ -467,7 +467,8 @@ int vgicp_server_create(int device, const vgicp_server_config *cfg, vgicp_server
   if ((o.accum != VGICP_ACC_MIXED && o.accum != VGICP_ACC_F32 && o.accum != VGICP_ACC_F64 &&
        o.accum != VGICP_ACC_F32_COMP) ||
       (o.resid != VGICP_RESID_F64 && o.resid != VGICP_RESID_F32) || !(o.fp64_kappa >= 0.0f) ||
-      !std::isfinite(o.fp64_kappa) || (o.fused != VGICP_FUSED_F64 && o.fused != VGICP_FUSED_F32))
+      !std::isfinite(o.fp64_kappa) || (o.fused != VGICP_FUSED_F64 && o.fused != VGICP_FUSED_F32) ||
+      (o.form != VGICP_FORM_AUTO && o.form != VGICP_FORM_SOURCE))
     return VGICP_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VGICP_EHIP;

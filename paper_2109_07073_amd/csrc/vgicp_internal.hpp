@@ -237,6 +237,11 @@ constexpr int kPartialStride = 32;
 constexpr int kNumSums = 28;
 constexpr int kWideSlot = 29;
 constexpr int kDegenerateSlot = 30;
+// The pair form's tile partials: 78 upper-triangle entries of the 12 x 12 H
+// (row-major), b (12) and the cost, one row of kPairStride doubles per tile;
+// its counters use the slots above in the source-frame partials.
+constexpr int kNumPairSums = 91;
+constexpr int kPairStride = 96;
 
 // Error bits of the device error word.
 constexpr uint32_t kErrNonFinite = 1u;
@@ -315,6 +320,7 @@ struct GraphEntry {
   int fused;
   float kappa;
   int kind;
+  int form;  // VGICP_FORM_SOURCE or VGICP_FORM_PAIR
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint64_t last_use = 0;  // factor set's replay counter at the last launch
@@ -336,6 +342,11 @@ struct vgicp_factorset_s {
   vgicp::FactorDesc *d_factors = nullptr;  // device
   vgicp::Tile *d_tiles = nullptr;          // device
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
+  // Pair-form tile partials, [pair_capacity][kPairStride], allocated at the
+  // first pair-form call.
+  double *d_partials_pair = nullptr;
+  int64_t pair_capacity = 0;
+  int32_t form = VGICP_FORM_SOURCE;  // the form of VGICP_FORM_AUTO calls
   std::vector<vgicp::FactorDesc> h_factors;
   std::vector<int64_t> tile_order;  // factors in tile order (grouped by target map)
   void *d_sorted = nullptr;  // device: ordered copies of the source clouds

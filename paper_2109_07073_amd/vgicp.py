@@ -31,6 +31,7 @@ KERNELS = {"linearize": 0, "reduce": 1, "overlap": 2, "evaluate": 3}
 SCHED = {"batched": 0, "per_factor": 1}
 RESID = {"f64": 0, "f32": 1}
 FUSED = {"f64": 0, "f32": 1}
+FORM = {"auto": 0, "source": 1, "pair": 2}
 NOALLOC_MAX_TILES = 32768      # VGICP_NOALLOC_MAX_TILES
 
 
@@ -52,7 +53,8 @@ class CFactor(ctypes.Structure):
 class COpts(ctypes.Structure):
     _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32),
-                ("fp64_kappa", ctypes.c_float), ("fused", ctypes.c_int32)]
+                ("fp64_kappa", ctypes.c_float), ("fused", ctypes.c_int32),
+                ("form", ctypes.c_int32)]
 
 
 class CSubmapRules(ctypes.Structure):
@@ -110,6 +112,7 @@ _PROTOS = {
     "vgicp_factorset_set_grid": (ctypes.c_int, [_vp, _vp, _i32]),
     "vgicp_factorset_time_kernel": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _i32, _i32, _P(_dbl)]),
     "vgicp_factorset_grid": (ctypes.c_int, [_vp, _P(_i32)]),
+    "vgicp_factorset_form": (ctypes.c_int, [_vp, _P(_i32)]),
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
@@ -443,7 +446,7 @@ class FactorSet:
 
 
 def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "f64",
-          fp64_kappa: float = 0.0, fused: str = "f64") -> COpts:
+          fp64_kappa: float = 0.0, fused: str = "f64", form: str = "auto") -> COpts:
     if accum not in ACC:
         raise ValueError(f"accum must be one of {sorted(ACC)}")
     if schedule not in SCHED:
@@ -452,8 +455,10 @@ def _opts(accum: str, schedule: str, use_graph: bool, resid: str = "f64",
         raise ValueError(f"resid must be one of {sorted(RESID)}")
     if fused not in FUSED:
         raise ValueError(f"fused must be one of {sorted(FUSED)}")
+    if form not in FORM:
+        raise ValueError(f"form must be one of {sorted(FORM)}")
     return COpts(ACC[accum], SCHED[schedule], int(bool(use_graph)), RESID[resid],
-                 float(fp64_kappa), FUSED[fused])
+                 float(fp64_kappa), FUSED[fused], FORM[form])
 
 
 def _check_poses(fs: FactorSet, poses):
@@ -464,11 +469,14 @@ def _check_poses(fs: FactorSet, poses):
 def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "mixed",
                       schedule: str = "batched", use_graph: bool = False,
                       with_corr: bool = False, out=None, resid: str = "f64",
-                      fp64_kappa: float = 0.0, fused: str = "f64"):
+                      fp64_kappa: float = 0.0, fused: str = "f64", form: str = "auto"):
     """Hessian factors of every factor at `poses` (float64 (P, 12) device).
     Returns dict of device tensors H (F,12,12), b (F,12), e (F,), inliers (F,)
     and corr (total_points,) when asked.  `out` may supply the same dict of
-    preallocated tensors (needed for graph replay with stable pointers)."""
+    preallocated tensors (needed for graph replay with stable pointers).
+    `form`: "source" (21 + 6 + 1 source-frame sums expanded per factor),
+    "pair" (Eqs. (5)-(6) term by term, 78 + 12 + 1 sums) or "auto" (the
+    factor set's form, see tune_tiles)."""
     torch = _torch()
     _graph_needs_out(use_graph, out)
     F = fs.n_factors
@@ -488,7 +496,7 @@ def linearize_factors(ctx: Context, fs: FactorSet, poses, accum: str = "mixed",
     corr = out.get("corr")
     if corr is not None:
         _dev_tensor(corr, torch.int32, (fs.total_points,), "out['corr']")
-    o = _opts(accum, schedule, use_graph, resid, fp64_kappa, fused)
+    o = _opts(accum, schedule, use_graph, resid, fp64_kappa, fused, form)
     _check(_lib.vgicp_linearize_factors(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                         out["H"].data_ptr(), out["b"].data_ptr(),
                                         out["e"].data_ptr(), out["inliers"].data_ptr(),
@@ -561,9 +569,11 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
 
 
 def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str = "mixed",
-               resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64"):
-    """Time a linearization round per candidate tile size and keep the fastest
-    (vgicp_factorset_tune).  Returns (tile_points, ms per round)."""
+               resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64",
+               form: str = "auto"):
+    """Time a linearization round per candidate tile size, grid and (with
+    form "auto") form, and keep the fastest (vgicp_factorset_tune).  Returns
+    (tile_points, ms per round); grid(fs) and form_of(fs) give the rest."""
     torch = _torch()
     _check_poses(fs, poses)
     dev = f"cuda:{ctx.device}"
@@ -572,7 +582,7 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
     b = torch.empty((max(F, 1), 12), dtype=torch.float64, device=dev)
     e = torch.empty((max(F, 1),), dtype=torch.float64, device=dev)
     inl = torch.empty((max(F, 1),), dtype=torch.int64, device=dev)
-    o = _opts(accum, "batched", False, resid, fp64_kappa, fused)
+    o = _opts(accum, "batched", False, resid, fp64_kappa, fused, form)
     cand = None
     n = 0
     if candidates is not None:
@@ -591,7 +601,7 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
 
 def time_kernel(ctx: Context, fs: FactorSet, poses, kernel: str = "linearize", reps: int = 20,
                 accum: str = "mixed", resid: str = "f64", fp64_kappa: float = 0.0,
-                fused: str = "f64") -> float:
+                fused: str = "f64", form: str = "auto") -> float:
     """Mean device milliseconds of one launch of a round's `kernel`
     ("linearize", "evaluate" or "overlap") over the whole factor set, from
     `reps` back-to-back launches between one pair of HIP events
@@ -599,7 +609,7 @@ def time_kernel(ctx: Context, fs: FactorSet, poses, kernel: str = "linearize", r
     _check_poses(fs, poses)
     if kernel not in ("linearize", "evaluate", "overlap"):
         raise ValueError("kernel must be linearize, evaluate or overlap")
-    o = _opts(accum, "batched", False, resid, fp64_kappa, fused)
+    o = _opts(accum, "batched", False, resid, fp64_kappa, fused, form)
     ms = ctypes.c_double()
     _check(_lib.vgicp_factorset_time_kernel(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                             KERNELS[kernel], int(reps), ctypes.byref(ms)),
@@ -619,6 +629,14 @@ def grid(fs: FactorSet) -> int:
     g = ctypes.c_int32()
     _check(_lib.vgicp_factorset_grid(fs.handle, ctypes.byref(g)))
     return g.value
+
+
+def form_of(fs: FactorSet) -> str:
+    """The form "auto" calls use on this factor set ("source" unless
+    tune_tiles chose "pair")."""
+    f = ctypes.c_int32()
+    _check(_lib.vgicp_factorset_form(fs.handle, ctypes.byref(f)))
+    return {v: k for k, v in FORM.items()}[f.value]
 
 
 def reorder_by_target(ctx: Context, fs: FactorSet, poses):
