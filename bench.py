@@ -783,6 +783,8 @@ def main():
     ap.add_argument("--fused", default="f64", choices=["f64", "f32"],
                     help="precision of the fused covariance and its inverse")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--layout", default="auto", choices=["auto", "grouped", "interleaved"],
+                    help="tile-table layout (auto: the tuner's choice, or grouped with --tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reorder", action="store_true",
                     help="keep the Morton-ordered source copies (no target-order copies)")
@@ -858,6 +860,8 @@ def main():
         vg.reorder_by_target(ctx, fs, poses)
         t_reorder = time.perf_counter() - t0
     tuned = None
+    if args.layout != "auto":
+        vg.set_layout(ctx, fs, args.layout)
     if not args.tile:      # measure the candidate tile sizes and keep the fastest
         best, best_ms = vg.tune_tiles(ctx, fs, poses, accum=args.accum, fused=args.fused)
         tuned = {"tile_points": best, "round_ms": round(best_ms, 4)}
@@ -1042,6 +1046,7 @@ def main():
             "tile_points": int(fs.tile_points),
             "grid_blocks": vg.grid(fs),
             "form": form,
+            "layout": vg.layout_of(fs),
             "source_order": "Morton cells" if args.no_reorder else "target voxel order",
             "seed": w.meta.get("seed"),
         },

@@ -109,6 +109,14 @@ extern "C" {
 #define VGICP_SCHED_BATCHED 0    /* one launch over the tiles of all factors, one reduce   */
 #define VGICP_SCHED_PER_FACTOR 1 /* one linearize launch and one reduce launch per factor */
 
+/* Layout of a factor set's tile table (fixed-size point ranges of one factor;
+ * results do not depend on it, bit for bit). */
+#define VGICP_LAYOUT_GROUPED 0     /* factors grouped by target map, each factor's tiles
+                                      consecutive (default)                            */
+#define VGICP_LAYOUT_INTERLEAVED 1 /* the factors that read one source copy side by
+                                      side, tile by tile, so that tiles streaming the
+                                      same source points run together and share L2   */
+
 typedef struct vgicp_context_s *vgicp_ctx;
 typedef struct vgicp_voxelmap_s *vgicp_map;
 typedef struct vgicp_factorset_s *vgicp_factorset;
@@ -255,7 +263,9 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
  * workgroup per tile, and a persistent grid of as many workgroups as the
  * device's CUs hold at once for opts' kernel, each walking several tiles),
  * twice in forward and reverse order keeping each pair's best, and keep the
- * fastest pair.  With opts' form VGICP_FORM_AUTO (the default) and an
+ * fastest pair.  When some source copy is read by more than one factor, every
+ * candidate is timed in both tile-table layouts (VGICP_LAYOUT_*) and the
+ * faster is kept.  With opts' form VGICP_FORM_AUTO (the default) and an
  * accumulation the pair form supports, every candidate is also timed in the
  * pair form and the factor set keeps the faster form for VGICP_FORM_AUTO
  * calls; with another form only that form is timed (and the kept form is not
@@ -264,8 +274,8 @@ int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tile
  * tiles and grid change (results change only by FP32 summation order; the
  * grid alone does not change them) and its captured graphs are dropped.
  * best_tile and best_ms (mean device time of a round) may be NULL; the grid
- * chosen is read with vgicp_factorset_grid and the form with
- * vgicp_factorset_form.  Synchronizes ctx's stream.
+ * chosen is read with vgicp_factorset_grid, the layout with
+ * vgicp_factorset_layout and the form with vgicp_factorset_form.  Synchronizes ctx's stream.
  * Errors: EINVAL, EHIP. */
 int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          const vgicp_opts *opts, double *H, double *b, double *e,
@@ -300,6 +310,16 @@ int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks);
 /* The form VGICP_FORM_AUTO calls use (VGICP_FORM_SOURCE unless
  * vgicp_factorset_tune chose VGICP_FORM_PAIR).  Errors: EINVAL. */
 int vgicp_factorset_form(vgicp_factorset fs, int32_t *form);
+
+/* Tile-table layout (VGICP_LAYOUT_*): rebuilds the tile table at the current
+ * tile size and drops captured graphs (synchronizes ctx's stream).  After
+ * vgicp_factorset_reorder every factor reads its own copy, so the interleaved
+ * layout then only puts the factors of one source next to each other.
+ * Errors: EINVAL, EHIP. */
+int vgicp_factorset_set_layout(vgicp_ctx ctx, vgicp_factorset fs, int32_t layout);
+
+/* The layout in use.  Errors: EINVAL. */
+int vgicp_factorset_layout(vgicp_factorset fs, int32_t *layout);
 
 /* Target-order source copies.  A round streams every source point once and
  * gathers the statistics of the target voxel it falls in (Sec. III-A, Eq. (3)

@@ -1287,7 +1287,7 @@ __device__ __forceinline__ void linearize_tile(
 template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
 __global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-            int64_t tile_base, int64_t tile_end, int32_t tile_points,
+            int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
             const double *__restrict__ poses, double *__restrict__ partials,
             int32_t *__restrict__ corr, float kappa) {
   __shared__ LinearizeLds<ACC, LIN ? kNumSums : 1> L;
@@ -1300,8 +1300,9 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const uint32_t *staged = nullptr;
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
-    linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base + t), factors, tiles,
-                                              tile_points, poses, partials, corr, kappa);
+    linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base) + int64_t(t) * tile_stride,
+                                              factors, tiles, tile_points, poses, partials, corr,
+                                              kappa);
 }
 
 // The pair form (Eqs. (5)-(6) term by term) over the tiles [tile_base,
@@ -1310,7 +1311,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
 template <int ACC, bool R64, int FUSE>
 __global__ void __launch_bounds__(kBlock, 2)
 k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-                 int64_t tile_base, int64_t tile_end, int32_t tile_points,
+                 int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
                  const double *__restrict__ poses, double *__restrict__ partials,
                  double *__restrict__ partials_pair, float kappa) {
   __shared__ LinearizeLds<ACC, kNumPairSums> L;
@@ -1322,9 +1323,9 @@ k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict_
   const uint32_t *staged = nullptr;
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
-    linearize_tile<ACC, true, R64, false, FUSE, true>(L, staged, int64_t(base + t), factors,
-                                                      tiles, tile_points, poses, partials,
-                                                      nullptr, kappa, partials_pair);
+    linearize_tile<ACC, true, R64, false, FUSE, true>(
+        L, staged, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, tile_points, poses,
+        partials, nullptr, kappa, partials_pair);
 }
 
 // Overlap hit count of one tile (Eq. (7)): brick records only.
@@ -1403,20 +1404,21 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
 // blocks as in k_linearize.
 __global__ void __launch_bounds__(kBlock)
 k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-          int64_t tile_base, int64_t tile_end, int32_t tile_points,
+          int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
           const double *__restrict__ poses, double *__restrict__ partials) {
   __shared__ int lds_cnt[kWaves];
   __shared__ uint32_t occ_lds[kOccMaxBits / 32];
   __shared__ uint8_t up_lds[kUpTable];
-  const int64_t per = (tile_end - tile_base + 7) >> 3;
-  const int64_t lo = tile_base + int64_t(blockIdx.x & 7u) * per;
-  const int64_t hi = min(lo + per, tile_end);
+  const uint32_t base = uint32_t(tile_base), count = uint32_t(tile_end - tile_base);
+  const uint32_t per = (count + 7u) >> 3;
+  const uint32_t lo = (blockIdx.x & 7u) * per;
+  const uint32_t hi = min(lo + per, count);
   const uint32_t P = gridDim.x >> 3;
   const uint32_t *staged = nullptr;
   up_table_fill(up_lds);  // read after the first tile's barrier
-  for (int64_t tile = lo + (blockIdx.x >> 3); tile < hi; tile += P)
-    overlap_tile(lds_cnt, occ_lds, up_lds, staged, tile, factors, tiles, tile_points, poses,
-                 partials);
+  for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
+    overlap_tile(lds_cnt, occ_lds, up_lds, staged, int64_t(base) + int64_t(t) * tile_stride,
+                 factors, tiles, tile_points, poses, partials);
 }
 
 // ---------------------------------------------------------------- target order
@@ -1489,7 +1491,7 @@ k_reduce(const FactorDesc *__restrict__ factors, int64_t factor_base,
     const bool used = (mode == 0) || lane >= 27;
     if (used)
       for (int32_t tt = 0; tt < fd.n_tiles; ++tt)
-        acc += partials[int64_t(fd.tile_begin + tt) * kPartialStride + lane];
+        acc += partials[(fd.tile_begin + int64_t(tt) * fd.tile_stride) * kPartialStride + lane];
     s[lane] = acc;
   }
   __syncthreads();
@@ -1582,13 +1584,13 @@ k_reduce_pair(const FactorDesc *__restrict__ factors, int64_t factor_base,
   for (int i = lane; i < kNumPairSums; i += 64) {
     double acc = 0.0;
     for (int32_t tt = 0; tt < fd.n_tiles; ++tt)
-      acc += partials_pair[int64_t(fd.tile_begin + tt) * kPairStride + i];
+      acc += partials_pair[(fd.tile_begin + int64_t(tt) * fd.tile_stride) * kPairStride + i];
     s[i] = acc;
   }
   if (lane == 0) {
     double hits = 0.0;
     for (int32_t tt = 0; tt < fd.n_tiles; ++tt)
-      hits += partials[int64_t(fd.tile_begin + tt) * kPartialStride + kNumSums];
+      hits += partials[(fd.tile_begin + int64_t(tt) * fd.tile_stride) * kPartialStride + kNumSums];
     inl[f] = int64_t(hits);
   }
   __syncthreads();
@@ -1661,49 +1663,55 @@ static inline unsigned tile_grid(int64_t tiles, int32_t persist_blocks) {
 }
 
 template <int ACC, bool LIN, bool R64, int FUSE>
-static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
+static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te, int32_t stride,
                              const double *poses, double *partials, int32_t *corr, float kappa,
                              hipStream_t st) {
   if (te <= tb) return hipSuccess;
+  const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (corr) {
-    k_linearize<ACC, LIN, R64, true, FUSE><<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, corr, kappa);
+    k_linearize<ACC, LIN, R64, true, FUSE><<<grid, kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials, corr, kappa);
   } else {
-    k_linearize<ACC, LIN, R64, false, FUSE><<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, nullptr, kappa);
+    k_linearize<ACC, LIN, R64, false, FUSE><<<grid, kBlock, 0, st>>>(
+        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials, nullptr,
+        kappa);
   }
   return hipGetLastError();
 }
 
 template <int ACC, int FUSE>
 static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool r64, int64_t tb,
-                             int64_t te, const double *poses, double *partials, int32_t *corr,
-                             float kappa, hipStream_t st) {
+                             int64_t te, int32_t stride, const double *poses, double *partials,
+                             int32_t *corr, float kappa, hipStream_t st) {
   if (lin) {
-    return r64 ? launch_lin<ACC, true, true, FUSE>(fs, tb, te, poses, partials, corr, kappa, st)
-               : launch_lin<ACC, true, false, FUSE>(fs, tb, te, poses, partials, corr, kappa, st);
+    return r64 ? launch_lin<ACC, true, true, FUSE>(fs, tb, te, stride, poses, partials, corr,
+                                                   kappa, st)
+               : launch_lin<ACC, true, false, FUSE>(fs, tb, te, stride, poses, partials, corr,
+                                                    kappa, st);
   }
-  return r64 ? launch_lin<ACC, false, true, FUSE>(fs, tb, te, poses, partials, corr, kappa, st)
-             : launch_lin<ACC, false, false, FUSE>(fs, tb, te, poses, partials, corr, kappa, st);
+  return r64 ? launch_lin<ACC, false, true, FUSE>(fs, tb, te, stride, poses, partials, corr,
+                                                  kappa, st)
+             : launch_lin<ACC, false, false, FUSE>(fs, tb, te, stride, poses, partials, corr,
+                                                   kappa, st);
 }
 
 template <int FUSE>
 static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool r64, int64_t tb,
-                           int64_t te, const double *poses, double *partials, int32_t *corr,
-                           float kappa, hipStream_t st) {
+                           int64_t te, int32_t stride, const double *poses, double *partials,
+                           int32_t *corr, float kappa, hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F64:
-      return launch_acc<VGICP_ACC_F64, FUSE>(fs, lin, r64, tb, te, poses, partials, corr, kappa,
-                                              st);
+      return launch_acc<VGICP_ACC_F64, FUSE>(fs, lin, r64, tb, te, stride, poses, partials, corr,
+                                              kappa, st);
     case VGICP_ACC_F32_COMP:
-      return launch_acc<VGICP_ACC_F32_COMP, FUSE>(fs, lin, r64, tb, te, poses, partials, corr,
-                                                   kappa, st);
+      return launch_acc<VGICP_ACC_F32_COMP, FUSE>(fs, lin, r64, tb, te, stride, poses, partials,
+                                                   corr, kappa, st);
     case VGICP_ACC_F32:
-      return launch_acc<VGICP_ACC_F32, FUSE>(fs, lin, r64, tb, te, poses, partials, corr, kappa,
-                                              st);
+      return launch_acc<VGICP_ACC_F32, FUSE>(fs, lin, r64, tb, te, stride, poses, partials, corr,
+                                              kappa, st);
     default:
-      return launch_acc<VGICP_ACC_MIXED, FUSE>(fs, lin, r64, tb, te, poses, partials, corr,
-                                                kappa, st);
+      return launch_acc<VGICP_ACC_MIXED, FUSE>(fs, lin, r64, tb, te, stride, poses, partials,
+                                                corr, kappa, st);
   }
 }
 
@@ -1747,71 +1755,75 @@ hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks) 
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
 
+// Launches over the tiles tb + k * stride, k < te - tb (stride 1: the range
+// [tb, te) of the tile table; a factor's own tiles: its tile_begin, n_tiles
+// and tile_stride).
 hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, bool lin, int64_t tb, int64_t te,
                                  const double *poses, double *partials, int32_t *corr,
-                                 hipStream_t st) {
+                                 hipStream_t st, int32_t stride) {
   const bool r64 = resid == VGICP_RESID_F64;
   if (fused == VGICP_FUSED_F64)
-    return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, poses, partials, corr, 0.f, st);
+    return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, 0.f, st);
   if (kappa > 0.f)
-    return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, poses, partials, corr, kappa, st);
-  return launch_k<kFuse32>(fs, accum, lin, r64, tb, te, poses, partials, corr, 0.f, st);
+    return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, kappa,
+                               st);
+  return launch_k<kFuse32>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, 0.f, st);
 }
 
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa, bool lin, int64_t tb, int64_t te, const double *poses,
-                            int32_t *corr, hipStream_t st) {
+                            int32_t *corr, hipStream_t st, int32_t stride) {
   return launch_linearize_into(fs, accum, resid, fused, kappa, lin, tb, te, poses,
-                               fs->d_partials, corr, st);
+                               fs->d_partials, corr, st, stride);
 }
 
 template <int ACC, int FUSE>
 static hipError_t launch_pair_acc(const vgicp_factorset_s *fs, bool r64, int64_t tb, int64_t te,
-                                  const double *poses, double *partials, double *partials_pair,
-                                  float kappa, hipStream_t st) {
+                                  int32_t stride, const double *poses, double *partials,
+                                  double *partials_pair, float kappa, hipStream_t st) {
   const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (r64)
     k_linearize_pair<ACC, true, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, partials_pair,
-        kappa);
+        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials,
+        partials_pair, kappa);
   else
     k_linearize_pair<ACC, false, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, fs->tile_points, poses, partials, partials_pair,
-        kappa);
+        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials,
+        partials_pair, kappa);
   return hipGetLastError();
 }
 
 template <int FUSE>
 static hipError_t launch_pair_k(const vgicp_factorset_s *fs, int accum, bool r64, int64_t tb,
-                                int64_t te, const double *poses, double *partials,
+                                int64_t te, int32_t stride, const double *poses, double *partials,
                                 double *partials_pair, float kappa, hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F32_COMP:
-      return launch_pair_acc<VGICP_ACC_F32_COMP, FUSE>(fs, r64, tb, te, poses, partials,
+      return launch_pair_acc<VGICP_ACC_F32_COMP, FUSE>(fs, r64, tb, te, stride, poses, partials,
                                                         partials_pair, kappa, st);
     case VGICP_ACC_F32:
-      return launch_pair_acc<VGICP_ACC_F32, FUSE>(fs, r64, tb, te, poses, partials,
+      return launch_pair_acc<VGICP_ACC_F32, FUSE>(fs, r64, tb, te, stride, poses, partials,
                                                    partials_pair, kappa, st);
     default:
-      return launch_pair_acc<VGICP_ACC_MIXED, FUSE>(fs, r64, tb, te, poses, partials,
+      return launch_pair_acc<VGICP_ACC_MIXED, FUSE>(fs, r64, tb, te, stride, poses, partials,
                                                      partials_pair, kappa, st);
   }
 }
 
 hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, int64_t tb, int64_t te, const double *poses,
-                                 hipStream_t st) {
+                                 hipStream_t st, int32_t stride) {
   if (te <= tb) return hipSuccess;
   if (accum == VGICP_ACC_F64) return hipErrorInvalidValue;  // rejected by the callers
   const bool r64 = resid == VGICP_RESID_F64;
   double *pp = fs->d_partials_pair;
+  double *part = fs->d_partials;
   if (fused == VGICP_FUSED_F64)
-    return launch_pair_k<kFuse64>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, 0.f, st);
+    return launch_pair_k<kFuse64>(fs, accum, r64, tb, te, stride, poses, part, pp, 0.f, st);
   if (kappa > 0.f)
-    return launch_pair_k<kFuseGate>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, kappa,
-                                    st);
-  return launch_pair_k<kFuse32>(fs, accum, r64, tb, te, poses, fs->d_partials, pp, 0.f, st);
+    return launch_pair_k<kFuseGate>(fs, accum, r64, tb, te, stride, poses, part, pp, kappa, st);
+  return launch_pair_k<kFuse32>(fs, accum, r64, tb, te, stride, poses, part, pp, 0.f, st);
 }
 
 hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,
@@ -1823,10 +1835,10 @@ hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t n
 }
 
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                          const double *poses, hipStream_t st) {
+                          const double *poses, hipStream_t st, int32_t stride) {
   if (te <= tb) return hipSuccess;
-  k_overlap<<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(fs->d_factors, fs->d_tiles, tb, te,
-                                                   fs->tile_points, poses, fs->d_partials);
+  k_overlap<<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
+      fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, fs->d_partials);
   return hipGetLastError();
 }
 

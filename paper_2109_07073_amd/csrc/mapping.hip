@@ -19,7 +19,7 @@
 
 namespace vgicp {
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                          const double *poses, hipStream_t st);
+                          const double *poses, hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
                          int mode, double *H, double *b, double *e, int64_t *inl,
                          double *overlap, hipStream_t st);
@@ -127,6 +127,7 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
     fd.tile_begin = int32_t(t);
     for (int64_t s = 0; s < c.n; s += kOverlapTile) h_tile[t++] = Tile{k, int32_t(s)};
     fd.n_tiles = int32_t(t - fd.tile_begin);
+    fd.tile_stride = 1;
   }
   vgicp_factorset_s view;
   view.device = ctx->device;

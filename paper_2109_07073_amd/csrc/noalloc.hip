@@ -17,7 +17,7 @@ namespace vgicp {
 hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, bool lin, int64_t tb, int64_t te,
                                  const double *poses, double *partials, int32_t *corr,
-                                 hipStream_t st);
+                                 hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce_from(const vgicp_factorset_s *fs, int64_t f0, int64_t nf,
                               const double *poses, const double *partials, int mode, double *H,
                               double *b, double *e, int64_t *inl, double *overlap,
@@ -101,7 +101,7 @@ int vgicp_linearize_factors_noalloc(vgicp_ctx ctx, vgicp_factorset fs, const dou
       const FactorDesc &d = fs->h_factors[size_t(f)];
       const int64_t tb = d.tile_begin, te = int64_t(d.tile_begin) + d.n_tiles;
       err = launch_linearize_into(fs, o.accum, o.resid, o.fused, o.fp64_kappa, true, tb, te, poses,
-                                  partials, corr, st);
+                                  partials, corr, st, d.tile_stride);
       if (err == hipSuccess)
         err = launch_reduce_from(fs, f, 1, poses, partials, 0, H, b, e, inliers, nullptr, st);
     }

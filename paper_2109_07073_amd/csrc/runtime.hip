@@ -16,9 +16,9 @@ int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, floa
                     int32_t *count, std::string &msg);
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa, bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st);
+                            hipStream_t st, int32_t stride = 1);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                          const double *poses, hipStream_t st);
+                          const double *poses, hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
                          int mode, double *H, double *b, double *e, int64_t *inl,
                          double *overlap, hipStream_t st);
@@ -27,7 +27,7 @@ hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const d
 hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks);
 hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, int64_t tb, int64_t te, const double *poses,
-                                 hipStream_t st);
+                                 hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,
                               double *b, double *e, int64_t *inl, hipStream_t st);
 }  // namespace vgicp
@@ -59,6 +59,54 @@ int use_device(vgicp_ctx ctx) {
 }
 
 constexpr int64_t kMinAutoTiles = 3072;  // several tiles per resident block slot
+
+// The tile table at `tp` points per tile in the factor set's layout, setting
+// every factor's tile_begin, n_tiles and tile_stride:
+//   VGICP_LAYOUT_GROUPED: factors in tile order (grouped by target map), each
+//     factor's tiles consecutive;
+//   VGICP_LAYOUT_INTERLEAVED: the factors that read one source copy (the same
+//     cloud, unless vgicp_factorset_reorder gave each factor its own copy) side
+//     by side, tile by tile (tile p of each such factor, then p + 1, ...), so
+//     that tiles streaming the same source points run at the same time on one
+//     XCD and share its L2; copies in order of their source cloud.
+void build_tiles(vgicp_factorset fs, int32_t tp, std::vector<Tile> &tiles) {
+  tiles.clear();
+  if (fs->layout != VGICP_LAYOUT_INTERLEAVED) {
+    for (int64_t f : fs->tile_order) {
+      FactorDesc &d = fs->h_factors[size_t(f)];
+      d.tile_begin = int32_t(tiles.size());
+      d.tile_stride = 1;
+      for (int64_t s = 0; s < d.n; s += tp) tiles.push_back(Tile{int32_t(f), int32_t(s)});
+      d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
+    }
+    return;
+  }
+  std::vector<int64_t> order = fs->tile_order;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return fs->h_src[size_t(a)] < fs->h_src[size_t(b)]; });
+  // group: consecutive factors of one source reading the same copy
+  size_t g0 = 0;
+  while (g0 < order.size()) {
+    const FactorDesc &first = fs->h_factors[size_t(order[g0])];
+    size_t g1 = g0 + 1;
+    while (g1 < order.size() && fs->h_src[size_t(order[g1])] == fs->h_src[size_t(order[g0])] &&
+           fs->h_factors[size_t(order[g1])].xyz == first.xyz)
+      ++g1;
+    const int32_t K = int32_t(g1 - g0);
+    const int64_t T = (first.n + tp - 1) / tp;
+    const int32_t base = int32_t(tiles.size());
+    for (size_t k = g0; k < g1; ++k) {
+      FactorDesc &d = fs->h_factors[size_t(order[k])];
+      d.tile_begin = base + int32_t(k - g0);
+      d.tile_stride = K;
+      d.n_tiles = int32_t(T);
+    }
+    for (int64_t p = 0; p < T; ++p)
+      for (size_t k = g0; k < g1; ++k)
+        tiles.push_back(Tile{int32_t(order[k]), int32_t(p * tp)});
+    g0 = g1;
+  }
+}
 
 // Brackets one kernel launch with events when timing is on.
 struct TimedLaunch {
@@ -400,16 +448,13 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
     corr_off += c.n;
   }
   fs->total_points = corr_off;
+  fs->tile_order = order;
+  fs->h_src.resize(size_t(n_factors));
+  for (int64_t f = 0; f < n_factors; ++f) fs->h_src[size_t(f)] = factors[f].src;
   std::vector<Tile> tiles;
-  for (int64_t f : order) {
-    FactorDesc &d = fs->h_factors[size_t(f)];
-    d.tile_begin = int32_t(tiles.size());
-    for (int64_t s = 0; s < d.n; s += tile_points) tiles.push_back(Tile{int32_t(f), int32_t(s)});
-    d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
-  }
+  build_tiles(fs, tile_points, tiles);
   fs->n_tiles = int64_t(tiles.size());
   fs->tiles_capacity = std::max<int64_t>(1, fs->n_tiles);
-  fs->tile_order = order;
 
   // CSR of system-assembly contributions (factor order within each pose/pair)
   std::vector<int64_t> pose_off(size_t(n_poses) + 1, 0), pose_ent;
@@ -486,17 +531,12 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
 
 namespace {
 
-// Rebuild the tile table for `tp` points per tile (factors keep their tile
-// order), growing the device tables when needed.  Captured graphs refer to the
+// Rebuild the tile table for `tp` points per tile in the factor set's layout
+// (build_tiles), growing the device tables when needed.  Captured graphs refer to the
 // old table and grid, so they are dropped.  Synchronizes ctx's stream.
 int set_tiles(vgicp_ctx ctx, vgicp_factorset fs, int32_t tp, const char *who) {
   std::vector<Tile> tiles;
-  for (int64_t f : fs->tile_order) {
-    FactorDesc &d = fs->h_factors[size_t(f)];
-    d.tile_begin = int32_t(tiles.size());
-    for (int64_t s = 0; s < d.n; s += tp) tiles.push_back(Tile{int32_t(f), int32_t(s)});
-    d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
-  }
+  build_tiles(fs, tp, tiles);
   hipError_t e = hipStreamSynchronize(ctx->stream);
   for (auto &g : fs->graphs) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -657,16 +697,16 @@ int ensure_pair_partials(vgicp_ctx ctx, vgicp_factorset fs, const char *who) {
 hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum, int resid,
                          int fused, float kappa, const double *poses, int64_t tb, int64_t te, int64_t f0, int64_t nf,
                          double *H, double *b, double *e, int64_t *inl, int32_t *corr,
-                         hipStream_t st, int form = VGICP_FORM_SOURCE) {
+                         hipStream_t st, int form = VGICP_FORM_SOURCE, int32_t stride = 1) {
   const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
   hipError_t err = hipSuccess;
   if (form == VGICP_FORM_PAIR && kind == kKindLinearize) {
     if (ctx) {
       TimedLaunch t(ctx, tk);
-      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st);
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride);
       t.done();
     } else {
-      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st);
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride);
     }
     if (err != hipSuccess) return err;
     if (ctx) {
@@ -681,11 +721,11 @@ hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum,
   if (ctx) {
     TimedLaunch t(ctx, tk);
     err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
-                           st);
+                           st, stride);
     t.done();
   } else {
     err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
-                           st);
+                           st, stride);
   }
   if (err != hipSuccess) return err;
   if (ctx) {
@@ -715,7 +755,8 @@ int run_factors(vgicp_ctx ctx, vgicp_factorset fs, int kind, const double *poses
     for (int64_t f = 0; f < fs->n_factors && err == hipSuccess; ++f) {
       const FactorDesc &d = fs->h_factors[size_t(f)];
       err = enqueue_range(ctx, fs, kind, o.accum, o.resid, o.fused, o.fp64_kappa, poses, d.tile_begin,
-                          int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st, form);
+                          int64_t(d.tile_begin) + d.n_tiles, f, 1, H, b, e, inl, corr, st, form,
+                          d.tile_stride);
     }
     if (err != hipSuccess) return hip_fail(ctx, who, err);
     return VGICP_OK;
@@ -916,12 +957,30 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
     }
     persist[fi] = std::max(8, (ctx->cu_count * std::max(per_cu, 1)) / 8 * 8);
   }
-  // slot (form, candidate, grid) -> best mean round time
-  std::vector<double> grid_ms(size_t(2 * n_forms * n_candidates), 1e300);
-  auto slot_of = [&](int fi, int32_t k, int g) { return size_t((fi * n_candidates + k) * 2 + g); };
-  for (int32_t step = 0; step < 2 * n_candidates && rc == VGICP_OK; ++step) {
-    const bool fwd = step < n_candidates;
-    const int32_t k = fwd ? step : 2 * n_candidates - 1 - step;
+  // layouts to time: both when some source copy is read by several factors
+  const int32_t layout0 = fs->layout;
+  int32_t layouts[2] = {VGICP_LAYOUT_GROUPED, VGICP_LAYOUT_INTERLEAVED};
+  int n_layouts = 1;
+  {
+    std::vector<const float *> copies;
+    copies.reserve(fs->h_factors.size());
+    for (const FactorDesc &d : fs->h_factors) copies.push_back(d.xyz);
+    std::sort(copies.begin(), copies.end());
+    if (std::adjacent_find(copies.begin(), copies.end()) != copies.end()) n_layouts = 2;
+    else layouts[0] = layout0;
+  }
+  // slot (layout, form, candidate, grid) -> best mean round time
+  const int32_t n_cfg = n_layouts * n_candidates;
+  std::vector<double> grid_ms(size_t(2 * n_forms * n_cfg), 1e300);
+  auto slot_of = [&](int li, int fi, int32_t k, int g) {
+    return size_t(((li * n_forms + fi) * n_candidates + k) * 2 + g);
+  };
+  for (int32_t step = 0; step < 2 * n_cfg && rc == VGICP_OK; ++step) {
+    const bool fwd = step < n_cfg;
+    const int32_t c = fwd ? step : 2 * n_cfg - 1 - step;
+    const int li = c / n_candidates;
+    const int32_t k = c % n_candidates;
+    fs->layout = layouts[li];
     rc = set_tiles(ctx, fs, candidates[k], who);
     for (int q = 0; q < 2 * n_forms && rc == VGICP_OK; ++q) {
       const int qq = fwd ? q : 2 * n_forms - 1 - q;
@@ -942,21 +1001,27 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
         rc = hip_fail(ctx, who, he);
       if (rc == VGICP_OK && (he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
         rc = hip_fail(ctx, who, he);
-      const size_t slot = slot_of(fi, k, g);
+      const size_t slot = slot_of(li, fi, k, g);
       if (rc == VGICP_OK) grid_ms[slot] = std::min(grid_ms[slot], double(ms) / kTimed);
     }
   }
   size_t best_slot = 0;
   for (size_t q = 1; q < grid_ms.size(); ++q)
     if (grid_ms[q] < grid_ms[best_slot]) best_slot = q;
-  const int best_fi = int(best_slot / size_t(2 * n_candidates));
-  const int32_t best = candidates[(best_slot / 2) % size_t(n_candidates)];
   const int best_g = int(best_slot % 2);
+  const int32_t best = candidates[(best_slot / 2) % size_t(n_candidates)];
+  const int best_fi = int((best_slot / size_t(2 * n_candidates)) % size_t(n_forms));
+  const int best_li = int(best_slot / size_t(2 * n_candidates * n_forms));
   const double best_t = grid_ms[best_slot];
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   fs->persist_blocks = 0;
-  if (rc != VGICP_OK) return rc;
+  if (rc != VGICP_OK) {
+    fs->layout = layout0;
+    (void)set_tiles(ctx, fs, fs->tile_points, who);
+    return rc;
+  }
+  fs->layout = layouts[best_li];
   rc = set_tiles(ctx, fs, best, who);
   if (rc != VGICP_OK) return rc;
   fs->persist_blocks = best_g ? persist[best_fi] : 0;
@@ -1048,6 +1113,30 @@ int vgicp_factorset_grid(vgicp_factorset fs, int32_t *persist_blocks) {
 int vgicp_factorset_form(vgicp_factorset fs, int32_t *form) {
   if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_form: factor set is NULL");
   if (form) *form = fs->form;
+  return VGICP_OK;
+}
+
+int vgicp_factorset_set_layout(vgicp_ctx ctx, vgicp_factorset fs, int32_t layout) {
+  const char *who = "vgicp_factorset_set_layout";
+  if (!ctx) return fail(nullptr, VGICP_EINVAL, std::string(who) + ": ctx is NULL");
+  if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
+  if (fs->device != ctx->device)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
+  if (layout != VGICP_LAYOUT_GROUPED && layout != VGICP_LAYOUT_INTERLEAVED)
+    return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown layout");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  if (layout == fs->layout) return VGICP_OK;
+  const int32_t old = fs->layout;
+  fs->layout = layout;
+  rc = set_tiles(ctx, fs, fs->tile_points, who);
+  if (rc != VGICP_OK) fs->layout = old;
+  return rc;
+}
+
+int vgicp_factorset_layout(vgicp_factorset fs, int32_t *layout) {
+  if (!fs) return fail(nullptr, VGICP_EINVAL, "vgicp_factorset_layout: factor set is NULL");
+  if (layout) *layout = fs->layout;
   return VGICP_OK;
 }
 

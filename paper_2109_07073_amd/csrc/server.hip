@@ -30,9 +30,9 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa,
                             bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st);
+                            hipStream_t st, int32_t stride = 1);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
-                          const double *poses, hipStream_t st);
+                          const double *poses, hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
                          int mode, double *H, double *b, double *e, int64_t *inl,
                          double *overlap, hipStream_t st);
@@ -258,6 +258,7 @@ void launch_batch(vgicp_server srv, size_t si) {
       d.tile_begin = int32_t(nt);
       for (int64_t st = 0; st < n; st += tp) s.h_tiles[nt++] = Tile{int32_t(nf), int32_t(st)};
       d.n_tiles = int32_t(nt - d.tile_begin);
+      d.tile_stride = 1;
       s.frames_used.push_back(x.src);
       s.frames_used.push_back(x.tgt);
       npts += n;

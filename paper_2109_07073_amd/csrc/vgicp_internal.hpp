@@ -183,11 +183,14 @@ struct FactorDesc {
   uint32_t log2cap;
   float scale;        // fl32(1/r) of the target map
   int32_t tile_begin; // first tile of this factor in the tile table
-  int32_t n_tiles;
+  int32_t n_tiles;    // its tiles: tile_begin + k * tile_stride, k < n_tiles
   uint32_t n_voxels;  // target map: voxels
   const uint32_t *occ;  // target map: occupancy bitset of the brick table
   uint32_t occ_mask;    // occ_bits(cap) - 1
-  uint32_t pad;
+  // Distance between consecutive tiles of this factor in the tile table: 1,
+  // or in the interleaved layout the number of factors reading the same
+  // source copy.
+  int32_t tile_stride;
   // Caller's index of each source point when xyz/cov are a reordered copy of
   // the caller's cloud (per-point outputs are written at it); NULL when the
   // points are in the caller's order.
@@ -349,6 +352,8 @@ struct vgicp_factorset_s {
   int32_t form = VGICP_FORM_SOURCE;  // the form of VGICP_FORM_AUTO calls
   std::vector<vgicp::FactorDesc> h_factors;
   std::vector<int64_t> tile_order;  // factors in tile order (grouped by target map)
+  std::vector<int32_t> h_src;       // source cloud of each factor
+  int32_t layout = VGICP_LAYOUT_GROUPED;  // tile table layout (VGICP_LAYOUT_*)
   void *d_sorted = nullptr;  // device: ordered copies of the source clouds
   // Source points with a non-finite coordinate / covariance entry, counted
   // when the ordered copies were made.

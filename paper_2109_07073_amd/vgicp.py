@@ -32,6 +32,7 @@ SCHED = {"batched": 0, "per_factor": 1}
 RESID = {"f64": 0, "f32": 1}
 FUSED = {"f64": 0, "f32": 1}
 FORM = {"auto": 0, "source": 1, "pair": 2}
+LAYOUT = {"grouped": 0, "interleaved": 1}
 NOALLOC_MAX_TILES = 32768      # VGICP_NOALLOC_MAX_TILES
 
 
@@ -113,6 +114,8 @@ _PROTOS = {
     "vgicp_factorset_time_kernel": (ctypes.c_int, [_vp, _vp, _vp, _P(COpts), _i32, _i32, _P(_dbl)]),
     "vgicp_factorset_grid": (ctypes.c_int, [_vp, _P(_i32)]),
     "vgicp_factorset_form": (ctypes.c_int, [_vp, _P(_i32)]),
+    "vgicp_factorset_set_layout": (ctypes.c_int, [_vp, _vp, _i32]),
+    "vgicp_factorset_layout": (ctypes.c_int, [_vp, _P(_i32)]),
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
@@ -571,9 +574,10 @@ def overlap(ctx: Context, fs: FactorSet, poses, out=None):
 def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str = "mixed",
                resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64",
                form: str = "auto"):
-    """Time a linearization round per candidate tile size, grid and (with
-    form "auto") form, and keep the fastest (vgicp_factorset_tune).  Returns
-    (tile_points, ms per round); grid(fs) and form_of(fs) give the rest."""
+    """Time a linearization round per candidate tile size, grid, tile-table
+    layout (when factors share source copies) and (with form "auto") form,
+    and keep the fastest (vgicp_factorset_tune).  Returns (tile_points, ms per
+    round); grid(fs), layout_of(fs) and form_of(fs) give the rest."""
     torch = _torch()
     _check_poses(fs, poses)
     dev = f"cuda:{ctx.device}"
@@ -592,10 +596,7 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
     _check(_lib.vgicp_factorset_tune(ctx.handle, fs.handle, poses.data_ptr(), ctypes.byref(o),
                                      H.data_ptr(), b.data_ptr(), e.data_ptr(), inl.data_ptr(),
                                      cand, n, ctypes.byref(best), ctypes.byref(ms)), ctx.handle)
-    a, nt, c3, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
-    _check(_lib.vgicp_factorset_info(fs.handle, ctypes.byref(a), ctypes.byref(nt),
-                                     ctypes.byref(c3), ctypes.byref(d)))
-    fs.n_tiles, fs.tile_points = nt.value, d.value
+    _refresh_tiles(fs)
     return best.value, ms.value
 
 
@@ -629,6 +630,31 @@ def grid(fs: FactorSet) -> int:
     g = ctypes.c_int32()
     _check(_lib.vgicp_factorset_grid(fs.handle, ctypes.byref(g)))
     return g.value
+
+
+def set_layout(ctx: Context, fs: FactorSet, layout: str):
+    """Tile-table layout: "grouped" (factors by target map, each factor's
+    tiles consecutive) or "interleaved" (the factors reading one source copy
+    side by side, tile by tile) (vgicp_factorset_set_layout).  Results are the
+    same bits in either layout."""
+    if layout not in LAYOUT:
+        raise ValueError(f"layout must be one of {sorted(LAYOUT)}")
+    _check(_lib.vgicp_factorset_set_layout(ctx.handle, fs.handle, LAYOUT[layout]), ctx.handle)
+    _refresh_tiles(fs)
+
+
+def layout_of(fs: FactorSet) -> str:
+    """The factor set's tile-table layout ("grouped" or "interleaved")."""
+    v = ctypes.c_int32()
+    _check(_lib.vgicp_factorset_layout(fs.handle, ctypes.byref(v)))
+    return {v2: k for k, v2 in LAYOUT.items()}[v.value]
+
+
+def _refresh_tiles(fs: FactorSet):
+    a, nt, c3, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.vgicp_factorset_info(fs.handle, ctypes.byref(a), ctypes.byref(nt),
+                                     ctypes.byref(c3), ctypes.byref(d)))
+    fs.n_tiles, fs.tile_points = nt.value, d.value
 
 
 def form_of(fs: FactorSet) -> str:

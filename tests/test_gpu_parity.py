@@ -296,13 +296,52 @@ def test_persistent_grids_give_the_same_bits(vg, ctx, ragged, scans, tile):
             vg.set_grid(ctx, g.fs, 12)
 
 
+@pytest.mark.parametrize("tile", [256, 1024])
+def test_interleaved_layout_gives_the_same_bits(vg, ctx, ragged, scans, tile):
+    """The interleaved tile table (the factors that read one source copy side
+    by side, tile by tile) writes the same bits as the grouped one, in the
+    batched and per-factor schedules, on a persistent grid and in the pair
+    form; the scan factors share source frames, the ragged ones do not."""
+    for w in (ragged, scans):
+        g = GpuWorkload(vg, ctx, w, tile_points=tile)
+        assert vg.layout_of(g.fs) == "grouped"
+        base = g.linearize(with_corr=True)
+        pair = g.linearize(form="pair")
+        ev0, ov0 = g.evaluate(), g.overlap()
+        vg.set_layout(ctx, g.fs, "interleaved")
+        assert vg.layout_of(g.fs) == "interleaved"
+        for kw in ({}, {"schedule": "per_factor"}):
+            got = g.linearize(with_corr=True, **kw)
+            for k in base:
+                assert np.array_equal(got[k], base[k]), (w.name, kw, k)
+        got = g.linearize(form="pair", schedule="per_factor")
+        for k in pair:
+            assert np.array_equal(got[k], pair[k]), (w.name, k)
+        ev, ov = g.evaluate(), g.overlap()
+        for k in ev0:
+            assert np.array_equal(ev[k], ev0[k]), (w.name, k)
+        for k in ov0:
+            assert np.array_equal(ov[k], ov0[k]), (w.name, k)
+        vg.set_grid(ctx, g.fs, 64)
+        got = g.linearize(with_corr=True)
+        for k in base:
+            assert np.array_equal(got[k], base[k]), (w.name, "grid 64", k)
+        vg.set_layout(ctx, g.fs, "grouped")
+        got = g.linearize(with_corr=True)
+        for k in base:
+            assert np.array_equal(got[k], base[k]), (w.name, "back to grouped", k)
+        with pytest.raises(ValueError):
+            vg.set_layout(ctx, g.fs, "diagonal")
+
+
 def test_tuner_picks_a_tile_and_a_grid(vg, ctx, scans):
     g = GpuWorkload(vg, ctx, scans)
     base = g.linearize()
     best, ms = vg.tune_tiles(ctx, g.fs, g.poses, candidates=[768, 2304])
     assert best in (768, 2304) and ms > 0
     assert vg.grid(g.fs) % 8 == 0
-    print(f"tuned: tile {best}, grid {vg.grid(g.fs)}, {ms:.4f} ms")
+    assert vg.layout_of(g.fs) in ("grouped", "interleaved")
+    print(f"tuned: tile {best}, grid {vg.grid(g.fs)}, layout {vg.layout_of(g.fs)}, {ms:.4f} ms")
     got = g.linearize()
     assert np.array_equal(got["inliers"], base["inliers"])
     _, ref = oracle_results(scans)
