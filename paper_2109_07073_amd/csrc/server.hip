@@ -78,21 +78,27 @@ struct Chunk {
   int64_t batch_pos;  // position of the first factor in the batch
 };
 
+// A batch moves its inputs to the device with one copy and its outputs back
+// with one: the inputs packed as [descriptors | tiles | poses] (each part
+// 256-byte aligned), the outputs of nf factors as [inliers | e | overlap | b |
+// H] (nf, nf, nf, 12 nf and 144 nf eight-byte values).
+constexpr size_t kOutPerFactor = 159;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 struct Slot {
   hipStream_t stream = nullptr;
   // device
-  FactorDesc *d_factors = nullptr;
-  Tile *d_tiles = nullptr;
+  unsigned char *d_in = nullptr;
+  double *d_out = nullptr;
   double *d_partials = nullptr;
-  double *d_poses = nullptr;
-  double *d_H = nullptr, *d_b = nullptr, *d_e = nullptr, *d_ov = nullptr;
-  int64_t *d_inl = nullptr;
-  // pinned host staging
-  FactorDesc *h_factors = nullptr;
+  // pinned host staging: the descriptors are written in place in h_in, tiles
+  // and poses gathered there at launch
+  unsigned char *h_in = nullptr;
+  double *h_out = nullptr;
+  FactorDesc *h_factors = nullptr;  // = h_in
   Tile *h_tiles = nullptr;
   double *h_poses = nullptr;
-  double *h_H = nullptr, *h_b = nullptr, *h_e = nullptr, *h_ov = nullptr;
-  int64_t *h_inl = nullptr;
   // batch in flight
   bool busy = false;
   bool finished = false;
@@ -154,33 +160,29 @@ hipError_t host_alloc(T **p, size_t count) {
 
 void free_slot(Slot &s) {
   if (s.stream) (void)hipStreamDestroy(s.stream);
-  for (void *p : {(void *)s.d_factors, (void *)s.d_tiles, (void *)s.d_partials, (void *)s.d_poses,
-                  (void *)s.d_H, (void *)s.d_b, (void *)s.d_e, (void *)s.d_ov, (void *)s.d_inl})
+  for (void *p : {(void *)s.d_in, (void *)s.d_out, (void *)s.d_partials})
     if (p) (void)hipFree(p);
-  for (void *p : {(void *)s.h_factors, (void *)s.h_tiles, (void *)s.h_poses, (void *)s.h_H,
-                  (void *)s.h_b, (void *)s.h_e, (void *)s.h_ov, (void *)s.h_inl})
+  for (void *p : {(void *)s.h_in, (void *)s.h_out, (void *)s.h_tiles, (void *)s.h_poses})
     if (p) (void)hipHostFree(p);
+}
+
+// Bytes of a packed input block for F descriptors, T tiles and P poses.
+size_t in_block_bytes(int64_t F, int64_t T, int64_t P) {
+  return align256(size_t(F) * sizeof(FactorDesc)) + align256(size_t(T) * sizeof(Tile)) +
+         size_t(P) * 12 * sizeof(double);
 }
 
 hipError_t alloc_slot(Slot &s, int64_t F, int64_t T, int64_t P) {
   hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = dev_alloc(&s.d_factors, F);
-  if (e == hipSuccess) e = dev_alloc(&s.d_tiles, T);
+  const size_t in_bytes = in_block_bytes(F, T, P);
+  if (e == hipSuccess) e = dev_alloc(&s.d_in, in_bytes);
+  if (e == hipSuccess) e = dev_alloc(&s.d_out, size_t(F) * kOutPerFactor);
   if (e == hipSuccess) e = dev_alloc(&s.d_partials, T * kPartialStride);
-  if (e == hipSuccess) e = dev_alloc(&s.d_poses, P * 12);
-  if (e == hipSuccess) e = dev_alloc(&s.d_H, F * 144);
-  if (e == hipSuccess) e = dev_alloc(&s.d_b, F * 12);
-  if (e == hipSuccess) e = dev_alloc(&s.d_e, F);
-  if (e == hipSuccess) e = dev_alloc(&s.d_ov, F);
-  if (e == hipSuccess) e = dev_alloc(&s.d_inl, F);
-  if (e == hipSuccess) e = host_alloc(&s.h_factors, F);
+  if (e == hipSuccess) e = host_alloc(&s.h_in, in_bytes);
+  if (e == hipSuccess) e = host_alloc(&s.h_out, size_t(F) * kOutPerFactor);
   if (e == hipSuccess) e = host_alloc(&s.h_tiles, T);
   if (e == hipSuccess) e = host_alloc(&s.h_poses, P * 12);
-  if (e == hipSuccess) e = host_alloc(&s.h_H, F * 144);
-  if (e == hipSuccess) e = host_alloc(&s.h_b, F * 12);
-  if (e == hipSuccess) e = host_alloc(&s.h_e, F);
-  if (e == hipSuccess) e = host_alloc(&s.h_ov, F);
-  if (e == hipSuccess) e = host_alloc(&s.h_inl, F);
+  s.h_factors = reinterpret_cast<FactorDesc *>(s.h_in);
   return e;
 }
 
@@ -298,49 +300,45 @@ void launch_batch(vgicp_server srv, size_t si) {
   for (const Slot &o : srv->slots) inflight += o.busy ? 1 : 0;
   srv->max_inflight = std::max(srv->max_inflight, inflight);
 
+  // one copy in: descriptors (written in place), tiles and poses packed
+  const size_t off_tiles = align256(size_t(nf) * sizeof(FactorDesc));
+  const size_t off_poses = off_tiles + align256(size_t(nt) * sizeof(Tile));
+  const size_t in_bytes = off_poses + size_t(npose) * 12 * sizeof(double);
+  std::memcpy(s.h_in + off_tiles, s.h_tiles, size_t(nt) * sizeof(Tile));
+  std::memcpy(s.h_in + off_poses, s.h_poses, size_t(npose) * 12 * sizeof(double));
+  double *d_poses = reinterpret_cast<double *>(s.d_in + off_poses);
   vgicp_factorset_s view;
   view.device = srv->device;
   view.n_factors = nf;
   view.n_tiles = nt;
   view.tile_points = int32_t(tp);
-  view.d_factors = s.d_factors;
-  view.d_tiles = s.d_tiles;
+  view.d_factors = reinterpret_cast<FactorDesc *>(s.d_in);
+  view.d_tiles = reinterpret_cast<Tile *>(s.d_in + off_tiles);
   view.d_partials = s.d_partials;
+  // outputs [inliers | e | overlap | b | H]
+  int64_t *d_inl = reinterpret_cast<int64_t *>(s.d_out);
+  double *d_e = s.d_out + nf, *d_ov = s.d_out + 2 * nf;
+  double *d_b = s.d_out + 3 * nf, *d_H = s.d_out + 15 * nf;
   const hipStream_t st = s.stream;
   const vgicp_opts &o = srv->cfg.opts;
-  hipError_t e = hipMemcpyAsync(s.d_factors, s.h_factors, size_t(nf) * sizeof(FactorDesc),
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && nt > 0)
-    e = hipMemcpyAsync(s.d_tiles, s.h_tiles, size_t(nt) * sizeof(Tile), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && npose > 0)
-    e = hipMemcpyAsync(s.d_poses, s.h_poses, size_t(npose) * 12 * sizeof(double),
-                       hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(s.d_in, s.h_in, in_bytes, hipMemcpyHostToDevice, st);
+  size_t out_values = 0;
   if (kind == VGICP_REQ_OVERLAP) {
-    if (e == hipSuccess) e = launch_overlap(&view, 0, nt, s.d_poses, st);
+    if (e == hipSuccess) e = launch_overlap(&view, 0, nt, d_poses, st);
     if (e == hipSuccess)
-      e = launch_reduce(&view, 0, nf, s.d_poses, 2, nullptr, nullptr, nullptr, s.d_inl, s.d_ov, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s.h_ov, s.d_ov, size_t(nf) * sizeof(double), hipMemcpyDeviceToHost, st);
+      e = launch_reduce(&view, 0, nf, d_poses, 2, nullptr, nullptr, nullptr, d_inl, d_ov, st);
+    out_values = 3 * size_t(nf);
   } else {
     const bool lin = kind == VGICP_REQ_LINEARIZE;
     if (e == hipSuccess)
-      e = launch_linearize(&view, o.accum, o.resid, o.fused, o.fp64_kappa, lin, 0, nt, s.d_poses, nullptr,
-                           st);
+      e = launch_linearize(&view, o.accum, o.resid, o.fused, o.fp64_kappa, lin, 0, nt, d_poses,
+                           nullptr, st);
     if (e == hipSuccess)
-      e = launch_reduce(&view, 0, nf, s.d_poses, lin ? 0 : 1, s.d_H, s.d_b, s.d_e, s.d_inl,
-                        nullptr, st);
-    if (e == hipSuccess && lin) {
-      e = hipMemcpyAsync(s.h_H, s.d_H, size_t(nf) * 144 * sizeof(double), hipMemcpyDeviceToHost,
-                         st);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(s.h_b, s.d_b, size_t(nf) * 12 * sizeof(double),
-                           hipMemcpyDeviceToHost, st);
-    }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s.h_e, s.d_e, size_t(nf) * sizeof(double), hipMemcpyDeviceToHost, st);
+      e = launch_reduce(&view, 0, nf, d_poses, lin ? 0 : 1, d_H, d_b, d_e, d_inl, nullptr, st);
+    out_values = (lin ? kOutPerFactor : 2) * size_t(nf);
   }
   if (e == hipSuccess)
-    e = hipMemcpyAsync(s.h_inl, s.d_inl, size_t(nf) * sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(s.h_out, s.d_out, out_values * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) {
     srv->callbacks_outstanding += 1;
     e = hipLaunchHostFunc(st, on_batch_done, new DoneArgs{srv, si});
@@ -368,19 +366,23 @@ void free_frame(Frame &fr) {
 // blocking HIP call may run under it).
 void retire(vgicp_server srv, Slot &s, std::vector<Frame> &to_free) {
   const bool ok = s.err == hipSuccess;
+  const int64_t nf = s.n_factors;
+  const int64_t *h_inl = reinterpret_cast<const int64_t *>(s.h_out);
+  const double *h_e = s.h_out + nf, *h_ov = s.h_out + 2 * nf;
+  const double *h_b = s.h_out + 3 * nf, *h_H = s.h_out + 15 * nf;
   for (const Chunk &c : s.chunks) {
     Request &r = *c.req;
     if (ok) {
       for (int64_t k = 0; k < c.count; ++k) {
         const int64_t f = c.first + k, p = c.batch_pos + k;
-        if (r.inliers) r.inliers[f] = s.h_inl[p];
+        if (r.inliers) r.inliers[f] = h_inl[p];
         if (s.kind == VGICP_REQ_OVERLAP) {
-          if (r.overlap) r.overlap[f] = s.h_ov[p];
+          if (r.overlap) r.overlap[f] = h_ov[p];
         } else {
-          if (r.e) r.e[f] = s.h_e[p];
+          if (r.e) r.e[f] = h_e[p];
           if (s.kind == VGICP_REQ_LINEARIZE) {
-            std::memcpy(r.H + f * 144, s.h_H + p * 144, 144 * sizeof(double));
-            std::memcpy(r.b + f * 12, s.h_b + p * 12, 12 * sizeof(double));
+            std::memcpy(r.H + f * 144, h_H + p * 144, 144 * sizeof(double));
+            std::memcpy(r.b + f * 12, h_b + p * 12, 12 * sizeof(double));
           }
         }
       }
