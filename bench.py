@@ -487,16 +487,24 @@ def run_serving(args):
         glob = set()
         for w_id in resident[-args.window:]:
             glob |= adj[w_id]
-        glob = [(a, b, a, b) for a, b in sorted(glob)]
+        glob = sorted(glob)
         loc_ids = resident[-10:]
-        loc = [(a, b, a, b) for ia, a in enumerate(loc_ids) for b in loc_ids[:ia]]
-        used = {a for a, _, _, _ in glob} | {b for _, b, _, _ in glob} | set(loc_ids)
+        loc = [(a, b) for ia, a in enumerate(loc_ids) for b in loc_ids[:ia]]
+        # the optimizer's variables: the poses its factors touch, numbered
+        # 0..U-1 in the requests (each request carries only those poses)
+        used_ids = sorted({a for a, _ in glob} | {b for _, b in glob} | set(loc_ids))
+        var = {k: n for n, k in enumerate(used_ids)}
+        glob = np.asarray([(a, b, var[a], var[b]) for a, b in glob], np.int32).reshape(-1, 4)
+        loc = np.asarray([(a, b, var[a], var[b]) for a, b in loc], np.int32).reshape(-1, 4)
+        prev = {}   # each optimizer reuses its previous round's host buffers
         for _ in range(3):
-            P = perturbed(poses, used)
+            P = perturbed(poses, used_ids)[used_ids]
             t0 = time.perf_counter()
-            reqs = [srv.submit("linearize", g, P) for g in (glob, loc) if g]
+            reqs = {k: srv.submit("linearize", g, P, out=prev.get(k))
+                    for k, g in (("glob", glob), ("loc", loc)) if len(g)}
             t1 = time.perf_counter()
-            done = [r.wait() for r in reqs]
+            done = [r.wait() for r in reqs.values()]
+            prev = reqs
             t2 = time.perf_counter()
             round_time += t2 - t0
             round_ms.append((t2 - t0) * 1e3)

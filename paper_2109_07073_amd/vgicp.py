@@ -800,16 +800,24 @@ def submap_step(ctx: Context, xyz, pose, first=None, first_pose=None, last=None,
 
 
 class ServerRequest:
-    """A submitted request: host output arrays are filled when it completes."""
+    """A submitted request: host output arrays are filled when it completes.
+    `out` (a finished request of the same kind and size) lends its arrays, so
+    that an optimizer's repeated rounds reuse their host buffers."""
 
-    def __init__(self, server, kind, n):
+    def __init__(self, server, kind, n, out=None):
         self.server = server
         self.kind = kind
-        self.inliers = np.zeros(n, dtype=np.int64)
-        self.e = np.zeros(n, dtype=np.float64)
-        self.H = np.zeros((n, 12, 12), dtype=np.float64) if kind == "linearize" else None
-        self.b = np.zeros((n, 12), dtype=np.float64) if kind == "linearize" else None
-        self.overlap = np.zeros(n, dtype=np.float64) if kind == "overlap" else None
+        if out is not None:
+            if out.kind != kind or out.inliers.shape[0] != n or out.ticket in server._inflight:
+                raise ValueError("out must be a finished request of the same kind and size")
+            self.inliers, self.e, self.H, self.b, self.overlap = (out.inliers, out.e, out.H,
+                                                                  out.b, out.overlap)
+        else:
+            self.inliers = np.zeros(n, dtype=np.int64)
+            self.e = np.zeros(n, dtype=np.float64)
+            self.H = np.zeros((n, 12, 12), dtype=np.float64) if kind == "linearize" else None
+            self.b = np.zeros((n, 12), dtype=np.float64) if kind == "linearize" else None
+            self.overlap = np.zeros(n, dtype=np.float64) if kind == "overlap" else None
         self.ticket = None
         self.latency_ms = None
 
@@ -873,10 +881,10 @@ class Server:
         _check_srv(_lib.vgicp_server_memory(self._h, ctypes.byref(used), ctypes.byref(budget)), self)
         return used.value, budget.value
 
-    def submit(self, kind: str, factors, poses) -> ServerRequest:
+    def submit(self, kind: str, factors, poses, out: ServerRequest = None) -> ServerRequest:
         arr, n = _factor_array(factors)
         p = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 12))
-        r = ServerRequest(self, kind, n)
+        r = ServerRequest(self, kind, n, out)
         t = ctypes.c_int64()
         ptr = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
         r._keep = (arr, p)

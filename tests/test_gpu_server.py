@@ -68,6 +68,32 @@ def test_alone_mix_split_and_factorset_agree(vg, scans):
     assert st["max_requests_per_batch"] >= 2 and st["batches"] >= 6
 
 
+def test_requests_reuse_host_buffers(vg, scans):
+    """A request submitted with out= writes into a finished request's arrays
+    (an optimizer's next round) and gives the same bits; an unfinished or
+    mismatched request is refused."""
+    with vg.Server(max_batch_factors=9, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        first = srv.submit("linearize", fac[:20], scans.poses).wait()
+        ref = {k: getattr(first, k).copy() for k in ("H", "b", "e", "inliers")}
+        for k in ("H", "b", "e"):
+            getattr(first, k)[...] = np.nan
+        again = srv.submit("linearize", fac[:20], scans.poses, out=first)
+        with pytest.raises(ValueError):   # still in flight
+            srv.submit("linearize", fac[:20], scans.poses, out=again)
+        again.wait()
+        assert again.H is first.H
+        for k in ref:
+            assert np.array_equal(getattr(again, k), ref[k]), k
+        with pytest.raises(ValueError):   # another size
+            srv.submit("linearize", fac[:19], scans.poses, out=again)
+        with pytest.raises(ValueError):   # another kind
+            srv.submit("evaluate", fac[:20], scans.poses, out=again)
+
+
 def test_evaluate_and_overlap_requests(vg, scans):
     with vg.Server(inflight=3) as srv:
         ids = _frames(srv, scans)
