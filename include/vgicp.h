@@ -411,7 +411,11 @@ int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
 
 /* The cost e (device float64 [n_factors]) and inliers (device int64
  * [n_factors]) alone, without Jacobians; equal to the e and inliers of
- * vgicp_linearize_factors with the same accumulation.  Errors: EINVAL, EHIP. */
+ * vgicp_linearize_factors with the same accumulation in the source-frame form
+ * (the pair form's e, summed in the target frame, agrees to FP32 rounding;
+ * inliers are always equal).  A call uses the factor set's tile partials:
+ * calls on one factor set that overlap in time (on two streams) race.
+ * Errors: EINVAL, EHIP. */
 int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                           const vgicp_opts *opts, double *e, int64_t *inliers);
 
