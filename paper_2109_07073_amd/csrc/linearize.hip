@@ -109,26 +109,22 @@ __device__ __forceinline__ f32x4 ld_f32x4(Rsrc r, uint32_t off) {
   return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, int(off), 0, AUX));
 }
 
-// The three coordinate planes of one tile, points [begin, end) of a source
-// cloud of n points: the prefetch past the tile's end reads zeros without
-// touching memory (it would otherwise fetch the next tile's lines).
+// The coordinates of one tile, points [begin, end) of a source copy stored
+// point by point ([n][3]): one 12-byte load per lane and pass.  The prefetch
+// past the tile's end reads zeros without touching memory (it would otherwise
+// fetch the next tile's lines).
 struct CloudRsrc {
-  Rsrc x, y, z;
+  Rsrc p;
 };
 
-__device__ __forceinline__ CloudRsrc tile_rsrc(const float *xyz, uint32_t n, uint32_t begin,
-                                               uint32_t end) {
-  const uint64_t bytes = 4ull * (end - begin);
-  return {make_rsrc(xyz + begin, bytes), make_rsrc(xyz + n + begin, bytes),
-          make_rsrc(xyz + 2ull * n + begin, bytes)};
+__device__ __forceinline__ CloudRsrc tile_rsrc(const float *xyz, uint32_t begin, uint32_t end) {
+  return {make_rsrc(xyz + 3ull * begin, 12ull * (end - begin))};
 }
 
 // Point `i` of the tile (counted from its first point).
 __device__ __forceinline__ void load_xyz(const CloudRsrc &c, uint32_t i, float p[3]) {
-  const uint32_t off = i * 4u;
-  p[0] = ld_f32<kNT>(c.x, off);
-  p[1] = ld_f32<kNT>(c.y, off);
-  p[2] = ld_f32<kNT>(c.z, off);
+  const f32x3 v = ld_f32x3<kNT>(c.p, i * 12u);
+  p[0] = v.x, p[1] = v.y, p[2] = v.z;
 }
 
 // Brick key halves, home record and bit of the voxel holding the point with
@@ -1125,7 +1121,7 @@ __device__ __forceinline__ void linearize_tile(
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(tile_points), n);
-  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const Rsrc rs = make_rsrc(fd.stats, 36ull * fd.n_voxels);
@@ -1349,7 +1345,7 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(tile_points), n);
-  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   int hits = 0;
   float cur[kOvlChunk][3];
@@ -1442,7 +1438,7 @@ k_voxel_order_keys(const FactorDesc *__restrict__ factors, const Tile *__restric
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(tile_points), n);
-  const CloudRsrc cx = tile_rsrc(fd.xyz, n, begin, end);
+  const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const uint64_t hi = uint64_t(uint32_t(td.factor)) << 32;
   // whole waves run every pass (the ballot in find_voxel); lanes past the

@@ -76,14 +76,16 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
   if (n == 0) return VGICP_OK;
   const int64_t tiles_per = (c.n + kOverlapTile - 1) / kOverlapTile;
   const int64_t nt = tiles_per * n;
-  // device: descriptors, tiles, poses, partials, hits, overlap
+  // device: descriptors, tiles, poses, partials, hits, overlap, then the
+  // cloud's coordinates point by point (the layout k_overlap reads)
   const size_t b_desc = aligned(sizeof(FactorDesc) * size_t(n));
   const size_t b_tile = aligned(sizeof(Tile) * size_t(std::max<int64_t>(nt, 1)));
   const size_t b_pose = aligned(sizeof(double) * 12 * size_t(n + 1));
   const size_t b_part = aligned(sizeof(double) * kPartialStride * size_t(std::max<int64_t>(nt, 1)));
   const size_t b_hits = aligned(sizeof(int64_t) * size_t(n));
   const size_t b_ov = aligned(sizeof(double) * size_t(n));
-  const size_t dev = b_desc + b_tile + b_pose + b_part + b_hits + b_ov;
+  const size_t b_xyz = aligned(sizeof(float) * 3 * size_t(c.n));
+  const size_t dev = b_desc + b_tile + b_pose + b_part + b_hits + b_ov + b_xyz;
   const size_t host = b_desc + b_tile + b_pose + b_hits + b_ov;
   int rc = grow(ctx, dev, host, who);
   if (rc) return rc;
@@ -100,6 +102,7 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
   auto *d_part = reinterpret_cast<double *>(d + b_desc + b_tile + b_pose);
   auto *d_hits = reinterpret_cast<int64_t *>(d + b_desc + b_tile + b_pose + b_part);
   auto *d_ov = reinterpret_cast<double *>(d + b_desc + b_tile + b_pose + b_part + b_hits);
+  auto *d_xyz = reinterpret_cast<float *>(d + b_desc + b_tile + b_pose + b_part + b_hits + b_ov);
 
   // the pinned staging may still be read by an earlier call's copies
   hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -111,7 +114,7 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
     const vgicp_voxelmap_s *m = maps[k];
     FactorDesc &fd = h_desc[k];
     std::memset(&fd, 0, sizeof(fd));
-    fd.xyz = c.xyz;
+    fd.xyz = d_xyz;
     fd.cov = c.cov;
     fd.bricks = m->bricks;
     fd.stats = m->stats;
@@ -139,6 +142,7 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
   view.d_partials = d_part;
   const hipStream_t st = ctx->stream;
   e = hipMemcpyAsync(d, h, b_desc + b_tile + b_pose, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_interleave_xyz(c.xyz, c.n, d_xyz, st);
   if (e == hipSuccess) e = launch_overlap(&view, 0, nt, d_pose, st);
   if (e == hipSuccess)
     e = launch_reduce(&view, 0, n, d_pose, 2, nullptr, nullptr, nullptr, d_hits, d_ov, st);

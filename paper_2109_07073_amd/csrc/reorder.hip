@@ -57,7 +57,7 @@ k_morton_keys(const float *__restrict__ xyz, uint32_t n, float inv_cell,
 }
 
 // Copy point perm[i] of the cloud to position i of the ordered copy
-// (coordinates as three planes, covariances as six floats per point), and
+// (three coordinates and six covariance entries per point), and
 // count the points with a non-finite coordinate (nonfinite[0]) or covariance
 // entry (nonfinite[1]): the only full pass over a factor set's inputs.
 __global__ void __launch_bounds__(kThreads)
@@ -68,9 +68,9 @@ k_gather_points(const float *__restrict__ xyz, const float *__restrict__ cov, ui
   if (i >= n) return;
   const uint64_t j = uint32_t(perm[i]);
   const float x = xyz[j], y = xyz[uint64_t(n) + j], z = xyz[2ull * n + j];
-  xyz_out[i] = x;
-  xyz_out[uint64_t(n) + i] = y;
-  xyz_out[2ull * n + i] = z;
+  xyz_out[3ull * i] = x;
+  xyz_out[3ull * i + 1] = y;
+  xyz_out[3ull * i + 2] = z;
   const float2 *src = reinterpret_cast<const float2 *>(cov + 6 * j);
   float2 *dst = reinterpret_cast<float2 *>(cov_out + 6ull * i);
   const float2 c0 = src[0], c1 = src[1], c2 = src[2];
@@ -100,12 +100,11 @@ k_gather_factor_points(const FactorDesc *__restrict__ old_desc,
   const uint64_t i = vals[q];
   const FactorDesc &o = old_desc[f];
   const FactorDesc &d = new_desc[f];
-  const uint64_t n = uint64_t(o.n);
   const uint64_t local = q - uint64_t(d.corr_offset);
   float *xyz = const_cast<float *>(d.xyz);
-  xyz[local] = o.xyz[i];
-  xyz[n + local] = o.xyz[n + i];
-  xyz[2 * n + local] = o.xyz[2 * n + i];
+  xyz[3 * local] = o.xyz[3 * i];
+  xyz[3 * local + 1] = o.xyz[3 * i + 1];
+  xyz[3 * local + 2] = o.xyz[3 * i + 2];
   const float2 *src = reinterpret_cast<const float2 *>(o.cov + 6 * i);
   float2 *dst = reinterpret_cast<float2 *>(const_cast<float *>(d.cov) + 6 * local);
   dst[0] = src[0];
@@ -114,7 +113,25 @@ k_gather_factor_points(const FactorDesc *__restrict__ old_desc,
   const_cast<int32_t *>(d.perm)[local] = o.perm ? o.perm[i] : int32_t(i);
 }
 
+// Coordinates of a caller's cloud ([3][n], one plane per axis) point by point
+// ([n][3]), the layout the lookup kernels read.
+__global__ void __launch_bounds__(kThreads)
+k_interleave_xyz(const float *__restrict__ planes, uint32_t n, float *__restrict__ out) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  out[3ull * i] = planes[i];
+  out[3ull * i + 1] = planes[uint64_t(n) + i];
+  out[3ull * i + 2] = planes[2ull * n + i];
+}
+
 }  // namespace
+
+hipError_t launch_interleave_xyz(const float *planes, int64_t n, float *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const uint32_t grid = uint32_t((uint64_t(n) + kThreads - 1) / kThreads);
+  k_interleave_xyz<<<grid, kThreads, 0, st>>>(planes, uint32_t(n), out);
+  return hipGetLastError();
+}
 
 hipError_t launch_voxel_order_keys(const vgicp_factorset_s *fs, const double *poses,
                                    uint64_t *keys, uint32_t *vals, hipStream_t st);
@@ -122,7 +139,7 @@ hipError_t launch_voxel_order_keys(const vgicp_factorset_s *fs, const double *po
 hipError_t reorder_by_target(vgicp_factorset_s *fs, const double *poses, hipStream_t st) {
   const int64_t total = fs->total_points;
   if (fs->n_factors == 0 || total == 0) return hipSuccess;
-  // new per-factor copies: covariances [n][6], coordinates [3][n], permutation [n]
+  // new per-factor copies: covariances [n][6], coordinates [n][3], permutation [n]
   std::vector<FactorDesc> nd = fs->h_factors;
   size_t bytes = 0;
   std::vector<size_t> off(nd.size(), 0);
@@ -199,7 +216,7 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
   *buffer = nullptr;
   if (nonfinite) nonfinite[0] = nonfinite[1] = 0;
   out.assign(size_t(n_sources), SortedSource{});
-  // layout: per used cloud, covariances [n][6], coordinates [3][n], permutation [n]
+  // layout: per used cloud, covariances [n][6], coordinates [n][3], permutation [n]
   size_t total = 0;
   uint32_t nmax = 0;
   std::vector<size_t> off(size_t(n_sources), 0);

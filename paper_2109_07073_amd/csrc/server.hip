@@ -46,7 +46,9 @@ namespace {
 
 struct Frame {
   bool live = false;
-  float *cloud = nullptr;  // device: xyz [3][n], then cov [n][6] at cov_offset floats
+  // device: xyz (the caller's [3][n] while the frame is voxelized, then its
+  // ordered copy [n][3]), then cov [n][6] at cov_offset floats
+  float *cloud = nullptr;
   int64_t cov_offset = 0;  // 3n rounded up to a multiple of 4 floats (16 bytes)
   int64_t n = 0;
   vgicp_map map = nullptr;
@@ -576,7 +578,8 @@ int vgicp_server_add_frame(vgicp_server srv, const float *h_xyz, const float *h_
     }
     // Then the frame's points are put in Morton order of cells of its own
     // resolution (the order a factor set gives a cloud matched against maps of
-    // that resolution), so that its rounds read neighbouring voxels together.
+    // that resolution), so that its rounds read neighbouring voxels together,
+    // and its coordinates are kept point by point, as the kernels read them.
     // Requests have no per-point outputs, so the permutation is not kept.
     if (rc == VGICP_OK && n > 0) {
       const std::vector<double> cell{resolution};

@@ -171,7 +171,7 @@ constexpr int kDefaultTile = 6 * kTileQuantum;  // 4608 points
 
 // Per-factor device descriptor (read with uniform loads by every tile).
 struct FactorDesc {
-  const float *xyz;        // [3][n]
+  const float *xyz;        // [n][3]: a library-owned copy, point by point
   const float *cov;        // [n][6]
   const BrickRecord *bricks;  // target map: brick table
   const VoxelStats *stats;    // target map: per-voxel mean and covariance
@@ -200,10 +200,14 @@ struct FactorDesc {
 // A factor set's ordered copy of one source cloud (Morton order of cells),
 // with the caller's index of each point.
 struct SortedSource {
-  const float *xyz = nullptr;   // [3][n]
+  const float *xyz = nullptr;   // [n][3]
   const float *cov = nullptr;   // [n][6]
   const int32_t *perm = nullptr;  // [n]
 };
+
+// Coordinates of a caller's cloud, [3][n], copied point by point to out
+// ([n][3]) on st.
+hipError_t launch_interleave_xyz(const float *planes, int64_t n, float *out, hipStream_t st);
 
 // Ordered copies of the clouds s with cell[s] > 0 and n > 0, in one device
 // allocation returned in *buffer (NULL when there is none); out[s] points into
