@@ -794,7 +794,8 @@ def main():
     ap.add_argument("--fused", default="f64", choices=["f64", "f32"],
                     help="precision of the fused covariance and its inverse")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--layout", default="auto", choices=["auto", "grouped", "interleaved"],
+    ap.add_argument("--layout", default="auto",
+                    choices=["auto", "grouped", "interleaved", "balanced"],
                     help="tile-table layout (auto: the tuner's choice, or grouped with --tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reorder", action="store_true",

@@ -109,13 +109,20 @@ extern "C" {
 #define VGICP_SCHED_BATCHED 0    /* one launch over the tiles of all factors, one reduce   */
 #define VGICP_SCHED_PER_FACTOR 1 /* one linearize launch and one reduce launch per factor */
 
-/* Layout of a factor set's tile table (fixed-size point ranges of one factor;
- * results do not depend on it, bit for bit). */
+/* Layout of a factor set's tile table (point ranges of one factor, of the
+ * factor set's tile size).  The grouped and interleaved layouts give the same
+ * bits; the balanced one cuts some factors into shorter tiles, which changes
+ * only their FP32 summation order (integer outputs are the same). */
 #define VGICP_LAYOUT_GROUPED 0     /* factors grouped by target map, each factor's tiles
                                       consecutive (default)                            */
 #define VGICP_LAYOUT_INTERLEAVED 1 /* the factors that read one source copy side by
                                       side, tile by tile, so that tiles streaming the
                                       same source points run together and share L2   */
+#define VGICP_LAYOUT_BALANCED 2    /* the grouped order in 8 runs of about equal points,
+                                      one per XCD, whose factors ending in the run's
+                                      last tenth of points get quarter-size tiles, so
+                                      that each XCD's last blocks are short; the runs
+                                      are padded to one length with empty tiles      */
 
 typedef struct vgicp_context_s *vgicp_ctx;
 typedef struct vgicp_voxelmap_s *vgicp_map;
@@ -250,33 +257,34 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
                            int64_t n_factors, int32_t n_poses, int32_t tile_points,
                            vgicp_factorset *out);
 
-/* Factor-set facts (tile_points: the tile size in use); any output may be
+/* Factor-set facts (tile_points: the tile size in use; n_tiles: entries of
+ * the tile table, the balanced layout's padding included); any output may be
  * NULL.  Errors: EINVAL. */
 int vgicp_factorset_info(vgicp_factorset fs, int64_t *n_factors, int64_t *n_tiles,
                          int64_t *total_points, int32_t *tile_points);
 
 /* Schedule autotuning (the batched schedule of Sec. III-D's one-launch
- * linearization round): after 10 warm-up rounds, time a linearization round
- * of this factor set at these poses for each candidate tile size (host int32
- * array of multiples of 256 in [256, 2^20]; NULL = 18432, 13824, 9216, 4608,
- * 3072, 2304, 1536, 768, whole lookup phases of a workgroup) on each of two grids (one
- * workgroup per tile, and a persistent grid of as many workgroups as the
- * device's CUs hold at once for opts' kernel, each walking several tiles),
- * twice in forward and reverse order keeping each pair's best, and keep the
- * fastest pair.  When some source copy is read by more than one factor, every
- * candidate is timed in both tile-table layouts (VGICP_LAYOUT_*) and the
- * faster is kept.  With opts' form VGICP_FORM_AUTO (the default) and an
- * accumulation the pair form supports, every candidate is also timed in the
- * pair form and the factor set keeps the faster form for VGICP_FORM_AUTO
- * calls; with another form only that form is timed (and the kept form is not
- * changed).  H, b, e, inliers are device buffers as for
- * vgicp_linearize_factors, overwritten by the trial rounds.  The factor set's
- * tiles and grid change (results change only by FP32 summation order; the
- * grid alone does not change them) and its captured graphs are dropped.
- * best_tile and best_ms (mean device time of a round) may be NULL; the grid
- * chosen is read with vgicp_factorset_grid, the layout with
- * vgicp_factorset_layout and the form with vgicp_factorset_form.  Synchronizes ctx's stream.
- * Errors: EINVAL, EHIP. */
+ * linearization round): after 10 warm-up rounds, time a linearization round of
+ * this factor set at these poses for each candidate tile size (host int32 array
+ * of multiples of 256 in [256, 2^20]; NULL = 32256, 23040, 18432, 13824, 9216,
+ * 4608, 3072, 2304, 1536, 768, whole lookup phases of a workgroup) on each of
+ * two grids (one workgroup per tile, and a persistent grid of as many
+ * workgroups as the device's CUs hold at once for opts' kernel, each walking
+ * several tiles), twice in forward and reverse order keeping each pair's best,
+ * and keep the fastest pair. Every candidate is timed in the grouped and
+ * balanced tile-table layouts (VGICP_LAYOUT_*), and in the interleaved one when
+ * some source copy is read by more than one factor; the fastest is kept. With
+ * opts' form VGICP_FORM_AUTO (the default) and an accumulation the pair form
+ * supports, every candidate is also timed in the pair form and the factor set
+ * keeps the faster form for VGICP_FORM_AUTO calls; with another form only that
+ * form is timed (and the kept form is not changed). H, b, e, inliers are device
+ * buffers as for vgicp_linearize_factors, overwritten by the trial rounds. The
+ * factor set's tiles and grid change (results change only by FP32 summation
+ * order; the grid alone does not change them) and its captured graphs are
+ * dropped. best_tile and best_ms (mean device time of a round) may be NULL; the
+ * grid chosen is read with vgicp_factorset_grid, the layout with
+ * vgicp_factorset_layout and the form with vgicp_factorset_form. Synchronizes
+ * ctx's stream. Errors: EINVAL, EHIP. */
 int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
                          const vgicp_opts *opts, double *H, double *b, double *e,
                          int64_t *inliers, const int32_t *candidates, int32_t n_candidates,

@@ -1095,7 +1095,7 @@ constexpr int tile_sums() {
 template <int ACC, bool LIN, bool R64, bool CORR, int FUSE, bool PAIR = false>
 __device__ __forceinline__ void linearize_tile(
     LinearizeLds<ACC, tile_sums<LIN, PAIR>()> &L, const uint32_t *&staged, int64_t tile,
-    const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles, int32_t tile_points,
+    const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
     const double *__restrict__ poses, double *__restrict__ partials, int32_t *__restrict__ corr,
     float kappa, double *__restrict__ partials_pair = nullptr) {
   static_assert(!PAIR || (LIN && !CORR), "the pair form linearizes without correspondences");
@@ -1109,6 +1109,7 @@ __device__ __forceinline__ void linearize_tile(
   uint32_t *occ_lds = L.occ;
 
   const Tile td = tiles[tile];
+  if (td.factor < 0) return;  // padding (uniform over the block)
   const FactorDesc fd = factors[td.factor];
   // the previous tile's reads of the LDS sums and bits end before this barrier
   if (fd.occ != staged) {
@@ -1120,7 +1121,7 @@ __device__ __forceinline__ void linearize_tile(
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
-  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const uint32_t end = min(begin + uint32_t(fd.tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
@@ -1283,7 +1284,7 @@ __device__ __forceinline__ void linearize_tile(
 template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
 __global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-            int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
+            int64_t tile_base, int64_t tile_end, int32_t tile_stride,
             const double *__restrict__ poses, double *__restrict__ partials,
             int32_t *__restrict__ corr, float kappa) {
   __shared__ LinearizeLds<ACC, LIN ? kNumSums : 1> L;
@@ -1297,8 +1298,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base) + int64_t(t) * tile_stride,
-                                              factors, tiles, tile_points, poses, partials, corr,
-                                              kappa);
+                                              factors, tiles, poses, partials, corr, kappa);
 }
 
 // The pair form (Eqs. (5)-(6) term by term) over the tiles [tile_base,
@@ -1307,7 +1307,7 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
 template <int ACC, bool R64, int FUSE>
 __global__ void __launch_bounds__(kBlock, 2)
 k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-                 int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
+                 int64_t tile_base, int64_t tile_end, int32_t tile_stride,
                  const double *__restrict__ poses, double *__restrict__ partials,
                  double *__restrict__ partials_pair, float kappa) {
   __shared__ LinearizeLds<ACC, kNumPairSums> L;
@@ -1320,8 +1320,8 @@ k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict_
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, true, R64, false, FUSE, true>(
-        L, staged, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, tile_points, poses,
-        partials, nullptr, kappa, partials_pair);
+        L, staged, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, poses, partials,
+        nullptr, kappa, partials_pair);
 }
 
 // Overlap hit count of one tile (Eq. (7)): brick records only.
@@ -1329,10 +1329,11 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
                                              const uint8_t *up_lds,
                                              const uint32_t *&staged, int64_t tile,
                                              const FactorDesc *__restrict__ factors,
-                                             const Tile *__restrict__ tiles, int32_t tile_points,
+                                             const Tile *__restrict__ tiles,
                                              const double *__restrict__ poses,
                                              double *__restrict__ partials) {
   const Tile td = tiles[tile];
+  if (td.factor < 0) return;  // padding (uniform over the block)
   const FactorDesc fd = factors[td.factor];
   // the previous tile's reads of the LDS counts and bits end before this barrier
   if (fd.occ != staged) {
@@ -1344,7 +1345,7 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
-  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const uint32_t end = min(begin + uint32_t(fd.tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   int hits = 0;
@@ -1400,7 +1401,7 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
 // blocks as in k_linearize.
 __global__ void __launch_bounds__(kBlock)
 k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-          int64_t tile_base, int64_t tile_end, int32_t tile_stride, int32_t tile_points,
+          int64_t tile_base, int64_t tile_end, int32_t tile_stride,
           const double *__restrict__ poses, double *__restrict__ partials) {
   __shared__ int lds_cnt[kWaves];
   __shared__ uint32_t occ_lds[kOccMaxBits / 32];
@@ -1414,7 +1415,7 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   up_table_fill(up_lds);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     overlap_tile(lds_cnt, occ_lds, up_lds, staged, int64_t(base) + int64_t(t) * tile_stride,
-                 factors, tiles, tile_points, poses, partials);
+                 factors, tiles, poses, partials);
 }
 
 // ---------------------------------------------------------------- target order
@@ -1428,16 +1429,17 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
 // blocks in tile order.
 __global__ void __launch_bounds__(kBlock)
 k_voxel_order_keys(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-                   int64_t n_tiles, int32_t tile_points, const double *__restrict__ poses,
+                   int64_t n_tiles, const double *__restrict__ poses,
                    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   const int64_t tile = blockIdx.x;
   if (tile >= n_tiles) return;
   const Tile td = tiles[tile];
+  if (td.factor < 0) return;  // padding
   const FactorDesc fd = factors[td.factor];
   const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
-  const uint32_t end = min(begin + uint32_t(tile_points), n);
+  const uint32_t end = min(begin + uint32_t(fd.tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const uint64_t hi = uint64_t(uint32_t(td.factor)) << 32;
@@ -1463,7 +1465,7 @@ hipError_t launch_voxel_order_keys(const vgicp_factorset_s *fs, const double *po
                                    uint64_t *keys, uint32_t *vals, hipStream_t st) {
   if (fs->n_tiles <= 0) return hipSuccess;
   k_voxel_order_keys<<<unsigned(fs->n_tiles), kBlock, 0, st>>>(
-      fs->d_factors, fs->d_tiles, fs->n_tiles, fs->tile_points, poses, keys, vals);
+      fs->d_factors, fs->d_tiles, fs->n_tiles, poses, keys, vals);
   return hipGetLastError();
 }
 
@@ -1666,10 +1668,10 @@ static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te
   const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (corr) {
     k_linearize<ACC, LIN, R64, true, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials, corr, kappa);
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials, corr, kappa);
   } else {
     k_linearize<ACC, LIN, R64, false, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials, nullptr,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials, nullptr,
         kappa);
   }
   return hipGetLastError();
@@ -1781,11 +1783,11 @@ static hipError_t launch_pair_acc(const vgicp_factorset_s *fs, bool r64, int64_t
   const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (r64)
     k_linearize_pair<ACC, true, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials,
         partials_pair, kappa);
   else
     k_linearize_pair<ACC, false, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, partials,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials,
         partials_pair, kappa);
   return hipGetLastError();
 }
@@ -1834,7 +1836,7 @@ hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st, int32_t stride) {
   if (te <= tb) return hipSuccess;
   k_overlap<<<tile_grid(te - tb, fs->persist_blocks), kBlock, 0, st>>>(
-      fs->d_factors, fs->d_tiles, tb, te, stride, fs->tile_points, poses, fs->d_partials);
+      fs->d_factors, fs->d_tiles, tb, te, stride, poses, fs->d_partials);
   return hipGetLastError();
 }
 

@@ -131,6 +131,7 @@ int overlap_of_cloud(vgicp_ctx ctx, const vgicp_cloud &c, const double *pose,
     for (int64_t s = 0; s < c.n; s += kOverlapTile) h_tile[t++] = Tile{k, int32_t(s)};
     fd.n_tiles = int32_t(t - fd.tile_begin);
     fd.tile_stride = 1;
+    fd.tile_points = kOverlapTile;
   }
   vgicp_factorset_s view;
   view.device = ctx->device;

@@ -60,22 +60,78 @@ int use_device(vgicp_ctx ctx) {
 
 constexpr int64_t kMinAutoTiles = 3072;  // several tiles per resident block slot
 
+// Tile length of the factors cut into short tiles at the end of an XCD's run
+// in the balanced layout: a quarter of tp in whole lookup phases.
+int32_t short_tile(int32_t tp) {
+  const int32_t q = (tp / 4) / kTileQuantum * kTileQuantum;
+  return std::min(tp, std::max(q, int32_t(kTileQuantum)));
+}
+
+// Balanced layout: the grouped order cut into 8 runs of about equal points,
+// one per XCD (the kernels deal the table to the XCDs in eighths); in each
+// run the factors that end in its last tenth of points get short tiles, so
+// that the blocks an XCD starts last are short and its CUs finish together;
+// the runs are padded to one length with padding tiles.
+void build_balanced(vgicp_factorset fs, int32_t tp, std::vector<Tile> &tiles) {
+  const std::vector<int64_t> &order = fs->tile_order;
+  int64_t total = 0;
+  for (int64_t f : order) total += fs->h_factors[size_t(f)].n;
+  std::vector<int> run_of(order.size(), 0);
+  int64_t run_points[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t before = 0;
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int64_t n = fs->h_factors[size_t(order[k])].n;
+    run_of[k] = total > 0 ? int(std::min<int64_t>(7, before * 8 / total)) : 0;
+    run_points[run_of[k]] += n;
+    before += n;
+  }
+  const int32_t tq = short_tile(tp);
+  std::vector<Tile> runs[8];
+  int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int r = run_of[k];
+    FactorDesc &d = fs->h_factors[size_t(order[k])];
+    acc[r] += d.n;
+    d.tile_points = 10 * acc[r] > 9 * run_points[r] ? tq : tp;
+    d.tile_stride = 1;
+    d.tile_begin = int32_t(runs[r].size());  // within the run for now
+    for (int64_t s = 0; s < d.n; s += d.tile_points)
+      runs[r].push_back(Tile{int32_t(order[k]), int32_t(s)});
+    d.n_tiles = int32_t(int64_t(runs[r].size()) - d.tile_begin);
+  }
+  size_t len = 0;
+  for (const auto &run : runs) len = std::max(len, run.size());
+  tiles.reserve(8 * len);
+  for (int r = 0; r < 8; ++r) {
+    tiles.insert(tiles.end(), runs[r].begin(), runs[r].end());
+    tiles.resize(size_t(r + 1) * len, Tile{kPaddingTile, 0});
+  }
+  for (size_t k = 0; k < order.size(); ++k)
+    fs->h_factors[size_t(order[k])].tile_begin += int32_t(size_t(run_of[k]) * len);
+}
+
 // The tile table at `tp` points per tile in the factor set's layout, setting
-// every factor's tile_begin, n_tiles and tile_stride:
+// every factor's tile_begin, n_tiles, tile_stride and tile_points:
 //   VGICP_LAYOUT_GROUPED: factors in tile order (grouped by target map), each
 //     factor's tiles consecutive;
 //   VGICP_LAYOUT_INTERLEAVED: the factors that read one source copy (the same
 //     cloud, unless vgicp_factorset_reorder gave each factor its own copy) side
 //     by side, tile by tile (tile p of each such factor, then p + 1, ...), so
 //     that tiles streaming the same source points run at the same time on one
-//     XCD and share its L2; copies in order of their source cloud.
+//     XCD and share its L2; copies in order of their source cloud;
+//   VGICP_LAYOUT_BALANCED: see build_balanced.
 void build_tiles(vgicp_factorset fs, int32_t tp, std::vector<Tile> &tiles) {
   tiles.clear();
+  if (fs->layout == VGICP_LAYOUT_BALANCED) {
+    build_balanced(fs, tp, tiles);
+    return;
+  }
   if (fs->layout != VGICP_LAYOUT_INTERLEAVED) {
     for (int64_t f : fs->tile_order) {
       FactorDesc &d = fs->h_factors[size_t(f)];
       d.tile_begin = int32_t(tiles.size());
       d.tile_stride = 1;
+      d.tile_points = tp;
       for (int64_t s = 0; s < d.n; s += tp) tiles.push_back(Tile{int32_t(f), int32_t(s)});
       d.n_tiles = int32_t(int64_t(tiles.size()) - d.tile_begin);
     }
@@ -99,6 +155,7 @@ void build_tiles(vgicp_factorset fs, int32_t tp, std::vector<Tile> &tiles) {
       FactorDesc &d = fs->h_factors[size_t(order[k])];
       d.tile_begin = base + int32_t(k - g0);
       d.tile_stride = K;
+      d.tile_points = tp;
       d.n_tiles = int32_t(T);
     }
     for (int64_t p = 0; p < T; ++p)
@@ -565,6 +622,11 @@ int set_tiles(vgicp_ctx ctx, vgicp_factorset fs, int32_t tp, const char *who) {
   if (e == hipSuccess && nt > 0)
     e = hipMemcpyAsync(fs->d_tiles, tiles.data(), size_t(nt) * sizeof(Tile),
                        hipMemcpyHostToDevice, ctx->stream);
+  // padding tiles keep zero partials (no kernel writes them; the counters
+  // sum every tile's row)
+  if (e == hipSuccess && nt > 0)
+    e = hipMemsetAsync(fs->d_partials, 0, size_t(nt) * kPartialStride * sizeof(double),
+                       ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, who, e);
   fs->n_tiles = nt;
@@ -912,7 +974,8 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
   if (rc) return rc;
   if (fs->n_factors > 0 && (!H || !b || !e || !inliers))
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": an output pointer is NULL");
-  static const int32_t kDefaultCandidates[] = {24 * kTileQuantum, 18 * kTileQuantum,
+  static const int32_t kDefaultCandidates[] = {42 * kTileQuantum, 30 * kTileQuantum,
+                                               24 * kTileQuantum, 18 * kTileQuantum,
                                                12 * kTileQuantum, 6 * kTileQuantum,
                                                4 * kTileQuantum,  3 * kTileQuantum,
                                                2 * kTileQuantum,  kTileQuantum};
@@ -957,17 +1020,18 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
     }
     persist[fi] = std::max(8, (ctx->cu_count * std::max(per_cu, 1)) / 8 * 8);
   }
-  // layouts to time: both when some source copy is read by several factors
+  // layouts to time: grouped and balanced, and interleaved when some source
+  // copy is read by several factors
   const int32_t layout0 = fs->layout;
-  int32_t layouts[2] = {VGICP_LAYOUT_GROUPED, VGICP_LAYOUT_INTERLEAVED};
-  int n_layouts = 1;
+  const int32_t layouts[3] = {VGICP_LAYOUT_GROUPED, VGICP_LAYOUT_BALANCED,
+                              VGICP_LAYOUT_INTERLEAVED};
+  int n_layouts = 2;
   {
     std::vector<const float *> copies;
     copies.reserve(fs->h_factors.size());
     for (const FactorDesc &d : fs->h_factors) copies.push_back(d.xyz);
     std::sort(copies.begin(), copies.end());
-    if (std::adjacent_find(copies.begin(), copies.end()) != copies.end()) n_layouts = 2;
-    else layouts[0] = layout0;
+    if (std::adjacent_find(copies.begin(), copies.end()) != copies.end()) n_layouts = 3;
   }
   // slot (layout, form, candidate, grid) -> best mean round time
   const int32_t n_cfg = n_layouts * n_candidates;
@@ -1122,7 +1186,8 @@ int vgicp_factorset_set_layout(vgicp_ctx ctx, vgicp_factorset fs, int32_t layout
   if (!fs) return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set is NULL");
   if (fs->device != ctx->device)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": factor set lives on another device");
-  if (layout != VGICP_LAYOUT_GROUPED && layout != VGICP_LAYOUT_INTERLEAVED)
+  if (layout != VGICP_LAYOUT_GROUPED && layout != VGICP_LAYOUT_INTERLEAVED &&
+      layout != VGICP_LAYOUT_BALANCED)
     return fail(ctx, VGICP_EINVAL, std::string(who) + ": unknown layout");
   int rc = use_device(ctx);
   if (rc) return rc;

@@ -263,6 +263,7 @@ void launch_batch(vgicp_server srv, size_t si) {
       for (int64_t st = 0; st < n; st += tp) s.h_tiles[nt++] = Tile{int32_t(nf), int32_t(st)};
       d.n_tiles = int32_t(nt - d.tile_begin);
       d.tile_stride = 1;
+      d.tile_points = int32_t(tp);
       s.frames_used.push_back(x.src);
       s.frames_used.push_back(x.tgt);
       npts += n;

@@ -191,6 +191,8 @@ struct FactorDesc {
   // or in the interleaved layout the number of factors reading the same
   // source copy.
   int32_t tile_stride;
+  // Source points per tile of this factor (its last tile may hold fewer).
+  int32_t tile_points;
   // Caller's index of each source point when xyz/cov are a reordered copy of
   // the caller's cloud (per-point outputs are written at it); NULL when the
   // points are in the caller's order.
@@ -225,11 +227,15 @@ hipError_t make_sorted_sources(const vgicp_cloud *sources, int32_t n_sources,
 // descriptors.  Synchronizes st.  On failure fs is unchanged.
 hipError_t reorder_by_target(vgicp_factorset_s *fs, const double *poses, hipStream_t st);
 
-// One tile: `count` source points of factor `factor` starting at `start`.
+// One tile: the source points [start, start + tile_points) (at most up to
+// the factor's last point) of factor `factor`, whose descriptor holds its
+// tile_points.  A padding tile (factor < 0) names no points: the kernels skip
+// it and no factor reads its partial sums.
 struct Tile {
   int32_t factor;
   int32_t start;
 };
+constexpr int32_t kPaddingTile = -1;
 
 // Per-tile partial sums written by the linearize/evaluate kernels.
 //   [0, 21)  upper triangle (row-major) of the 6x6 source-frame Hessian

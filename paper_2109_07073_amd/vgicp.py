@@ -32,7 +32,7 @@ SCHED = {"batched": 0, "per_factor": 1}
 RESID = {"f64": 0, "f32": 1}
 FUSED = {"f64": 0, "f32": 1}
 FORM = {"auto": 0, "source": 1, "pair": 2}
-LAYOUT = {"grouped": 0, "interleaved": 1}
+LAYOUT = {"grouped": 0, "interleaved": 1, "balanced": 2}
 NOALLOC_MAX_TILES = 32768      # VGICP_NOALLOC_MAX_TILES
 
 
@@ -575,7 +575,8 @@ def tune_tiles(ctx: Context, fs: FactorSet, poses, candidates=None, accum: str =
                resid: str = "f64", fp64_kappa: float = 0.0, fused: str = "f64",
                form: str = "auto"):
     """Time a linearization round per candidate tile size, grid, tile-table
-    layout (when factors share source copies) and (with form "auto") form,
+    layout (grouped and balanced, and interleaved when factors share source
+    copies) and (with form "auto") form,
     and keep the fastest (vgicp_factorset_tune).  Returns (tile_points, ms per
     round); grid(fs), layout_of(fs) and form_of(fs) give the rest."""
     torch = _torch()
@@ -634,9 +635,12 @@ def grid(fs: FactorSet) -> int:
 
 def set_layout(ctx: Context, fs: FactorSet, layout: str):
     """Tile-table layout: "grouped" (factors by target map, each factor's
-    tiles consecutive) or "interleaved" (the factors reading one source copy
-    side by side, tile by tile) (vgicp_factorset_set_layout).  Results are the
-    same bits in either layout."""
+    tiles consecutive), "interleaved" (the factors reading one source copy
+    side by side, tile by tile) or "balanced" (the grouped order in one run of
+    about equal points per XCD, the factors ending a run cut into quarter-size
+    tiles) (vgicp_factorset_set_layout).  Grouped and interleaved give the
+    same bits; balanced changes the FP32 summation order of the factors it
+    cuts shorter (integer outputs are the same)."""
     if layout not in LAYOUT:
         raise ValueError(f"layout must be one of {sorted(LAYOUT)}")
     _check(_lib.vgicp_factorset_set_layout(ctx.handle, fs.handle, LAYOUT[layout]), ctx.handle)
@@ -644,7 +648,8 @@ def set_layout(ctx: Context, fs: FactorSet, layout: str):
 
 
 def layout_of(fs: FactorSet) -> str:
-    """The factor set's tile-table layout ("grouped" or "interleaved")."""
+    """The factor set's tile-table layout ("grouped", "interleaved" or
+    "balanced")."""
     v = ctypes.c_int32()
     _check(_lib.vgicp_factorset_layout(fs.handle, ctypes.byref(v)))
     return {v2: k for k, v2 in LAYOUT.items()}[v.value]

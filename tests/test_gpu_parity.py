@@ -334,13 +334,84 @@ def test_interleaved_layout_gives_the_same_bits(vg, ctx, ragged, scans, tile):
             vg.set_layout(ctx, g.fs, "diagonal")
 
 
+@pytest.mark.parametrize("tile", [1024, 3072])
+def test_balanced_layout(vg, ctx, ragged, degenerate, scans, tile):
+    """The balanced tile table (one run of about equal points per XCD, the
+    factors ending a run in quarter-size tiles, runs padded with empty tiles):
+    correspondences, inliers, hits and the FP64/degenerate counters equal the
+    grouped table's bit for bit, H, b, e match the oracle, and the batched and
+    per-factor schedules, a persistent grid, the pair form and graph replays
+    agree bit for bit within the layout."""
+    import torch
+    for w in (ragged, degenerate, scans):
+        _, ref = oracle_results(w)
+        g = GpuWorkload(vg, ctx, w, tile_points=tile)
+        base = g.linearize(with_corr=True)
+        chk0 = vg.check_inputs(ctx, g.fs)
+        wide0 = vg.fp64_points(ctx, g.fs)
+        ov0 = g.overlap()
+        vg.set_layout(ctx, g.fs, "balanced")
+        assert vg.layout_of(g.fs) == "balanced"
+        assert g.fs.n_tiles % 8 == 0
+        print(f"balanced {w.name}, tile {tile}: {g.fs.n_tiles} tiles", flush=True)
+        got = g.linearize(with_corr=True)
+        for k in ("corr", "inliers"):
+            assert np.array_equal(got[k], base[k]), (w.name, k)
+        assert vg.check_inputs(ctx, g.fs) == chk0
+        assert vg.fp64_points(ctx, g.fs) == wide0
+        assert_linearize_parity(got, ref)
+        again = g.linearize(with_corr=True, schedule="per_factor")
+        for k in got:
+            assert np.array_equal(again[k], got[k]), (w.name, "per factor", k)
+        # graph replays (on a context with its own stream)
+        side = torch.cuda.Stream()
+        gctx = vg.Context(0, stream=side)
+        fs2 = vg.FactorSet(gctx, g.src, g.maps, g.factors, g.poses.shape[0], tile)
+        vg.set_layout(gctx, fs2, "balanced")
+        F = fs2.n_factors
+        out = {"H": torch.empty((F, 12, 12), dtype=torch.float64, device="cuda"),
+               "b": torch.empty((F, 12), dtype=torch.float64, device="cuda"),
+               "e": torch.empty((F,), dtype=torch.float64, device="cuda"),
+               "inliers": torch.empty((F,), dtype=torch.int64, device="cuda")}
+        for rep in range(3):
+            for v in out.values():
+                v.zero_()
+            torch.cuda.synchronize()
+            vg.linearize_factors(gctx, fs2, g.poses, use_graph=True, out=out)
+            gctx.synchronize()
+            for k in out:
+                assert np.array_equal(out[k].cpu().numpy(), got[k]), (w.name, "graph", rep, k)
+        del fs2, gctx
+        pair = g.linearize(form="pair")
+        assert np.array_equal(pair["inliers"], base["inliers"])
+        assert_linearize_parity(pair, ref)
+        ev = g.evaluate()
+        assert np.array_equal(ev["inliers"], base["inliers"])
+        assert np.array_equal(ev["e"], got["e"])
+        ov = g.overlap()
+        for k in ov0:
+            assert np.array_equal(ov[k], ov0[k]), (w.name, k)
+        vg.set_grid(ctx, g.fs, 64)
+        again = g.linearize(with_corr=True)
+        for k in got:
+            assert np.array_equal(again[k], got[k]), (w.name, "grid 64", k)
+        assert np.array_equal(g.linearize(form="pair")["H"], pair["H"])
+        vg.set_grid(ctx, g.fs, 0)
+        vg.set_layout(ctx, g.fs, "grouped")
+        back = g.linearize(with_corr=True)
+        for k in base:
+            assert np.array_equal(back[k], base[k]), (w.name, "back to grouped", k)
+        del g
+        torch.cuda.synchronize()
+
+
 def test_tuner_picks_a_tile_and_a_grid(vg, ctx, scans):
     g = GpuWorkload(vg, ctx, scans)
     base = g.linearize()
     best, ms = vg.tune_tiles(ctx, g.fs, g.poses, candidates=[768, 2304])
     assert best in (768, 2304) and ms > 0
     assert vg.grid(g.fs) % 8 == 0
-    assert vg.layout_of(g.fs) in ("grouped", "interleaved")
+    assert vg.layout_of(g.fs) in ("grouped", "interleaved", "balanced")
     print(f"tuned: tile {best}, grid {vg.grid(g.fs)}, layout {vg.layout_of(g.fs)}, {ms:.4f} ms")
     got = g.linearize()
     assert np.array_equal(got["inliers"], base["inliers"])
