@@ -938,6 +938,36 @@ __device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
 constexpr int kChunk = kLookupPasses;  // lookup passes per phase of k_linearize (4 waves/SIMD)
 constexpr int kOvlChunk = 2;  // lookup passes per step of k_overlap (8 waves/SIMD)
 constexpr uint32_t kRing = 64 * kChunk + 64;  // >= 63 left over + 64 * kChunk appended
+// Occupancy words of the largest bitset that each thread of a block stages.
+constexpr int kOccWordsPerThread = int(kOccMaxBits / 32 / kBlock);
+static_assert(kOccWordsPerThread * kBlock * 32 == int(kOccMaxBits), "whole words per thread");
+
+// Start of a tile: the map's occupancy words go to the block's LDS and each
+// lane's coordinates of the first NP passes (points threadIdx.x + p kBlock of
+// the tile) are loaded.  The words are loaded first, so that the wait for
+// them before their LDS stores leaves the coordinates in flight across the
+// caller's barrier.  Words past the bitset and points past the tile read
+// zeros without a memory request.  (A block that runs several tiles of one
+// map stores the same words again.)
+template <int NP>
+__device__ __forceinline__ void tile_prologue(const FactorDesc &fd, uint32_t *occ_lds,
+                                              const CloudRsrc &cx, float cur[NP][3]) {
+  const uint32_t words = (fd.occ_mask + 1u) >> 5;
+  const Rsrc ro = make_rsrc(fd.occ, 4ull * words);
+  uint32_t ow[kOccWordsPerThread];
+#pragma unroll
+  for (int j = 0; j < kOccWordsPerThread; ++j)
+    ow[j] = __builtin_bit_cast(uint32_t, ld_f32(ro, (threadIdx.x + uint32_t(j) * kBlock) * 4u));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) load_xyz(cx, threadIdx.x + uint32_t(p) * kBlock, cur[p]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < kOccWordsPerThread; ++j) {
+    const uint32_t w = threadIdx.x + uint32_t(j) * kBlock;
+    if (w < words) occ_lds[w] = ow[j];
+  }
+}
 
 struct HitQueue {
   float x[kRing], y[kRing], z[kRing];
@@ -1083,8 +1113,7 @@ struct LinearizeLds {
   uint8_t up[kUpTable];
 };
 
-// One tile of k_linearize.  `staged` names the map whose occupancy bits the
-// block's LDS holds (restaged only when the tile's map differs).
+// Sums per lane of one tile of k_linearize.
 template <bool LIN, bool PAIR>
 constexpr int tile_sums() {
   return PAIR ? kNumPairSums : LIN ? kNumSums : 1;
@@ -1094,7 +1123,7 @@ constexpr int tile_sums() {
 // kPairStride), its counters to partials as in the source-frame form.
 template <int ACC, bool LIN, bool R64, bool CORR, int FUSE, bool PAIR = false>
 __device__ __forceinline__ void linearize_tile(
-    LinearizeLds<ACC, tile_sums<LIN, PAIR>()> &L, const uint32_t *&staged, int64_t tile,
+    LinearizeLds<ACC, tile_sums<LIN, PAIR>()> &L, int64_t tile,
     const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
     const double *__restrict__ poses, double *__restrict__ partials, int32_t *__restrict__ corr,
     float kappa, double *__restrict__ partials_pair = nullptr) {
@@ -1111,25 +1140,26 @@ __device__ __forceinline__ void linearize_tile(
   const Tile td = tiles[tile];
   if (td.factor < 0) return;  // padding (uniform over the block)
   const FactorDesc fd = factors[td.factor];
-  // the previous tile's reads of the LDS sums and bits end before this barrier
-  if (fd.occ != staged) {
-    const uint32_t words = (fd.occ_mask + 1u) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) occ_lds[w] = fd.occ[w];
-    staged = fd.occ;
-  }
-  __syncthreads();
-  const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(fd.tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x >> 6;
+
+  // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead;
+  // past the tile's end the loads return zeros and the lanes are invalid).
+  float cur[kChunk][3];
+  uint32_t base = begin + wave * 64;
+  tile_prologue<kChunk>(fd, occ_lds, cx, cur);
+  // the previous tile's reads of the LDS sums and bits end before this barrier
+  __syncthreads();
+  const FactorConsts k = factor_consts(fd, poses);
   const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const Rsrc rs = make_rsrc(fd.stats, 36ull * fd.n_voxels);
   const Rsrc ri = make_rsrc(fd.info, 16ull * fd.n_voxels);
   const CorrOut pcorr = corr_out<CORR>(corr, fd, begin);
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = threadIdx.x >> 6;
   HitQueue &Q = queues[wave];
 
   SumsT acc;
@@ -1139,14 +1169,6 @@ __device__ __forceinline__ void linearize_tile(
   uint32_t nwide = 0;            // per lane: hits with the FP64 fused covariance
   uint32_t ndeg = 0;  // hits with a degenerate fused covariance (complete in lane 0)
 
-  // Coordinates of the chunk's kChunk passes (prefetched one chunk ahead;
-  // past the tile's end the loads return zeros and the lanes are invalid).
-  float cur[kChunk][3];
-  uint32_t base = begin + wave * 64;
-  if (base < end) {
-#pragma unroll
-    for (int p = 0; p < kChunk; ++p) load_xyz(cx, base - begin + p * kBlock + lane, cur[p]);
-  }
   while (base < end) {
     // ---- lookup phase: the brick records of all kChunk passes are in flight
     // at once, then the next chunk's coordinates; records are then resolved
@@ -1279,8 +1301,8 @@ __device__ __forceinline__ void linearize_tile(
 // tiles in flight on one XCD are neighbours in the table: tiles of one factor,
 // and factors sorted by target map, share that XCD's L2.  With one block per
 // tile (P = the eighth's length) each block runs one tile; a persistent grid
-// (P blocks per XCD resident at once) runs several and keeps a map's
-// occupancy bits in LDS across its consecutive tiles of that map.
+// (P blocks per XCD resident at once) runs several.  Every tile stages its
+// map's occupancy bits in the block's LDS.
 template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
 __global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
@@ -1294,10 +1316,9 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   const uint32_t lo = (blockIdx.x & 7u) * per;
   const uint32_t hi = min(lo + per, count);
   const uint32_t P = gridDim.x >> 3;
-  const uint32_t *staged = nullptr;
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
-    linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, staged, int64_t(base) + int64_t(t) * tile_stride,
+    linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, int64_t(base) + int64_t(t) * tile_stride,
                                               factors, tiles, poses, partials, corr, kappa);
 }
 
@@ -1316,18 +1337,16 @@ k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict_
   const uint32_t lo = (blockIdx.x & 7u) * per;
   const uint32_t hi = min(lo + per, count);
   const uint32_t P = gridDim.x >> 3;
-  const uint32_t *staged = nullptr;
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, true, R64, false, FUSE, true>(
-        L, staged, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, poses, partials,
+        L, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, poses, partials,
         nullptr, kappa, partials_pair);
 }
 
 // Overlap hit count of one tile (Eq. (7)): brick records only.
 __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
-                                             const uint8_t *up_lds,
-                                             const uint32_t *&staged, int64_t tile,
+                                             const uint8_t *up_lds, int64_t tile,
                                              const FactorDesc *__restrict__ factors,
                                              const Tile *__restrict__ tiles,
                                              const double *__restrict__ poses,
@@ -1335,27 +1354,19 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
   const Tile td = tiles[tile];
   if (td.factor < 0) return;  // padding (uniform over the block)
   const FactorDesc fd = factors[td.factor];
-  // the previous tile's reads of the LDS counts and bits end before this barrier
-  if (fd.occ != staged) {
-    const uint32_t words = (fd.occ_mask + 1u) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) occ_lds[w] = fd.occ[w];
-    staged = fd.occ;
-  }
-  __syncthreads();
-  const FactorConsts k = factor_consts(fd, poses);
   const uint32_t n = uint32_t(fd.n);
   const uint32_t begin = uint32_t(td.start);
   const uint32_t end = min(begin + uint32_t(fd.tile_points), n);
   const CloudRsrc cx = tile_rsrc(fd.xyz, begin, end);
-  const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
-  int hits = 0;
   float cur[kOvlChunk][3];
   uint32_t base = begin + (threadIdx.x & ~63u);
   const uint32_t lane = threadIdx.x & 63;
-  if (base < end) {
-#pragma unroll
-    for (int p = 0; p < kOvlChunk; ++p) load_xyz(cx, base - begin + p * kBlock + lane, cur[p]);
-  }
+  tile_prologue<kOvlChunk>(fd, occ_lds, cx, cur);
+  // the previous tile's reads of the LDS counts and bits end before this barrier
+  __syncthreads();
+  const FactorConsts k = factor_consts(fd, poses);
+  const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
+  int hits = 0;
   for (; base < end; base += kOvlChunk * kBlock) {
     VoxelKey vk[kOvlChunk];
     RecordLoad rec[kOvlChunk];
@@ -1411,10 +1422,9 @@ k_overlap(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles
   const uint32_t lo = (blockIdx.x & 7u) * per;
   const uint32_t hi = min(lo + per, count);
   const uint32_t P = gridDim.x >> 3;
-  const uint32_t *staged = nullptr;
   up_table_fill(up_lds);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
-    overlap_tile(lds_cnt, occ_lds, up_lds, staged, int64_t(base) + int64_t(t) * tile_stride,
+    overlap_tile(lds_cnt, occ_lds, up_lds, int64_t(base) + int64_t(t) * tile_stride,
                  factors, tiles, poses, partials);
 }
 
