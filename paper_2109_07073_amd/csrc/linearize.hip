@@ -942,19 +942,18 @@ constexpr uint32_t kRing = 64 * kChunk + 64;  // >= 63 left over + 64 * kChunk a
 constexpr int kOccWordsPerThread = int(kOccMaxBits / 32 / kBlock);
 static_assert(kOccWordsPerThread * kBlock * 32 == int(kOccMaxBits), "whole words per thread");
 
-// Start of a tile: the map's occupancy words go to the block's LDS and each
-// lane's coordinates of the first NP passes (points threadIdx.x + p kBlock of
-// the tile) are loaded.  The words are loaded first, so that the wait for
-// them before their LDS stores leaves the coordinates in flight across the
-// caller's barrier.  Words past the bitset and points past the tile read
-// zeros without a memory request.  (A block that runs several tiles of one
-// map stores the same words again.)
+// Start of a tile, in two steps around the caller's work that needs no
+// memory: tile_loads loads this thread's share of the map's occupancy words
+// and each lane's coordinates of the first NP passes (points threadIdx.x +
+// p kBlock of the tile), the words first; tile_stage then stores the words in
+// the block's LDS.  The wait for the words leaves the coordinates in flight
+// across the caller's barrier.  Words past the bitset and points past the
+// tile read zeros without a memory request.  (A block that runs several tiles
+// of one map stores the same words again.)
 template <int NP>
-__device__ __forceinline__ void tile_prologue(const FactorDesc &fd, uint32_t *occ_lds,
-                                              const CloudRsrc &cx, float cur[NP][3]) {
-  const uint32_t words = (fd.occ_mask + 1u) >> 5;
-  const Rsrc ro = make_rsrc(fd.occ, 4ull * words);
-  uint32_t ow[kOccWordsPerThread];
+__device__ __forceinline__ void tile_loads(const FactorDesc &fd, const CloudRsrc &cx,
+                                           uint32_t ow[kOccWordsPerThread], float cur[NP][3]) {
+  const Rsrc ro = make_rsrc(fd.occ, 4ull * ((fd.occ_mask + 1u) >> 5));
 #pragma unroll
   for (int j = 0; j < kOccWordsPerThread; ++j)
     ow[j] = __builtin_bit_cast(uint32_t, ld_f32(ro, (threadIdx.x + uint32_t(j) * kBlock) * 4u));
@@ -962,6 +961,11 @@ __device__ __forceinline__ void tile_prologue(const FactorDesc &fd, uint32_t *oc
 #pragma unroll
   for (int p = 0; p < NP; ++p) load_xyz(cx, threadIdx.x + uint32_t(p) * kBlock, cur[p]);
   __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void tile_stage(const FactorDesc &fd, uint32_t *occ_lds,
+                                           const uint32_t ow[kOccWordsPerThread]) {
+  const uint32_t words = (fd.occ_mask + 1u) >> 5;
 #pragma unroll
   for (int j = 0; j < kOccWordsPerThread; ++j) {
     const uint32_t w = threadIdx.x + uint32_t(j) * kBlock;
@@ -1151,10 +1155,13 @@ __device__ __forceinline__ void linearize_tile(
   // past the tile's end the loads return zeros and the lanes are invalid).
   float cur[kChunk][3];
   uint32_t base = begin + wave * 64;
-  tile_prologue<kChunk>(fd, occ_lds, cx, cur);
-  // the previous tile's reads of the LDS sums and bits end before this barrier
-  __syncthreads();
+  uint32_t ow[kOccWordsPerThread];
+  tile_loads<kChunk>(fd, cx, ow, cur);
+  // the relative pose while the loads are in flight
   const FactorConsts k = factor_consts(fd, poses);
+  // the previous tile's reads of the LDS sums and bits end before this barrier
+  tile_stage(fd, occ_lds, ow);
+  __syncthreads();
   const Rsrc rc = make_rsrc(fd.cov + 6ull * begin, 24ull * (end - begin));
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   const Rsrc rs = make_rsrc(fd.stats, 36ull * fd.n_voxels);
@@ -1361,10 +1368,13 @@ __device__ __forceinline__ void overlap_tile(int *lds_cnt, uint32_t *occ_lds,
   float cur[kOvlChunk][3];
   uint32_t base = begin + (threadIdx.x & ~63u);
   const uint32_t lane = threadIdx.x & 63;
-  tile_prologue<kOvlChunk>(fd, occ_lds, cx, cur);
-  // the previous tile's reads of the LDS counts and bits end before this barrier
-  __syncthreads();
+  uint32_t ow[kOccWordsPerThread];
+  tile_loads<kOvlChunk>(fd, cx, ow, cur);
+  // the relative pose while the loads are in flight
   const FactorConsts k = factor_consts(fd, poses);
+  // the previous tile's reads of the LDS counts and bits end before this barrier
+  tile_stage(fd, occ_lds, ow);
+  __syncthreads();
   const Rsrc rb = make_rsrc(fd.bricks, 32ull << fd.log2cap);
   int hits = 0;
   for (; base < end; base += kOvlChunk * kBlock) {
