@@ -88,12 +88,12 @@ def build_workload(name: str):
                               n_factors=spec["n_factors"], src_range=spec["src_range"])
 
 
-def profiled_traffic(workload: str, tile_points: int | None = None):
+def profiled_traffic(workload: str, tile_points: int | None = None, layout: str | None = None):
     """HBM bytes per linearize launch measured by rocprofv3 (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) for this workload, from
     profiles/k_linearize_<workload>.md, or None when there is no profile, the
     kernel sources have changed since it was taken, or no figure was taken at
-    this tile size."""
+    this tile size and tile-table layout."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_linearize_{workload}.md")
     if not os.path.exists(path):
@@ -102,7 +102,7 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
     with open(path) as fh:
         for line in fh:
             key, _, val = line.strip().partition(": ")
-            if key in ("traffic_bytes_per_launch", "source_sha256_16", "tile_points") or \
+            if key in ("traffic_bytes_per_launch", "source_sha256_16", "tile_points", "layout") or \
                     key.startswith("traffic_bytes_per_launch_at_"):
                 fields[key] = val.strip()
     csrc = os.path.join(ROOT, "paper_2109_07073_amd", "csrc")
@@ -111,6 +111,8 @@ def profiled_traffic(workload: str, tile_points: int | None = None):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    if layout is not None and fields.get("layout", "grouped") != layout:
         return None
     if tile_points is None or fields.get("tile_points") == str(tile_points):
         return float(fields["traffic_bytes_per_launch"])
@@ -983,7 +985,7 @@ def main():
     # the same with the covariance of every source point charged (36 B per point)
     all_cov_bytes = float(36 * sizes.sum() + 44 * U.sum() + 91 * 8 * F)
     achieved = needed_bytes / (k_ms * 1e-3) / 1e9
-    traffic = (profiled_traffic(args.workload, fs.tile_points)
+    traffic = (profiled_traffic(args.workload, fs.tile_points, vg.layout_of(fs))
                if (args.accum, args.fused, form) == ("mixed", "f64", "source") else None)
     copy_gbs = measured_copy_gbs()
 

@@ -27,6 +27,7 @@ def test_profiled_traffic_follows_the_sources():
     # most three times the 3.88 GB of algorithmic bytes per round
     assert t is None or 12 * 101_596_832 < t < 3 * 3.88e9
     assert bench.profiled_traffic("batched4500", 1536) is None
+    assert bench.profiled_traffic("batched4500", None, "interleaved") is None
     assert bench.profiled_traffic("no_such_workload") is None
 
 

@@ -90,6 +90,13 @@ def test_noalloc_other_options_and_schedules(vg, ctx):
         got = vg.linearize_factors_noalloc(ctx, g.fs, g.poses, _outputs(F, n, False), **kw)
         ctx.synchronize()
         _assert_same(_np(got), _np(ref))
+    # the balanced tile table (short tiles and padding tiles)
+    vg.set_layout(ctx, g.fs, "balanced")
+    print(f"noalloc balanced layout: {g.fs.n_tiles} tiles", flush=True)
+    ref = vg.linearize_factors(ctx, g.fs, g.poses, with_corr=True)
+    got = vg.linearize_factors_noalloc(ctx, g.fs, g.poses, _outputs(F, n, True))
+    ctx.synchronize()
+    _assert_same(_np(got), _np(ref))
 
 
 def test_noalloc_rejects_graphs_and_too_many_tiles(vg, ctx):
