@@ -928,9 +928,10 @@ def main():
     n_pts = int(fs.total_points)
 
     # ---- round latency: device time (events) and host-visible (incl. D2H),
-    # over at least 100 rounds, after three untimed rounds that capture and
-    # instantiate the round's graph
-    for _ in range(3):
+    # over at least 100 rounds, after untimed rounds that capture and
+    # instantiate the round's graph and bring the clocks up (the first of them
+    # run long)
+    for _ in range(max(args.warmup, 20)):
         vg.linearize_factors(ctx, fs, poses, accum=args.accum, fused=args.fused, use_graph=True, out=out)
     torch.cuda.synchronize()
     dev_ms, host_ms = [], []

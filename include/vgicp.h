@@ -591,9 +591,10 @@ const char *vgicp_server_last_error(vgicp_server srv);
  * order a factor set gives a source cloud whose maps all have this resolution,
  * so a server factor and a factor-set factor agree bit for bit when every
  * target of that source in the factor set has the source frame's resolution
- * and both use the same tile_points; otherwise the points are summed in
- * another order and they agree within FP32 summation error (integer outputs
- * always agree).  Requests have no per-point outputs.  Returns its id.
+ * and both use the same tile_points, the factor set in the grouped or
+ * interleaved layout without target-order copies; otherwise the points are
+ * summed in another order and they agree within FP32 summation error (integer
+ * outputs always agree).  Requests have no per-point outputs.  Returns its id.
  * Errors: EINVAL (n outside [0, 2^26], NULL arrays, bad resolution), ENONFINITE,
  * ERANGE, EFULL (the frame would exceed the memory
  * budget; nothing is kept), ENOMEM, EHIP. */
