@@ -565,6 +565,7 @@ struct FactorConsts {
   double R64[9];  // R itself: FP64 residual and FP64 fused covariance
   double t64[3];  // t itself: FP64 residual
 };
+static_assert(sizeof(FactorConsts) == kFactorConstsBytes, "the factor set's constant table");
 
 __device__ __forceinline__ float uniform_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
@@ -911,23 +912,45 @@ __device__ __forceinline__ bool add_pair_terms(SumsT &acc, const FactorConsts &k
 }
 
 // ---------------------------------------------------------------- tiles
-__device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
-                                                      const double *__restrict__ poses) {
+// The constants of factor fd at `poses`, computed by this lane.
+__device__ __forceinline__ FactorConsts factor_consts_lane(const FactorDesc &fd,
+                                                           const double *__restrict__ poses) {
   double R[9], t[3];
   relative_pose64(poses + 12 * int64_t(fd.pose_i), poses + 12 * int64_t(fd.pose_j), R, t);
   const double s = fd.scale;
   FactorConsts k;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    k.S[i] = uniform_f(float(s * R[i]));
-    k.R[i] = uniform_f(float(R[i]));
-    k.R64[i] = uniform_d(R[i]);
+    k.S[i] = float(s * R[i]);
+    k.R[i] = float(R[i]);
+    k.R64[i] = R[i];
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    k.u[i] = uniform_f(float(s * t[i]));
-    k.t[i] = uniform_f(float(t[i]));
-    k.t64[i] = uniform_d(t[i]);
+    k.u[i] = float(s * t[i]);
+    k.t[i] = float(t[i]);
+    k.t64[i] = t[i];
+  }
+  return k;
+}
+
+// The same, computed by every lane of a wave (fd is the same in all lanes)
+// and held as wave-uniform values.
+__device__ __forceinline__ FactorConsts factor_consts(const FactorDesc &fd,
+                                                      const double *__restrict__ poses) {
+  const FactorConsts l = factor_consts_lane(fd, poses);
+  FactorConsts k;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    k.S[i] = uniform_f(l.S[i]);
+    k.R[i] = uniform_f(l.R[i]);
+    k.R64[i] = uniform_d(l.R64[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    k.u[i] = uniform_f(l.u[i]);
+    k.t[i] = uniform_f(l.t[i]);
+    k.t64[i] = uniform_d(l.t64[i]);
   }
   return k;
 }
@@ -1129,8 +1152,9 @@ template <int ACC, bool LIN, bool R64, bool CORR, int FUSE, bool PAIR = false>
 __device__ __forceinline__ void linearize_tile(
     LinearizeLds<ACC, tile_sums<LIN, PAIR>()> &L, int64_t tile,
     const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
-    const double *__restrict__ poses, double *__restrict__ partials, int32_t *__restrict__ corr,
-    float kappa, double *__restrict__ partials_pair = nullptr) {
+    const double *__restrict__ poses, const FactorConsts *__restrict__ consts,
+    double *__restrict__ partials, int32_t *__restrict__ corr, float kappa,
+    double *__restrict__ partials_pair = nullptr) {
   static_assert(!PAIR || (LIN && !CORR), "the pair form linearizes without correspondences");
   constexpr int N = tile_sums<LIN, PAIR>();
   using SumsT = Sums<ACC, N>;
@@ -1157,8 +1181,9 @@ __device__ __forceinline__ void linearize_tile(
   uint32_t base = begin + wave * 64;
   uint32_t ow[kOccWordsPerThread];
   tile_loads<kChunk>(fd, cx, ow, cur);
-  // the relative pose while the loads are in flight
-  const FactorConsts k = factor_consts(fd, poses);
+  // the relative pose (from the round's table when there is one) while the
+  // loads are in flight
+  const FactorConsts k = consts ? consts[td.factor] : factor_consts(fd, poses);
   // the previous tile's reads of the LDS sums and bits end before this barrier
   tile_stage(fd, occ_lds, ow);
   __syncthreads();
@@ -1314,8 +1339,8 @@ template <int ACC, bool LIN, bool R64, bool CORR, int FUSE>
 __global__ void __launch_bounds__(kBlock, ACC == VGICP_ACC_F64 ? 1 : 4)
 k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
             int64_t tile_base, int64_t tile_end, int32_t tile_stride,
-            const double *__restrict__ poses, double *__restrict__ partials,
-            int32_t *__restrict__ corr, float kappa) {
+            const double *__restrict__ poses, const FactorConsts *__restrict__ consts,
+            double *__restrict__ partials, int32_t *__restrict__ corr, float kappa) {
   __shared__ LinearizeLds<ACC, LIN ? kNumSums : 1> L;
   // tile indices are below 2^31 (the tile table is indexed by int32)
   const uint32_t base = uint32_t(tile_base), count = uint32_t(tile_end - tile_base);
@@ -1326,7 +1351,8 @@ k_linearize(const FactorDesc *__restrict__ factors, const Tile *__restrict__ til
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, LIN, R64, CORR, FUSE>(L, int64_t(base) + int64_t(t) * tile_stride,
-                                              factors, tiles, poses, partials, corr, kappa);
+                                              factors, tiles, poses, consts, partials, corr,
+                                              kappa);
 }
 
 // The pair form (Eqs. (5)-(6) term by term) over the tiles [tile_base,
@@ -1336,8 +1362,9 @@ template <int ACC, bool R64, int FUSE>
 __global__ void __launch_bounds__(kBlock, 2)
 k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict__ tiles,
                  int64_t tile_base, int64_t tile_end, int32_t tile_stride,
-                 const double *__restrict__ poses, double *__restrict__ partials,
-                 double *__restrict__ partials_pair, float kappa) {
+                 const double *__restrict__ poses, const FactorConsts *__restrict__ consts,
+                 double *__restrict__ partials, double *__restrict__ partials_pair,
+                 float kappa) {
   __shared__ LinearizeLds<ACC, kNumPairSums> L;
   const uint32_t base = uint32_t(tile_base), count = uint32_t(tile_end - tile_base);
   const uint32_t per = (count + 7u) >> 3;
@@ -1347,7 +1374,7 @@ k_linearize_pair(const FactorDesc *__restrict__ factors, const Tile *__restrict_
   up_table_fill(L.up);  // read after the first tile's barrier
   for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += P)
     linearize_tile<ACC, true, R64, false, FUSE, true>(
-        L, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, poses, partials,
+        L, int64_t(base) + int64_t(t) * tile_stride, factors, tiles, poses, consts, partials,
         nullptr, kappa, partials_pair);
 }
 
@@ -1682,16 +1709,16 @@ static inline unsigned tile_grid(int64_t tiles, int32_t persist_blocks) {
 
 template <int ACC, bool LIN, bool R64, int FUSE>
 static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te, int32_t stride,
-                             const double *poses, double *partials, int32_t *corr, float kappa,
-                             hipStream_t st) {
+                             const double *poses, const FactorConsts *consts, double *partials,
+                             int32_t *corr, float kappa, hipStream_t st) {
   if (te <= tb) return hipSuccess;
   const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (corr) {
     k_linearize<ACC, LIN, R64, true, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials, corr, kappa);
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, consts, partials, corr, kappa);
   } else {
     k_linearize<ACC, LIN, R64, false, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials, nullptr,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, consts, partials, nullptr,
         kappa);
   }
   return hipGetLastError();
@@ -1699,37 +1726,39 @@ static hipError_t launch_lin(const vgicp_factorset_s *fs, int64_t tb, int64_t te
 
 template <int ACC, int FUSE>
 static hipError_t launch_acc(const vgicp_factorset_s *fs, bool lin, bool r64, int64_t tb,
-                             int64_t te, int32_t stride, const double *poses, double *partials,
-                             int32_t *corr, float kappa, hipStream_t st) {
+                             int64_t te, int32_t stride, const double *poses,
+                             const FactorConsts *consts, double *partials, int32_t *corr,
+                             float kappa, hipStream_t st) {
   if (lin) {
-    return r64 ? launch_lin<ACC, true, true, FUSE>(fs, tb, te, stride, poses, partials, corr,
-                                                   kappa, st)
-               : launch_lin<ACC, true, false, FUSE>(fs, tb, te, stride, poses, partials, corr,
-                                                    kappa, st);
+    return r64 ? launch_lin<ACC, true, true, FUSE>(fs, tb, te, stride, poses, consts, partials,
+                                                   corr, kappa, st)
+               : launch_lin<ACC, true, false, FUSE>(fs, tb, te, stride, poses, consts, partials,
+                                                    corr, kappa, st);
   }
-  return r64 ? launch_lin<ACC, false, true, FUSE>(fs, tb, te, stride, poses, partials, corr,
-                                                  kappa, st)
-             : launch_lin<ACC, false, false, FUSE>(fs, tb, te, stride, poses, partials, corr,
-                                                   kappa, st);
+  return r64 ? launch_lin<ACC, false, true, FUSE>(fs, tb, te, stride, poses, consts, partials,
+                                                  corr, kappa, st)
+             : launch_lin<ACC, false, false, FUSE>(fs, tb, te, stride, poses, consts, partials,
+                                                   corr, kappa, st);
 }
 
 template <int FUSE>
 static hipError_t launch_k(const vgicp_factorset_s *fs, int accum, bool lin, bool r64, int64_t tb,
-                           int64_t te, int32_t stride, const double *poses, double *partials,
-                           int32_t *corr, float kappa, hipStream_t st) {
+                           int64_t te, int32_t stride, const double *poses,
+                           const FactorConsts *consts, double *partials, int32_t *corr,
+                           float kappa, hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F64:
-      return launch_acc<VGICP_ACC_F64, FUSE>(fs, lin, r64, tb, te, stride, poses, partials, corr,
-                                              kappa, st);
+      return launch_acc<VGICP_ACC_F64, FUSE>(fs, lin, r64, tb, te, stride, poses, consts,
+                                              partials, corr, kappa, st);
     case VGICP_ACC_F32_COMP:
-      return launch_acc<VGICP_ACC_F32_COMP, FUSE>(fs, lin, r64, tb, te, stride, poses, partials,
-                                                   corr, kappa, st);
+      return launch_acc<VGICP_ACC_F32_COMP, FUSE>(fs, lin, r64, tb, te, stride, poses, consts,
+                                                   partials, corr, kappa, st);
     case VGICP_ACC_F32:
-      return launch_acc<VGICP_ACC_F32, FUSE>(fs, lin, r64, tb, te, stride, poses, partials, corr,
-                                              kappa, st);
+      return launch_acc<VGICP_ACC_F32, FUSE>(fs, lin, r64, tb, te, stride, poses, consts,
+                                              partials, corr, kappa, st);
     default:
-      return launch_acc<VGICP_ACC_MIXED, FUSE>(fs, lin, r64, tb, te, stride, poses, partials,
-                                                corr, kappa, st);
+      return launch_acc<VGICP_ACC_MIXED, FUSE>(fs, lin, r64, tb, te, stride, poses, consts,
+                                                partials, corr, kappa, st);
   }
 }
 
@@ -1773,75 +1802,99 @@ hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks) 
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
 
+// Constants of every factor of fs at `poses` into fs->d_consts (one thread
+// per factor), for the linearize launches of a round that follow on st.
+__global__ void __launch_bounds__(64)
+k_factor_consts(const FactorDesc *__restrict__ factors, int64_t n, const double *__restrict__ poses,
+                FactorConsts *__restrict__ out) {
+  const int64_t f = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  if (f >= n) return;
+  out[f] = factor_consts_lane(factors[f], poses);
+}
+
+hipError_t launch_factor_consts(const vgicp_factorset_s *fs, const double *poses, hipStream_t st) {
+  if (!fs->d_consts || fs->n_factors <= 0) return hipSuccess;
+  k_factor_consts<<<unsigned((fs->n_factors + 63) / 64), 64, 0, st>>>(
+      fs->d_factors, fs->n_factors, poses, static_cast<FactorConsts *>(fs->d_consts));
+  return hipGetLastError();
+}
+
 // Launches over the tiles tb + k * stride, k < te - tb (stride 1: the range
 // [tb, te) of the tile table; a factor's own tiles: its tile_begin, n_tiles
-// and tile_stride).
+// and tile_stride).  `consts` (may be NULL: every tile computes its factor's
+// constants) is the table launch_factor_consts wrote for these poses.
 hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, bool lin, int64_t tb, int64_t te,
                                  const double *poses, double *partials, int32_t *corr,
-                                 hipStream_t st, int32_t stride) {
+                                 hipStream_t st, int32_t stride, const void *consts) {
   const bool r64 = resid == VGICP_RESID_F64;
+  const FactorConsts *k = static_cast<const FactorConsts *>(consts);
   if (fused == VGICP_FUSED_F64)
-    return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, 0.f, st);
+    return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, stride, poses, k, partials, corr, 0.f,
+                             st);
   if (kappa > 0.f)
-    return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, kappa,
-                               st);
-  return launch_k<kFuse32>(fs, accum, lin, r64, tb, te, stride, poses, partials, corr, 0.f, st);
+    return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, stride, poses, k, partials, corr,
+                               kappa, st);
+  return launch_k<kFuse32>(fs, accum, lin, r64, tb, te, stride, poses, k, partials, corr, 0.f, st);
 }
 
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa, bool lin, int64_t tb, int64_t te, const double *poses,
-                            int32_t *corr, hipStream_t st, int32_t stride) {
+                            int32_t *corr, hipStream_t st, int32_t stride, const void *consts) {
   return launch_linearize_into(fs, accum, resid, fused, kappa, lin, tb, te, poses,
-                               fs->d_partials, corr, st, stride);
+                               fs->d_partials, corr, st, stride, consts);
 }
 
 template <int ACC, int FUSE>
 static hipError_t launch_pair_acc(const vgicp_factorset_s *fs, bool r64, int64_t tb, int64_t te,
-                                  int32_t stride, const double *poses, double *partials,
+                                  int32_t stride, const double *poses,
+                                  const FactorConsts *consts, double *partials,
                                   double *partials_pair, float kappa, hipStream_t st) {
   const unsigned grid = tile_grid(te - tb, fs->persist_blocks);
   if (r64)
     k_linearize_pair<ACC, true, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, consts, partials,
         partials_pair, kappa);
   else
     k_linearize_pair<ACC, false, FUSE><<<grid, kBlock, 0, st>>>(
-        fs->d_factors, fs->d_tiles, tb, te, stride, poses, partials,
+        fs->d_factors, fs->d_tiles, tb, te, stride, poses, consts, partials,
         partials_pair, kappa);
   return hipGetLastError();
 }
 
 template <int FUSE>
 static hipError_t launch_pair_k(const vgicp_factorset_s *fs, int accum, bool r64, int64_t tb,
-                                int64_t te, int32_t stride, const double *poses, double *partials,
+                                int64_t te, int32_t stride, const double *poses,
+                                const FactorConsts *consts, double *partials,
                                 double *partials_pair, float kappa, hipStream_t st) {
   switch (accum) {
     case VGICP_ACC_F32_COMP:
-      return launch_pair_acc<VGICP_ACC_F32_COMP, FUSE>(fs, r64, tb, te, stride, poses, partials,
-                                                        partials_pair, kappa, st);
+      return launch_pair_acc<VGICP_ACC_F32_COMP, FUSE>(fs, r64, tb, te, stride, poses, consts,
+                                                        partials, partials_pair, kappa, st);
     case VGICP_ACC_F32:
-      return launch_pair_acc<VGICP_ACC_F32, FUSE>(fs, r64, tb, te, stride, poses, partials,
-                                                   partials_pair, kappa, st);
+      return launch_pair_acc<VGICP_ACC_F32, FUSE>(fs, r64, tb, te, stride, poses, consts,
+                                                   partials, partials_pair, kappa, st);
     default:
-      return launch_pair_acc<VGICP_ACC_MIXED, FUSE>(fs, r64, tb, te, stride, poses, partials,
-                                                     partials_pair, kappa, st);
+      return launch_pair_acc<VGICP_ACC_MIXED, FUSE>(fs, r64, tb, te, stride, poses, consts,
+                                                     partials, partials_pair, kappa, st);
   }
 }
 
 hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, int64_t tb, int64_t te, const double *poses,
-                                 hipStream_t st, int32_t stride) {
+                                 hipStream_t st, int32_t stride, const void *consts) {
   if (te <= tb) return hipSuccess;
   if (accum == VGICP_ACC_F64) return hipErrorInvalidValue;  // rejected by the callers
   const bool r64 = resid == VGICP_RESID_F64;
+  const FactorConsts *k = static_cast<const FactorConsts *>(consts);
   double *pp = fs->d_partials_pair;
   double *part = fs->d_partials;
   if (fused == VGICP_FUSED_F64)
-    return launch_pair_k<kFuse64>(fs, accum, r64, tb, te, stride, poses, part, pp, 0.f, st);
+    return launch_pair_k<kFuse64>(fs, accum, r64, tb, te, stride, poses, k, part, pp, 0.f, st);
   if (kappa > 0.f)
-    return launch_pair_k<kFuseGate>(fs, accum, r64, tb, te, stride, poses, part, pp, kappa, st);
-  return launch_pair_k<kFuse32>(fs, accum, r64, tb, te, stride, poses, part, pp, 0.f, st);
+    return launch_pair_k<kFuseGate>(fs, accum, r64, tb, te, stride, poses, k, part, pp, kappa,
+                                    st);
+  return launch_pair_k<kFuse32>(fs, accum, r64, tb, te, stride, poses, k, part, pp, 0.f, st);
 }
 
 hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,

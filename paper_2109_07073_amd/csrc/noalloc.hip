@@ -17,7 +17,8 @@ namespace vgicp {
 hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, bool lin, int64_t tb, int64_t te,
                                  const double *poses, double *partials, int32_t *corr,
-                                 hipStream_t st, int32_t stride = 1);
+                                 hipStream_t st, int32_t stride = 1,
+                                 const void *consts = nullptr);
 hipError_t launch_reduce_from(const vgicp_factorset_s *fs, int64_t f0, int64_t nf,
                               const double *poses, const double *partials, int mode, double *H,
                               double *b, double *e, int64_t *inl, double *overlap,

@@ -16,7 +16,8 @@ int map_export_impl(vgicp_ctx ctx, vgicp_map m, int32_t *keys, float *mean, floa
                     int32_t *count, std::string &msg);
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa, bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st, int32_t stride = 1);
+                            hipStream_t st, int32_t stride = 1, const void *consts = nullptr);
+hipError_t launch_factor_consts(const vgicp_factorset_s *fs, const double *poses, hipStream_t st);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,
@@ -27,7 +28,8 @@ hipError_t launch_assemble(const vgicp_factorset_s *fs, const double *H, const d
 hipError_t linearize_blocks_per_cu(int accum, int fused, int form, int *blocks);
 hipError_t launch_linearize_pair(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                                  float kappa, int64_t tb, int64_t te, const double *poses,
-                                 hipStream_t st, int32_t stride = 1);
+                                 hipStream_t st, int32_t stride = 1,
+                                 const void *consts = nullptr);
 hipError_t launch_reduce_pair(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, double *H,
                               double *b, double *e, int64_t *inl, hipStream_t st);
 }  // namespace vgicp
@@ -554,6 +556,8 @@ int vgicp_factorset_create(vgicp_ctx ctx, const vgicp_cloud *sources, int32_t n_
   const size_t tbytes = std::max<size_t>(1, tiles.size()) * sizeof(Tile);
   const size_t pbytes = std::max<size_t>(1, tiles.size()) * kPartialStride * sizeof(double);
   e = hipMalloc(&fs->d_factors, fbytes);
+  if (e == hipSuccess)
+    e = hipMalloc(&fs->d_consts, std::max<size_t>(1, fs->h_factors.size()) * kFactorConstsBytes);
   if (e == hipSuccess) e = hipMalloc(&fs->d_tiles, tbytes);
   if (e == hipSuccess) e = hipMalloc(&fs->d_partials, pbytes);
   // zeroed so that the FP64-point count reads 0 before the first call
@@ -663,6 +667,7 @@ int vgicp_factorset_destroy(vgicp_factorset fs) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (fs->d_factors) (void)hipFree(fs->d_factors);
+  if (fs->d_consts) (void)hipFree(fs->d_consts);
   if (fs->d_tiles) (void)hipFree(fs->d_tiles);
   if (fs->d_partials) (void)hipFree(fs->d_partials);
   if (fs->d_partials_pair) (void)hipFree(fs->d_partials_pair);
@@ -762,13 +767,24 @@ hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum,
                          hipStream_t st, int form = VGICP_FORM_SOURCE, int32_t stride = 1) {
   const int tk = kind == kKindLinearize ? VGICP_KERNEL_LINEARIZE : VGICP_KERNEL_EVALUATE;
   hipError_t err = hipSuccess;
+  // a launch over the whole tile table reads the factors' constants from a
+  // table written once for the round; a launch over one factor's tiles
+  // computes them in every tile
+  const void *consts = nullptr;
+  if (tb == 0 && te == fs->n_tiles && f0 == 0 && nf == fs->n_factors && fs->d_consts) {
+    err = launch_factor_consts(fs, poses, st);
+    if (err != hipSuccess) return err;
+    consts = fs->d_consts;
+  }
   if (form == VGICP_FORM_PAIR && kind == kKindLinearize) {
     if (ctx) {
       TimedLaunch t(ctx, tk);
-      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride);
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride,
+                                  consts);
       t.done();
     } else {
-      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride);
+      err = launch_linearize_pair(fs, accum, resid, fused, kappa, tb, te, poses, st, stride,
+                                  consts);
     }
     if (err != hipSuccess) return err;
     if (ctx) {
@@ -783,11 +799,11 @@ hipError_t enqueue_range(vgicp_ctx ctx, vgicp_factorset fs, int kind, int accum,
   if (ctx) {
     TimedLaunch t(ctx, tk);
     err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
-                           st, stride);
+                           st, stride, consts);
     t.done();
   } else {
     err = launch_linearize(fs, accum, resid, fused, kappa, kind == kKindLinearize, tb, te, poses, corr,
-                           st, stride);
+                           st, stride, consts);
   }
   if (err != hipSuccess) return err;
   if (ctx) {
@@ -1119,7 +1135,12 @@ int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double 
     if (rc) return rc;
   }
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipError_t e = hipEventCreate(&t0);
+  // the round's constants table, written before the timed launches (a round
+  // writes it once before its linearize launch)
+  hipError_t e = kernel == VGICP_KERNEL_OVERLAP ? hipSuccess
+                                                : launch_factor_consts(fs, poses, ctx->stream);
+  const void *consts = kernel == VGICP_KERNEL_OVERLAP ? nullptr : fs->d_consts;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
   if (e == hipSuccess) e = hipEventRecord(t0, ctx->stream);
   for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
@@ -1127,11 +1148,11 @@ int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double 
       e = launch_overlap(fs, 0, fs->n_tiles, poses, ctx->stream);
     else if (pair)
       e = launch_linearize_pair(fs, o.accum, o.resid, o.fused, o.fp64_kappa, 0, fs->n_tiles, poses,
-                                ctx->stream);
+                                ctx->stream, 1, consts);
     else
       e = launch_linearize(fs, o.accum, o.resid, o.fused, o.fp64_kappa,
                            kernel == VGICP_KERNEL_LINEARIZE, 0, fs->n_tiles, poses, nullptr,
-                           ctx->stream);
+                           ctx->stream, 1, consts);
   }
   if (e == hipSuccess) e = hipEventRecord(t1, ctx->stream);
   if (e == hipSuccess) e = hipEventSynchronize(t1);

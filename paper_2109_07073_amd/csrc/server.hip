@@ -30,7 +30,7 @@ int voxelize_impl(vgicp_ctx ctx, const vgicp_cloud *cloud, double resolution, vg
 hipError_t launch_linearize(const vgicp_factorset_s *fs, int accum, int resid, int fused,
                             float kappa,
                             bool lin, int64_t tb, int64_t te, const double *poses, int32_t *corr,
-                            hipStream_t st, int32_t stride = 1);
+                            hipStream_t st, int32_t stride = 1, const void *consts = nullptr);
 hipError_t launch_overlap(const vgicp_factorset_s *fs, int64_t tb, int64_t te,
                           const double *poses, hipStream_t st, int32_t stride = 1);
 hipError_t launch_reduce(const vgicp_factorset_s *fs, int64_t f0, int64_t nf, const double *poses,

@@ -169,6 +169,11 @@ constexpr int kLookupPasses = 3;
 constexpr int kTileQuantum = 256 * kLookupPasses;
 constexpr int kDefaultTile = 6 * kTileQuantum;  // 4608 points
 
+// Bytes of one factor's relative-pose constants in a factor set's table
+// (FP32 rotation and translation scaled by 1/r and unscaled, FP64 rotation
+// and translation).
+constexpr size_t kFactorConstsBytes = 24 * sizeof(float) + 12 * sizeof(double);
+
 // Per-factor device descriptor (read with uniform loads by every tile).
 struct FactorDesc {
   const float *xyz;        // [n][3]: a library-owned copy, point by point
@@ -353,6 +358,9 @@ struct vgicp_factorset_s {
   // Blocks of a persistent grid (a multiple of 8), 0 for one block per tile.
   int32_t persist_blocks = 0;
   vgicp::FactorDesc *d_factors = nullptr;  // device
+  // device [n_factors] relative-pose constants, rewritten by every round over
+  // the whole tile table before its linearize launch (kFactorConstsBytes each)
+  void *d_consts = nullptr;
   vgicp::Tile *d_tiles = nullptr;          // device
   double *d_partials = nullptr;            // device [n_tiles][kPartialStride]
   // Pair-form tile partials, [pair_capacity][kPairStride], allocated at the
