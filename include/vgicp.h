@@ -295,8 +295,9 @@ int vgicp_factorset_tune(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
  * (VGICP_KERNEL_EVALUATE) or overlap (VGICP_KERNEL_OVERLAP) kernel over every
  * tile of the factor set at `poses`, with opts' variant (NULL: defaults),
  * bracketed by one pair of HIP events on ctx's stream and no event between
- * launches; *avg_ms receives the mean duration of a launch.  The launches
- * write only the factor set's tile partials (the next call overwrites them).
+ * launches; *avg_ms receives the mean duration of a launch.  The call writes
+ * only the factor set's tile partials and, once before the timed launches,
+ * its table of per-factor pose constants (the next call overwrites both).
  * Synchronizes ctx's stream.  Errors: EINVAL (unknown or reduce kernel, reps
  * out of range), EHIP. */
 int vgicp_factorset_time_kernel(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
@@ -421,7 +422,8 @@ int vgicp_linearize_factors(vgicp_ctx ctx, vgicp_factorset fs, const double *pos
  * [n_factors]) alone, without Jacobians; equal to the e and inliers of
  * vgicp_linearize_factors with the same accumulation in the source-frame form
  * (the pair form's e, summed in the target frame, agrees to FP32 rounding;
- * inliers are always equal).  A call uses the factor set's tile partials:
+ * inliers are always equal).  A call uses the factor set's tile partials and
+ * its table of per-factor pose constants:
  * calls on one factor set that overlap in time (on two streams) race.
  * Errors: EINVAL, EHIP. */
 int vgicp_evaluate_errors(vgicp_ctx ctx, vgicp_factorset fs, const double *poses,
