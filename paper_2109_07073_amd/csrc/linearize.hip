@@ -1182,8 +1182,13 @@ __device__ __forceinline__ void linearize_tile(
   uint32_t ow[kOccWordsPerThread];
   tile_loads<kChunk>(fd, cx, ow, cur);
   // the relative pose (from the round's table when there is one) while the
-  // loads are in flight
-  const FactorConsts k = consts ? consts[td.factor] : factor_consts(fd, poses);
+  // loads are in flight.  The gated variant always computes it: compiled with
+  // the table's branch it ran 13 % slower on the full-size precision workload.
+  FactorConsts k;
+  if constexpr (FUSE == kFuseGate)
+    k = factor_consts(fd, poses);
+  else
+    k = consts ? consts[td.factor] : factor_consts(fd, poses);
   // the previous tile's reads of the LDS sums and bits end before this barrier
   tile_stage(fd, occ_lds, ow);
   __syncthreads();
@@ -1832,8 +1837,8 @@ hipError_t launch_linearize_into(const vgicp_factorset_s *fs, int accum, int res
   if (fused == VGICP_FUSED_F64)
     return launch_k<kFuse64>(fs, accum, lin, r64, tb, te, stride, poses, k, partials, corr, 0.f,
                              st);
-  // the gated variant keeps computing the constants in every workgroup: with
-  // the table it measured 13 % slower on the full-size precision workload
+  // the gated variant computes the constants in every workgroup (see
+  // linearize_tile)
   if (kappa > 0.f)
     return launch_k<kFuseGate>(fs, accum, lin, r64, tb, te, stride, poses, nullptr, partials,
                                corr, kappa, st);
