@@ -23,8 +23,9 @@
  *     specified and no handle is created.
  *   - Arguments are validated on the host before anything is enqueued.
  *   - Clouds are frame-local.  A cloud of n points is two arrays:
- *       xyz: float32 [3][n]  (x[0..n), then y[0..n), then z[0..n)): every
- *                              lookup streams all of it
+ *       xyz: float32 [3][n]  (x[0..n), then y[0..n), then z[0..n)); the
+ *                              rounds stream the library's own copies, which
+ *                              keep the coordinates point by point
  *       cov: float32 [n][6]  (per point xx, xy, xz, yy, yz, zz of the
  *                              symmetric 3x3 covariance; 8-byte aligned): only
  *                              points that fall in a voxel read theirs
@@ -239,8 +240,8 @@ int vgicp_map_free(vgicp_map map);
  * owned, read during this call only): the factor set keeps its own copy of
  * every source cloud a factor uses, its points in Morton order of cells of the
  * finest resolution among the maps that cloud is matched against, so that
- * neighbouring points of a wave look up neighbouring voxels (40 bytes of
- * device memory per point; results differ from the caller's order only by
+ * neighbouring points of a wave look up neighbouring voxels, coordinates
+ * stored point by point (40 bytes of device memory per point; results differ from the caller's order only by
  * FP32 summation order, and per-point outputs keep the caller's order);
  * maps: host array of n_maps handles (they must outlive the factor set);
  * factors: host array of n_factors rows; n_poses: length of the pose arrays
