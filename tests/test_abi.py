@@ -173,3 +173,27 @@ def test_keyframe_calls_reject_null_handles_without_a_device():
                                     None) == vg.EINVAL
     assert lib.vgicp_server_submap_step(None, ctypes.byref(r), 0, None, 0, None, 0, None, 0,
                                         ctypes.byref(d), None, None) == vg.EINVAL
+
+
+def test_binding_constants_match_the_header():
+    """Every constant the Python binding mirrors has the header's value."""
+    import re
+    with open(vg.HEADER) as fh:
+        text = fh.read()
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"^#define (VGICP_\w+) \(?(-?\d+)\)?", text, re.M)}
+    for name, value in (("OK", vg.OK), ("EINVAL", vg.EINVAL), ("ENOMEM", vg.ENOMEM),
+                        ("ERANGE", vg.ERANGE), ("ENONFINITE", vg.ENONFINITE),
+                        ("EHIP", vg.EHIP), ("EFULL", vg.EFULL),
+                        ("NOALLOC_MAX_TILES", vg.NOALLOC_MAX_TILES)):
+        assert defs["VGICP_" + name] == value, name
+    groups = {"ACC": vg.ACC, "RESID": vg.RESID, "FUSED": vg.FUSED, "FORM": vg.FORM,
+              "SCHED": vg.SCHED, "LAYOUT": vg.LAYOUT, "KERNEL": vg.KERNELS, "REQ": vg.REQ,
+              "GATE": vg.GATE}
+    for prefix, table in groups.items():
+        header = {k[len("VGICP_" + prefix) + 1:].lower(): v for k, v in defs.items()
+                  if k.startswith("VGICP_" + prefix + "_") and k != "VGICP_KERNEL_KINDS"}
+        assert header == table, (prefix, header, table)
+    header = {v: k[len("VGICP_SUBMAP_"):].lower() for k, v in defs.items()
+              if k.startswith("VGICP_SUBMAP_")}
+    assert header == vg.SUBMAP
