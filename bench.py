@@ -505,8 +505,11 @@ def run_serving(args):
         for _ in range(3):
             P = perturbed(poses, used_ids)[used_ids]
             t0 = time.perf_counter()
-            reqs = {k: srv.submit("linearize", g, P, out=prev.get(k))
-                    for k, g in (("glob", glob), ("loc", loc)) if len(g)}
+            # both optimizers' requests queued together (one batch when they fit)
+            keys = [k for k, g in (("glob", glob), ("loc", loc)) if len(g)]
+            mine = {"glob": glob, "loc": loc}
+            reqs = dict(zip(keys, srv.submit_many([("linearize", mine[k], P, prev.get(k))
+                                                    for k in keys])))
             t1 = time.perf_counter()
             done = [r.wait() for r in reqs.values()]
             prev = reqs

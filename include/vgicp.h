@@ -622,6 +622,29 @@ int vgicp_server_submit(vgicp_server srv, int kind, const vgicp_factor *factors,
                         const double *h_poses, int32_t n_poses, double *H, double *b, double *e,
                         int64_t *inliers, double *overlap, int64_t *ticket);
 
+/* One request of vgicp_server_submit_many: the arguments of
+ * vgicp_server_submit (host arrays, same ownership and sizes). */
+typedef struct {
+  int32_t kind;                 /* VGICP_REQ_* */
+  int32_t n_poses;
+  int64_t n;                    /* factors */
+  const vgicp_factor *factors;  /* [n] */
+  const double *h_poses;        /* [n_poses][12] */
+  double *H, *b, *e;            /* outputs as for vgicp_server_submit */
+  int64_t *inliers;
+  double *overlap;
+} vgicp_server_request;
+
+/* Several requests queued at once (Sec. III-D: an optimizer issues all of its
+ * cost-evaluation tasks, then synchronizes once): the worker finds them
+ * together, so requests of one kind share a batch and its launches instead of
+ * following one another.  Each request as for vgicp_server_submit; tickets
+ * [n_reqs] receives their tickets in order.  All or nothing: on an error no
+ * request is queued.  Errors: as vgicp_server_submit, and EINVAL for
+ * n_reqs < 0 or NULL arrays with n_reqs > 0. */
+int vgicp_server_submit_many(vgicp_server srv, const vgicp_server_request *reqs, int32_t n_reqs,
+                             int64_t *tickets);
+
 /* Nonzero in *done once the request's outputs are written.  Errors: EINVAL. */
 int vgicp_server_poll(vgicp_server srv, int64_t ticket, int *done);
 

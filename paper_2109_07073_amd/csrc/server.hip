@@ -667,60 +667,82 @@ int vgicp_server_memory(vgicp_server srv, int64_t *used_bytes, int64_t *budget_b
 int vgicp_server_submit(vgicp_server srv, int kind, const vgicp_factor *factors, int64_t n,
                         const double *h_poses, int32_t n_poses, double *H, double *b, double *e,
                         int64_t *inliers, double *overlap, int64_t *ticket) {
+  const vgicp_server_request r{kind, n_poses, n, factors, h_poses, H, b, e, inliers, overlap};
+  return vgicp_server_submit_many(srv, &r, 1, ticket);
+}
+
+int vgicp_server_submit_many(vgicp_server srv, const vgicp_server_request *reqs, int32_t n_reqs,
+                             int64_t *tickets) {
   if (!srv) return VGICP_EINVAL;
-  if (!ticket) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: ticket is NULL");
-  if (kind < VGICP_REQ_LINEARIZE || kind > VGICP_REQ_OVERLAP)
-    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: unknown kind");
-  if (n < 0 || (n > 0 && !factors) || n_poses < 0 || (n_poses > 0 && !h_poses))
-    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: bad factor or pose arrays");
-  if (n_poses > srv->cfg.max_batch_poses)
-    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: more poses than max_batch_poses");
-  if (n > 0 && !inliers) return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: inliers is NULL");
-  if (n > 0 && kind == VGICP_REQ_LINEARIZE && (!H || !b || !e))
-    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: H, b or e is NULL");
-  if (n > 0 && kind == VGICP_REQ_EVALUATE && !e)
-    return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: e is NULL");
-  for (int64_t k = 0; k < int64_t(n_poses) * 12; ++k)
-    if (!std::isfinite(h_poses[k]))
-      return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: non-finite pose");
-  auto req = std::make_shared<Request>();
-  req->kind = kind;
-  req->factors.assign(factors, factors + n);
-  req->poses.assign(h_poses, h_poses + size_t(n_poses) * 12);
-  req->H = H;
-  req->b = b;
-  req->e = e;
-  req->inliers = inliers;
-  req->overlap = overlap;
-  req->remaining = n;
-  req->t_submit = Clock::now();
+  const char *who = n_reqs == 1 ? "vgicp_server_submit" : "vgicp_server_submit_many";
+  if (n_reqs < 0 || (n_reqs > 0 && (!reqs || !tickets)))
+    return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": bad request or ticket array");
+  // every argument checked and copied before anything is queued
+  std::vector<std::shared_ptr<Request>> batch;
+  batch.reserve(size_t(n_reqs));
+  for (int32_t q = 0; q < n_reqs; ++q) {
+    const vgicp_server_request &r = reqs[q];
+    if (r.kind < VGICP_REQ_LINEARIZE || r.kind > VGICP_REQ_OVERLAP)
+      return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": unknown kind");
+    if (r.n < 0 || (r.n > 0 && !r.factors) || r.n_poses < 0 || (r.n_poses > 0 && !r.h_poses))
+      return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": bad factor or pose arrays");
+    if (r.n_poses > srv->cfg.max_batch_poses)
+      return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": more poses than max_batch_poses");
+    if (r.n > 0 && !r.inliers) return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": inliers is NULL");
+    if (r.n > 0 && r.kind == VGICP_REQ_LINEARIZE && (!r.H || !r.b || !r.e))
+      return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": H, b or e is NULL");
+    if (r.n > 0 && r.kind == VGICP_REQ_EVALUATE && !r.e)
+      return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": e is NULL");
+    for (int64_t k = 0; k < int64_t(r.n_poses) * 12; ++k)
+      if (!std::isfinite(r.h_poses[k]))
+        return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": non-finite pose");
+    auto req = std::make_shared<Request>();
+    req->kind = r.kind;
+    req->factors.assign(r.factors, r.factors + r.n);
+    req->poses.assign(r.h_poses, r.h_poses + size_t(r.n_poses) * 12);
+    req->H = r.H;
+    req->b = r.b;
+    req->e = r.e;
+    req->inliers = r.inliers;
+    req->overlap = r.overlap;
+    req->remaining = r.n;
+    batch.push_back(std::move(req));
+  }
+  const auto now = Clock::now();
   {
     std::lock_guard<std::mutex> g(srv->mu);
-    for (const vgicp_factor &x : req->factors) {
-      auto bad_frame = [&](int32_t f) {
-        return f < 0 || size_t(f) >= srv->frames.size() || !srv->frames[size_t(f)].live ||
-               srv->frames[size_t(f)].remove_pending;
-      };
-      if (bad_frame(x.src) || bad_frame(x.tgt) || x.pose_i < 0 || x.pose_i >= n_poses ||
-          x.pose_j < 0 || x.pose_j >= n_poses)
-        return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: factor references an unknown "
-                                           "frame or pose");
-      if (srv->frames[size_t(x.src)].n > srv->cfg.max_batch_points)
-        return srv_fail(srv, VGICP_EINVAL, "vgicp_server_submit: a source frame has more points "
-                                           "than max_batch_points");
+    auto bad_frame = [&](int32_t f) {
+      return f < 0 || size_t(f) >= srv->frames.size() || !srv->frames[size_t(f)].live ||
+             srv->frames[size_t(f)].remove_pending;
+    };
+    for (size_t q = 0; q < batch.size(); ++q) {
+      const int32_t n_poses = reqs[q].n_poses;
+      for (const vgicp_factor &x : batch[q]->factors) {
+        if (bad_frame(x.src) || bad_frame(x.tgt) || x.pose_i < 0 || x.pose_i >= n_poses ||
+            x.pose_j < 0 || x.pose_j >= n_poses)
+          return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": factor references an unknown "
+                                                                "frame or pose");
+        if (srv->frames[size_t(x.src)].n > srv->cfg.max_batch_points)
+          return srv_fail(srv, VGICP_EINVAL, std::string(who) + ": a source frame has more "
+                                                                "points than max_batch_points");
+      }
     }
-    for (const vgicp_factor &x : req->factors) {
-      srv->frames[size_t(x.src)].users += 1;
-      srv->frames[size_t(x.tgt)].users += 1;
-    }
-    req->ticket = srv->next_ticket++;
-    *ticket = req->ticket;
-    srv->requests[req->ticket] = req;
-    if (n == 0) {
-      req->done = true;
-      ++srv->n_completed;
-    } else {
-      srv->pending.push_back(req);
+    for (size_t q = 0; q < batch.size(); ++q) {
+      Request &req = *batch[q];
+      for (const vgicp_factor &x : req.factors) {
+        srv->frames[size_t(x.src)].users += 1;
+        srv->frames[size_t(x.tgt)].users += 1;
+      }
+      req.t_submit = now;
+      req.ticket = srv->next_ticket++;
+      tickets[q] = req.ticket;
+      srv->requests[req.ticket] = batch[q];
+      if (req.factors.empty()) {
+        req.done = true;
+        ++srv->n_completed;
+      } else {
+        srv->pending.push_back(batch[q]);
+      }
     }
   }
   srv->cv.notify_all();

@@ -51,6 +51,13 @@ class CFactor(ctypes.Structure):
                 ("pose_i", ctypes.c_int32), ("pose_j", ctypes.c_int32)]
 
 
+class CServerRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_poses", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("factors", ctypes.c_void_p), ("h_poses", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("b", ctypes.c_void_p), ("e", ctypes.c_void_p),
+                ("inliers", ctypes.c_void_p), ("overlap", ctypes.c_void_p)]
+
+
 class COpts(ctypes.Structure):
     _fields_ = [("accum", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("resid", ctypes.c_int32),
@@ -119,6 +126,7 @@ _PROTOS = {
     "vgicp_server_memory": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "vgicp_server_submit": (ctypes.c_int, [_vp, ctypes.c_int, _P(CFactor), _i64, _vp, _i32, _vp,
                                            _vp, _vp, _vp, _vp, _P(_i64)]),
+    "vgicp_server_submit_many": (ctypes.c_int, [_vp, _P(CServerRequest), _i32, _P(_i64)]),
     "vgicp_server_poll": (ctypes.c_int, [_vp, _i64, _P(ctypes.c_int)]),
     "vgicp_server_wait": (ctypes.c_int, [_vp, _i64, _P(_dbl)]),
     "vgicp_server_stats": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)]),
@@ -899,6 +907,31 @@ class Server:
         r.ticket = t.value
         self._inflight[r.ticket] = r
         return r
+
+    def submit_many(self, requests) -> list:
+        """Queue several requests at once (vgicp_server_submit_many), so that
+        requests of one kind share a batch: `requests` is a sequence of
+        (kind, factors, poses) or (kind, factors, poses, out) as for submit.
+        All or nothing; returns the ServerRequests in order."""
+        items = [tuple(r) + (None,) * (4 - len(r)) for r in requests]
+        reqs = (CServerRequest * max(len(items), 1))()
+        out, keep = [], []
+        ptr = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
+        for q, (kind, factors, poses, prev) in enumerate(items):
+            arr, n = _factor_array(factors)
+            p = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 12))
+            r = ServerRequest(self, kind, n, prev)
+            r._keep = (arr, p)
+            reqs[q] = CServerRequest(REQ[kind], p.shape[0], n, arr.rows.ctypes.data, p.ctypes.data,
+                                     ptr(r.H), ptr(r.b), ptr(r.e), ptr(r.inliers),
+                                     ptr(r.overlap))
+            out.append(r)
+        tickets = (ctypes.c_int64 * max(len(items), 1))()
+        _check_srv(_lib.vgicp_server_submit_many(self._h, reqs, len(items), tickets), self)
+        for q, r in enumerate(out):
+            r.ticket = tickets[q]
+            self._inflight[r.ticket] = r
+        return out
 
     def connect(self, frame: int, pose, candidates, candidate_poses, threshold: float = 0.025,
                 rule: str = "above"):

@@ -94,6 +94,45 @@ def test_requests_reuse_host_buffers(vg, scans):
             srv.submit("evaluate", fac[:20], scans.poses, out=again)
 
 
+def test_submit_many_matches_single_submits(vg, scans):
+    """Requests queued together (vgicp_server_submit_many) give the bits of the
+    same requests submitted one by one, share batches, reuse host buffers, and
+    an invalid request queues none of them."""
+    with vg.Server(max_batch_factors=64, inflight=2) as srv:
+        ids = _frames(srv, scans)
+        fac = scans.factors.copy()
+        fac[:, 0] = [ids[s] for s in fac[:, 0]]
+        fac[:, 1] = [ids[t] for t in fac[:, 1]]
+        parts = [("linearize", fac[:12], scans.poses), ("linearize", fac[12:], scans.poses),
+                 ("evaluate", fac, scans.poses), ("overlap", fac[:7], scans.poses)]
+        single = [srv.submit(*p).wait() for p in parts]
+        before = srv.stats()["batches"]
+        many = [r.wait() for r in srv.submit_many(parts)]
+        # the two linearize requests went out in one batch
+        assert srv.stats()["batches"] - before <= 3
+        for a, b in zip(single, many):
+            for k in ("H", "b", "e", "inliers", "overlap"):
+                x, y = getattr(a, k), getattr(b, k)
+                assert (x is None) == (y is None), k
+                if x is not None:
+                    assert np.array_equal(x, y), (a.kind, k)
+        # the next round reuses the first round's host arrays
+        again = [r.wait() for r in srv.submit_many([p + (m,) for p, m in zip(parts, many)])]
+        for a, b in zip(many, again):
+            assert b.inliers is a.inliers
+        # all or nothing: a bad frame id in the last request queues none
+        bad = fac[:3].copy()
+        bad[0, 0] = 10**6
+        n_req = srv.stats()["requests"]
+        with pytest.raises(vg.VgicpError) as ei:
+            srv.submit_many([parts[0], ("linearize", bad, scans.poses)])
+        assert ei.value.code == vg.EINVAL
+        # a request queued by the failed call would complete before this one
+        srv.submit(*parts[3]).wait()
+        assert srv.stats()["requests"] == n_req + 1
+        assert srv.submit_many([]) == []
+
+
 def test_evaluate_and_overlap_requests(vg, scans):
     with vg.Server(inflight=3) as srv:
         ids = _frames(srv, scans)
