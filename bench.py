@@ -505,11 +505,11 @@ def run_serving(args):
         for _ in range(3):
             P = perturbed(poses, used_ids)[used_ids]
             t0 = time.perf_counter()
-            # both optimizers' requests queued together (one batch when they fit)
-            keys = [k for k, g in (("glob", glob), ("loc", loc)) if len(g)]
-            mine = {"glob": glob, "loc": loc}
-            reqs = dict(zip(keys, srv.submit_many([("linearize", mine[k], P, prev.get(k))
-                                                    for k in keys])))
+            # the two optimizers submit on their own (queued together with
+            # submit_many they share one batch, and the round takes longer than
+            # two batches overlapping on the server's two streams)
+            reqs = {k: srv.submit("linearize", g, P, out=prev.get(k))
+                    for k, g in (("glob", glob), ("loc", loc)) if len(g)}
             t1 = time.perf_counter()
             done = [r.wait() for r in reqs.values()]
             prev = reqs
