@@ -637,10 +637,11 @@ typedef struct {
 
 /* Several requests queued at once (Sec. III-D: an optimizer issues all of its
  * cost-evaluation tasks, then synchronizes once): the worker finds them
- * together, so requests of one kind share a batch and its launches instead of
- * following one another.  Each request as for vgicp_server_submit; tickets
- * [n_reqs] receives their tickets in order.  All or nothing: on an error no
- * request is queued.  Errors: as vgicp_server_submit, and EINVAL for
+ * together, so requests of one kind share a batch and its launches (fewer
+ * launches and copies; small requests submitted one by one can instead finish
+ * sooner on separate in-flight slots, whose copies and launches overlap).
+ * Each request as for vgicp_server_submit; tickets [n_reqs] receives their
+ * tickets in order.  All or nothing: on an error no request is queued.  Errors: as vgicp_server_submit, and EINVAL for
  * n_reqs < 0 or NULL arrays with n_reqs > 0. */
 int vgicp_server_submit_many(vgicp_server srv, const vgicp_server_request *reqs, int32_t n_reqs,
                              int64_t *tickets);
