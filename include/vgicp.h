@@ -241,8 +241,9 @@ int vgicp_map_free(vgicp_map map);
  * every source cloud a factor uses, its points in Morton order of cells of the
  * finest resolution among the maps that cloud is matched against, so that
  * neighbouring points of a wave look up neighbouring voxels, coordinates
- * stored point by point (40 bytes of device memory per point; results differ from the caller's order only by
- * FP32 summation order, and per-point outputs keep the caller's order);
+ * stored point by point (40 bytes of device memory per point; results differ
+ * from the caller's order only by FP32 summation order, and per-point outputs
+ * keep the caller's order);
  * maps: host array of n_maps handles (they must outlive the factor set);
  * factors: host array of n_factors rows; n_poses: length of the pose arrays
  * later calls pass; tile_points: source points per workgroup tile, a multiple
@@ -641,8 +642,9 @@ typedef struct {
  * launches and copies; small requests submitted one by one can instead finish
  * sooner on separate in-flight slots, whose copies and launches overlap).
  * Each request as for vgicp_server_submit; tickets [n_reqs] receives their
- * tickets in order.  All or nothing: on an error no request is queued.  Errors: as vgicp_server_submit, and EINVAL for
- * n_reqs < 0 or NULL arrays with n_reqs > 0. */
+ * tickets in order.  All or nothing: on an error no request is queued.
+ * Errors: as vgicp_server_submit, and EINVAL for n_reqs < 0 or NULL arrays
+ * with n_reqs > 0. */
 int vgicp_server_submit_many(vgicp_server srv, const vgicp_server_request *reqs, int32_t n_reqs,
                              int64_t *tickets);
 
