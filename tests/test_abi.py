@@ -197,3 +197,37 @@ def test_binding_constants_match_the_header():
     header = {v: k[len("VGICP_SUBMAP_"):].lower() for k, v in defs.items()
               if k.startswith("VGICP_SUBMAP_")}
     assert header == vg.SUBMAP
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct the Python binding mirrors has the C compiler's size and
+    field offsets for the header's typedef (a swapped or missing field in either
+    would shift every later argument)."""
+    import shutil
+    import os
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"vgicp_cloud": vg.CCloud, "vgicp_factor": vg.CFactor, "vgicp_opts": vg.COpts,
+               "vgicp_submap_rules": vg.CSubmapRules, "vgicp_server_config": vg.CServerConfig,
+               "vgicp_server_request": vg.CServerRequest}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vgicp.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(vg.HEADER),
+                    str(src), "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
