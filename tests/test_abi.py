@@ -116,6 +116,10 @@ def test_server_rejects_bad_config_and_null_handles():
     assert lib.vgicp_server_wait(None, 1, None) == vg.EINVAL
     assert lib.vgicp_server_remove_frame(None, 0) == vg.EINVAL
     assert lib.vgicp_server_stats(None, None, None, None, None) == vg.EINVAL
+    tickets = (ctypes.c_int64 * 1)()
+    assert lib.vgicp_server_submit_many(None, None, 0, tickets) == vg.EINVAL
+    assert lib.vgicp_server_submit(None, 0, None, 0, None, 0, None, None, None, None, None,
+                                   tickets) == vg.EINVAL
 
 
 def test_bad_output_tensors_raise_before_any_library_call():
