@@ -815,14 +815,19 @@ def submap_step(ctx: Context, xyz, pose, first=None, first_pose=None, last=None,
 class ServerRequest:
     """A submitted request: host output arrays are filled when it completes.
     `out` (a finished request of the same kind and size) lends its arrays, so
-    that an optimizer's repeated rounds reuse their host buffers."""
+    that an optimizer's repeated rounds reuse their host buffers; the arrays
+    serve one request in flight at a time."""
 
-    def __init__(self, server, kind, n, out=None):
+    def __init__(self, server, kind, n, out=None, pending=()):
         self.server = server
         self.kind = kind
         if out is not None:
             if out.kind != kind or out.inliers.shape[0] != n or out.ticket in server._inflight:
                 raise ValueError("out must be a finished request of the same kind and size")
+            # one set of host arrays serves one request in flight at a time
+            holders = list(server._inflight.values()) + list(pending)
+            if any(r.inliers is out.inliers for r in holders):
+                raise ValueError("out's arrays are already lent to a request in flight")
             self.inliers, self.e, self.H, self.b, self.overlap = (out.inliers, out.e, out.H,
                                                                   out.b, out.overlap)
         else:
@@ -920,7 +925,7 @@ class Server:
         for q, (kind, factors, poses, prev) in enumerate(items):
             arr, n = _factor_array(factors)
             p = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 12))
-            r = ServerRequest(self, kind, n, prev)
+            r = ServerRequest(self, kind, n, prev, pending=out)
             r._keep = (arr, p)
             reqs[q] = CServerRequest(REQ[kind], p.shape[0], n, arr.rows.ctypes.data, p.ctypes.data,
                                      ptr(r.H), ptr(r.b), ptr(r.e), ptr(r.inliers),

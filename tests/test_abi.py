@@ -235,3 +235,27 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_server_request_arrays_are_lent_to_one_request_at_a_time():
+    """A finished request's host arrays may be reused by the next request, but
+    never by two requests in flight (the worker would write both into them)."""
+    class Srv:
+        _inflight = {}
+    srv = Srv()
+    a = vg.ServerRequest(srv, "evaluate", 3)
+    a.ticket = 1                                    # finished: not in flight
+    b = vg.ServerRequest(srv, "evaluate", 3, out=a)
+    assert b.inliers is a.inliers and b.e is a.e
+    b.ticket = 2
+    srv._inflight[2] = b
+    with pytest.raises(ValueError):
+        vg.ServerRequest(srv, "evaluate", 3, out=a)  # b still holds the arrays
+    with pytest.raises(ValueError):
+        vg.ServerRequest(srv, "evaluate", 3, out=b)  # b itself is in flight
+    with pytest.raises(ValueError):
+        vg.ServerRequest(srv, "linearize", 3, out=a)
+    del srv._inflight[2]
+    c = vg.ServerRequest(srv, "evaluate", 3, out=a)
+    with pytest.raises(ValueError):                  # queued in the same call
+        vg.ServerRequest(srv, "evaluate", 3, out=b, pending=[c])

@@ -120,6 +120,9 @@ def test_submit_many_matches_single_submits(vg, scans):
         again = [r.wait() for r in srv.submit_many([p + (m,) for p, m in zip(parts, many)])]
         for a, b in zip(many, again):
             assert b.inliers is a.inliers
+        # one request's arrays serve one request in flight
+        with pytest.raises(ValueError):
+            srv.submit_many([parts[0] + (again[0],), parts[0] + (again[0],)])
         # all or nothing: a bad frame id in the last request queues none
         bad = fac[:3].copy()
         bad[0, 0] = 10**6
