@@ -616,7 +616,8 @@ int vgicp_server_memory(vgicp_server srv, int64_t *used_bytes, int64_t *budget_b
  * and pose_j index h_poses [n_poses][12]).  Factors and poses are copied before
  * the call returns.  The host output arrays (H [n][144], b [n][12], e [n],
  * inliers [n], overlap [n]; those the kind does not produce may be NULL) must
- * stay valid until the request completes.  Returns a ticket.
+ * stay valid until the request completes, and two requests in flight must not
+ * share one (the library does not check).  Returns a ticket.
  * Errors: EINVAL (unknown frame, index out of range, NULL outputs, more poses
  * than max_batch_poses). */
 int vgicp_server_submit(vgicp_server srv, int kind, const vgicp_factor *factors, int64_t n,
